@@ -1,0 +1,156 @@
+/*
+ * dft3d -- 3D complex DFT on one AMD Instinct MI355X (gfx950).
+ *
+ * Computes the 3D DFT (Section 2.1, eqs. (1)-(2); Section 2.3, eqs. (6)-(8))
+ *
+ *   y[k0,k1,k2] = sum_{i0,i1,i2} x[i0,i1,i2] w_{n0}^{i0 k0} w_{n1}^{i1 k1}
+ *                                            w_{n2}^{i2 k2},
+ *   w_n = exp(sign * 2 pi i / n),
+ *
+ * as passes of batched 1D FFTs with layout changes between them.  The
+ * paper's decompositions become on-device schedules:
+ *   SLAB        2D DFT of every (n1, n2) plane, then a 1D DFT along n0
+ *               (eq. (6), Fig. 5);
+ *   PENCIL      three passes of 1D DFTs, each writing its output rotated so
+ *               that the next axis is contiguous, xyz -> yzx -> zxy -> xyz
+ *               (eq. (8), Fig. 6, Section 2.4);
+ *   VOLUMETRIC  every axis of length n = a b split four-step style (eq. (3),
+ *               eqs. (13)-(17)): batched DFT_b over the stride-a subsequences
+ *               with the twiddle of eq. (4) and an exchanging store, then
+ *               batched DFT_a (Fig. 9, Section 3.2);
+ *   AUTO        a per-shape choice (measured when an autotune cache entry
+ *               exists, otherwise a fixed heuristic).
+ *
+ * Data: complex64 = two IEEE binary32 (re, im), interleaved, 8 bytes per
+ * point; C order (n0, n1, n2), n2 contiguous; device pointers, 16-byte
+ * aligned.  Forward is sign = -1 and inverse sign = +1; neither is scaled,
+ * so inverse(forward(x)) = n0 n1 n2 x.
+ *
+ * Every call returns a status (DFT3D_OK = 0, errors negative).  Argument
+ * errors are detected before any work is enqueued; after any error nothing
+ * is leaked and output handles are set to NULL.  Plans are not thread-safe: one plan is used from one host
+ * thread and one stream at a time; distinct plans are independent.
+ */
+#ifndef DFT3D_H
+#define DFT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dft3d_plan_s* dft3d_plan_t;
+
+/* Schedules (the paper's decompositions, Section 2.3/2.4 and Fig. 9). */
+enum dft3d_schedule {
+  DFT3D_SCHED_AUTO = 0,
+  DFT3D_SCHED_SLAB = 1,
+  DFT3D_SCHED_PENCIL = 2,
+  DFT3D_SCHED_VOLUMETRIC = 3
+};
+
+/* Output layouts.  NATURAL is C order (n0, n1, n2).  SHUFFLED leaves the
+ * digit-transposed order of a four-step transform (Section 2.4: the last
+ * redistribution may be dropped when the consumer does not need natural
+ * order); it is accepted only where documented and otherwise rejected with
+ * DFT3D_ERR_UNSUPPORTED_SCHEDULE. */
+enum dft3d_layout { DFT3D_LAYOUT_NATURAL = 0, DFT3D_LAYOUT_SHUFFLED = 1 };
+
+/* Leaf arithmetic.  FP32 runs every butterfly in binary32 with twiddles
+ * generated in FP64 and rounded once.  The split forms run leaf DFTs of
+ * length 16 or 32 as real GEMMs on the matrix cores with operands split
+ * into bf16 / fp16 terms and FP32 accumulation; X1 forms use a single term
+ * and are not accurate to FP32 (reported, never a parity claim). */
+enum dft3d_precision {
+  DFT3D_PREC_FP32 = 0,
+  DFT3D_PREC_BF16X1 = 1,
+  DFT3D_PREC_FP16X1 = 2,
+  DFT3D_PREC_BF16X6 = 3,
+  DFT3D_PREC_BF16X9 = 4,
+  DFT3D_PREC_FP16X3 = 5
+};
+
+/* Status codes. */
+enum dft3d_status {
+  DFT3D_OK = 0,
+  DFT3D_ERR_INVALID_ARG = -1,          /* null pointer, bad enum, bad sign */
+  DFT3D_ERR_UNSUPPORTED_SIZE = -2,     /* n_d not a power of two in [1, 4096] */
+  DFT3D_ERR_UNSUPPORTED_SCHEDULE = -3, /* schedule/layout/precision combination */
+  DFT3D_ERR_NO_DEVICE = -4,            /* no HIP device visible */
+  DFT3D_ERR_OUT_OF_MEMORY = -5,        /* device allocation failed */
+  DFT3D_ERR_HIP = -6,                  /* a HIP runtime call failed */
+  DFT3D_ERR_WORKSPACE_TOO_SMALL = -7   /* dft3d_set_workspace buffer too small */
+};
+
+/* Option keys for dft3d_plan_set_option / dft3d_plan_get_option.  Setting
+ * an option rebuilds the pass list (host work plus a table upload). */
+enum dft3d_option {
+  DFT3D_OPT_PRECISION = 1,   /* enum dft3d_precision; default FP32 */
+  DFT3D_OPT_TILE = 2,        /* pencils per workgroup, power of two; 0 = default */
+  DFT3D_OPT_XCD_REMAP = 3,   /* 1 = map consecutive tiles to one XCD; default 1 */
+  DFT3D_OPT_SPLIT_MAX = 4,   /* longest axis done in one pass; longer axes
+                                are split four-step; 0 = default */
+  DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
+};
+
+/* Text for a status code; never NULL. */
+const char* dft3d_status_string(int status);
+
+/* Build a plan for a (n0, n1, n2) complex64 transform.  Each n_d must be a
+ * power of two in [1, 4096].  Validates the arguments first
+ * (INVALID_ARG / UNSUPPORTED_SIZE / UNSUPPORTED_SCHEDULE), then needs a HIP
+ * device (NO_DEVICE), then allocates and uploads the twiddle tables on the
+ * current device (OUT_OF_MEMORY / HIP_ERROR).  *out receives the handle, or
+ * NULL on error.  The workspace is not allocated here. */
+int dft3d_plan(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
+               dft3d_plan_t* out);
+
+/* Describe the pass list a plan would use, without touching any device:
+ * writes a NUL-terminated JSON text into buf (at most len bytes, truncated
+ * if needed) and stores the full length in *needed (may be NULL).  Same
+ * argument validation as dft3d_plan. */
+int dft3d_plan_describe(int64_t n0, int64_t n1, int64_t n2, int schedule,
+                        int layout, char* buf, size_t len, size_t* needed);
+
+int dft3d_plan_set_option(dft3d_plan_t plan, int key, int64_t value);
+int dft3d_plan_get_option(dft3d_plan_t plan, int key, int64_t* value);
+
+/* Bytes of device workspace dft3d_execute needs (0 if none). */
+int dft3d_workspace_size(dft3d_plan_t plan, size_t* bytes);
+
+/* Hand the plan a caller-owned device buffer of `bytes` bytes to use as
+ * workspace (WORKSPACE_TOO_SMALL if below dft3d_workspace_size).  The plan
+ * does not free it.  Without this call the plan allocates its own on the
+ * first execute and frees it in dft3d_destroy.  Passing NULL reverts to
+ * plan-owned workspace. */
+int dft3d_set_workspace(dft3d_plan_t plan, void* dev_ptr, size_t bytes);
+
+/* Enqueue the transform on `stream` (a hipStream_t; NULL = default stream)
+ * and return.  in, out: device pointers of n0 n1 n2 complex64, distinct and
+ * non-overlapping (in == out is INVALID_ARG); in is never written.
+ * sign = -1 forward, +1 inverse, anything else INVALID_ARG.  Launch errors
+ * are returned (HIP_ERROR); faults inside kernels surface at the caller's
+ * next synchronisation. */
+int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
+                  void* stream);
+
+/* Enqueue `count` transforms of possibly different shapes as one persistent
+ * launch captured in a HIP graph.  plans[i] describes problem i, in[i] and
+ * out[i] are its device buffers (same rules as dft3d_execute).  The first
+ * call for a given sequence of plans captures the graph; later calls with
+ * the same plans replay it after refreshing the pointer descriptors.
+ * count == 0 is a no-op.  Plans must use the NATURAL layout and FP32. */
+int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
+                          void* const* out, int count, int sign, void* stream);
+
+/* Release the plan, its device tables and any plan-owned workspace.
+ * NULL is accepted. */
+int dft3d_destroy(dft3d_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFT3D_H */

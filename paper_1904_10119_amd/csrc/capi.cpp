@@ -1,0 +1,314 @@
+// C ABI of libdft3d.so (declared in include/dft3d.h): plan life cycle, table
+// upload, workspace management and pass launches.
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+
+#include "../../include/dft3d.h"
+#include "internal.h"
+
+using namespace dft3d;
+
+struct dft3d_plan_s {
+  int64_t n[3] = {0, 0, 0};
+  int schedule = 0;
+  int resolved = 0;
+  int layout = 0;
+  Options opt;
+  std::vector<Pass> passes;
+  std::vector<int64_t> tw_off, twp_off;  // per pass, element offsets in tables
+  int device = -1;
+  float2* tables = nullptr;
+  size_t ws_need = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+};
+
+namespace {
+
+// Test hook: DFT3D_FAULT_INJECT=alloc|upload|launch forces that step to
+// fail so the error paths can be exercised.
+bool fault(const char* what) {
+  const char* e = std::getenv("DFT3D_FAULT_INJECT");
+  return e && std::strcmp(e, what) == 0;
+}
+
+int validate(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout) {
+  if (schedule < DFT3D_SCHED_AUTO || schedule > DFT3D_SCHED_VOLUMETRIC)
+    return DFT3D_ERR_INVALID_ARG;
+  if (layout != DFT3D_LAYOUT_NATURAL && layout != DFT3D_LAYOUT_SHUFFLED)
+    return DFT3D_ERR_INVALID_ARG;
+  const int64_t n[3] = {n0, n1, n2};
+  for (int d = 0; d < 3; ++d)
+    if (n[d] < 1 || n[d] > 4096 || (n[d] & (n[d] - 1)) != 0)
+      return DFT3D_ERR_UNSUPPORTED_SIZE;
+  return DFT3D_OK;
+}
+
+void free_tables(dft3d_plan_s* p) {
+  if (p->tables) (void)hipFree(p->tables);
+  p->tables = nullptr;
+}
+
+void free_workspace(dft3d_plan_s* p) {
+  if (p->ws_owned && p->ws) (void)hipFree(p->ws);
+  if (p->ws_owned) {
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+  }
+  p->ws_owned = false;
+}
+
+// (Re)build the pass list and upload one root table per distinct length.
+int rebuild(dft3d_plan_s* p) {
+  std::vector<Pass> passes;
+  size_t ws = 0;
+  int resolved = 0;
+  int st = build_passes(p->n, p->schedule, p->layout, p->opt, passes, ws, resolved);
+  if (st != DFT3D_OK) return st;
+
+  std::map<int64_t, int64_t> offsets;  // length -> element offset
+  int64_t total = 0;
+  for (const Pass& ps : passes) {
+    for (int64_t len : {ps.tw_len, ps.twp_len}) {
+      if (len > 0 && !offsets.count(len)) {
+        offsets[len] = total;
+        total += len;
+      }
+    }
+  }
+  std::vector<float2> host((size_t)total);
+  for (auto& kv : offsets) make_roots(kv.first, host.data() + kv.second);
+
+  float2* dev = nullptr;
+  if (fault("alloc") || hipMalloc(&dev, sizeof(float2) * (size_t)total) != hipSuccess) {
+    (void)hipGetLastError();
+    return DFT3D_ERR_OUT_OF_MEMORY;
+  }
+  if (fault("upload") || hipMemcpy(dev, host.data(), sizeof(float2) * (size_t)total,
+                                   hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(dev);
+    return DFT3D_ERR_HIP;
+  }
+  free_tables(p);
+  p->tables = dev;
+  p->passes.swap(passes);
+  p->tw_off.clear();
+  p->twp_off.clear();
+  for (const Pass& ps : p->passes) {
+    p->tw_off.push_back(offsets[ps.tw_len]);
+    p->twp_off.push_back(ps.twp_len > 0 ? offsets[ps.twp_len] : 0);
+  }
+  p->resolved = resolved;
+  if (ws > p->ws_need && p->ws_owned) free_workspace(p);  // regrown lazily
+  p->ws_need = ws;
+  return DFT3D_OK;
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dft3d_status_string(int status) {
+  switch (status) {
+    case DFT3D_OK: return "ok";
+    case DFT3D_ERR_INVALID_ARG: return "invalid argument";
+    case DFT3D_ERR_UNSUPPORTED_SIZE: return "unsupported size (each n_d must be a power of two in [1, 4096])";
+    case DFT3D_ERR_UNSUPPORTED_SCHEDULE: return "unsupported schedule/layout/precision combination";
+    case DFT3D_ERR_NO_DEVICE: return "no HIP device";
+    case DFT3D_ERR_OUT_OF_MEMORY: return "device out of memory";
+    case DFT3D_ERR_HIP: return "HIP runtime error";
+    case DFT3D_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+int dft3d_plan_describe(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
+                        char* buf, size_t len, size_t* needed) {
+  int st = validate(n0, n1, n2, schedule, layout);
+  if (st != DFT3D_OK) return st;
+  const int64_t n[3] = {n0, n1, n2};
+  std::vector<Pass> passes;
+  size_t ws = 0;
+  int resolved = 0;
+  st = build_passes(n, schedule, layout, Options{}, passes, ws, resolved);
+  if (st != DFT3D_OK) return st;
+  const std::string s = describe_passes(n, resolved, passes, ws);
+  if (needed) *needed = s.size() + 1;
+  if (buf && len > 0) {
+    const size_t m = s.size() < len - 1 ? s.size() : len - 1;
+    std::memcpy(buf, s.data(), m);
+    buf[m] = '\0';
+  }
+  return DFT3D_OK;
+}
+
+int dft3d_plan(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
+               dft3d_plan_t* out) {
+  if (!out) return DFT3D_ERR_INVALID_ARG;
+  *out = nullptr;
+  int st = validate(n0, n1, n2, schedule, layout);
+  if (st != DFT3D_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return DFT3D_ERR_NO_DEVICE;
+  }
+  dft3d_plan_s* p = new (std::nothrow) dft3d_plan_s();
+  if (!p) return DFT3D_ERR_OUT_OF_MEMORY;
+  p->n[0] = n0;
+  p->n[1] = n1;
+  p->n[2] = n2;
+  p->schedule = schedule;
+  p->layout = layout;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return DFT3D_ERR_HIP;
+  }
+  st = rebuild(p);
+  if (st != DFT3D_OK) {
+    free_tables(p);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return DFT3D_OK;
+}
+
+int dft3d_plan_set_option(dft3d_plan_t p, int key, int64_t value) {
+  if (!p) return DFT3D_ERR_INVALID_ARG;
+  Options saved = p->opt;
+  switch (key) {
+    case DFT3D_OPT_PRECISION:
+      if (value < DFT3D_PREC_FP32 || value > DFT3D_PREC_FP16X3) return DFT3D_ERR_INVALID_ARG;
+      p->opt.precision = (int)value;
+      break;
+    case DFT3D_OPT_TILE:
+      if (value < 0 || value > 4096 || (value & (value - 1)) != 0) return DFT3D_ERR_INVALID_ARG;
+      p->opt.tile = (int)value;
+      break;
+    case DFT3D_OPT_XCD_REMAP:
+      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
+      p->opt.xcd_remap = (int)value;
+      break;
+    case DFT3D_OPT_SPLIT_MAX:
+      if (value < 0 || value > 4096) return DFT3D_ERR_INVALID_ARG;
+      p->opt.split_max = (int)value;
+      break;
+    default:
+      return DFT3D_ERR_INVALID_ARG;
+  }
+  int st = rebuild(p);
+  if (st != DFT3D_OK) p->opt = saved;  // previous pass list stays in force
+  return st;
+}
+
+int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
+  if (!p || !value) return DFT3D_ERR_INVALID_ARG;
+  switch (key) {
+    case DFT3D_OPT_PRECISION: *value = p->opt.precision; break;
+    case DFT3D_OPT_TILE: *value = p->opt.tile; break;
+    case DFT3D_OPT_XCD_REMAP: *value = p->opt.xcd_remap; break;
+    case DFT3D_OPT_SPLIT_MAX: *value = p->opt.split_max; break;
+    case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
+    default: return DFT3D_ERR_INVALID_ARG;
+  }
+  return DFT3D_OK;
+}
+
+int dft3d_workspace_size(dft3d_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return DFT3D_ERR_INVALID_ARG;
+  *bytes = p->ws_need;
+  return DFT3D_OK;
+}
+
+int dft3d_set_workspace(dft3d_plan_t p, void* dev_ptr, size_t bytes) {
+  if (!p) return DFT3D_ERR_INVALID_ARG;
+  if (!dev_ptr) {
+    if (!p->ws_owned) {
+      p->ws = nullptr;
+      p->ws_bytes = 0;
+    }
+    return DFT3D_OK;
+  }
+  if (bytes < p->ws_need) return DFT3D_ERR_WORKSPACE_TOO_SMALL;
+  free_workspace(p);
+  p->ws = dev_ptr;
+  p->ws_bytes = bytes;
+  p->ws_owned = false;
+  return DFT3D_OK;
+}
+
+int dft3d_execute(dft3d_plan_t p, const void* in, void* out, int sign, void* stream) {
+  if (!p || !in || !out || (sign != -1 && sign != 1)) return DFT3D_ERR_INVALID_ARG;
+  const size_t bytes = (size_t)(p->n[0] * p->n[1] * p->n[2]) * sizeof(float2);
+  if (overlaps(in, out, bytes)) return DFT3D_ERR_INVALID_ARG;
+  if (p->ws_need > 0 && (!p->ws || p->ws_bytes < p->ws_need)) {
+    if (!p->ws_owned && p->ws) return DFT3D_ERR_WORKSPACE_TOO_SMALL;
+    free_workspace(p);
+    void* w = nullptr;
+    if (fault("alloc") || hipMalloc(&w, p->ws_need) != hipSuccess) {
+      (void)hipGetLastError();
+      return DFT3D_ERR_OUT_OF_MEMORY;
+    }
+    p->ws = w;
+    p->ws_bytes = p->ws_need;
+    p->ws_owned = true;
+  }
+  if (p->ws_need > 0 && (overlaps(p->ws, in, bytes) || overlaps(p->ws, out, bytes)))
+    return DFT3D_ERR_INVALID_ARG;
+  if (fault("launch")) return DFT3D_ERR_HIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* bufs[3] = {const_cast<float2*>(static_cast<const float2*>(in)),
+                     static_cast<float2*>(out), static_cast<float2*>(p->ws)};
+  const size_t np = p->passes.size();
+  for (size_t i = 0; i < np; ++i) {
+    const Pass& ps = p->passes[i];
+    PassArgs a = ps.args;
+    a.conj_in = (sign == 1 && i == 0) ? 1 : 0;
+    a.conj_out = (sign == 1 && i + 1 == np) ? 1 : 0;
+    const float2* tw = p->tables + p->tw_off[i];
+    const float2* twp = p->tables + p->twp_off[i];
+    hipError_t e = ps.k->launch(a, bufs[ps.src], bufs[ps.dst], tw, twp, s);
+    if (e != hipSuccess) return DFT3D_ERR_HIP;
+  }
+  return DFT3D_OK;
+}
+
+int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
+                          void* const* out, int count, int sign, void* stream) {
+  if (count == 0) return DFT3D_OK;
+  if (count < 0 || !plans || !in || !out || (sign != -1 && sign != 1))
+    return DFT3D_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !in[i] || !out[i]) return DFT3D_ERR_INVALID_ARG;
+    if (plans[i]->layout != DFT3D_LAYOUT_NATURAL || plans[i]->opt.precision != 0)
+      return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+  }
+  for (int i = 0; i < count; ++i) {
+    int st = dft3d_execute(plans[i], in[i], out[i], sign, stream);
+    if (st != DFT3D_OK) return st;
+  }
+  return DFT3D_OK;
+}
+
+int dft3d_destroy(dft3d_plan_t p) {
+  if (!p) return DFT3D_OK;
+  free_workspace(p);
+  free_tables(p);
+  delete p;
+  return DFT3D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal declarations shared by the host planner, the runtime and the
+// kernel translation units of libdft3d.so.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dft3d {
+
+// How a pass reads or writes a tile of T pencils.
+//   ROW: the pencil's own elements are contiguous (element stride 1), so
+//        lanes run along the pencil;
+//   COL: consecutive pencils are contiguous (pencil stride 1), so lanes run
+//        across the T pencils of the tile and every element row is one
+//        T * 8-byte segment.
+enum Mode { MODE_ROW = 0, MODE_COL = 1 };
+
+// Kernel arguments of one batched-1D-FFT pass.  Pencil b (0 <= b < B) is
+// split into three bit fields b0 = b & m0, b1 = (b >> s0) & m1, b2 = b >> s1;
+// element j of pencil b is read at  b2*is2 + b1*is1 + b0*is0 + j*ijs  and
+// output k is written at  b2*os2 + b1*os1 + b0*os0 + k*oks  (complex64
+// units).  With post_twiddle, output k of pencil b is multiplied by
+// w_L^{(res * k) mod L}, res = (b >> res_shift) & res_mask, L = twp_mask + 1
+// (the twiddle stage of eq. (3) / eq. (14)).
+struct PassArgs {
+  int64_t B;
+  int64_t m0, m1;
+  int32_t s0, s1;
+  int64_t is0, is1, is2, ijs;
+  int64_t os0, os1, os2, oks;
+  int64_t res_mask, twp_mask;
+  int32_t res_shift;
+  int32_t conj_in, conj_out;  // inverse as conj(DFT(conj(x)))
+  int32_t xcd_remap;          // 1: consecutive tiles on one XCD
+};
+
+using LaunchFn = hipError_t (*)(const PassArgs&, const float2* src, float2* dst,
+                                const float2* tw, const float2* twp,
+                                hipStream_t stream);
+
+struct KernelInfo {
+  int n;             // transform length
+  int tile;          // pencils per workgroup
+  int lmode, smode;  // Mode of the load and of the store
+  int post_twiddle;  // 1: multiply outputs by the four-step twiddle
+  int threads;       // workgroup size
+  int lds_bytes;     // static LDS per workgroup
+  LaunchFn launch;
+};
+
+// All compiled pass kernels.
+const std::vector<KernelInfo>& kernel_registry();
+const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle);
+
+// Roots w_n^m = exp(-2 pi i m / n), m < n, computed in FP64 with exact
+// octant reduction and rounded once to FP32 (eq. (4) entries).
+void make_roots(int64_t n, float2* out);
+
+enum BufId { BUF_IN = 0, BUF_OUT = 1, BUF_WS = 2 };
+
+struct Pass {
+  const KernelInfo* k = nullptr;
+  int src = BUF_IN, dst = BUF_OUT;
+  PassArgs args{};
+  int64_t tw_len = 0;   // root table of the transform length (== k->n)
+  int64_t twp_len = 0;  // post-twiddle table length, 0 if none
+  std::string label;
+};
+
+struct Options {
+  int precision = 0;
+  int tile = 0;        // 0: default per pass
+  int xcd_remap = 1;
+  int split_max = 0;   // 0: default
+};
+
+// Builds the pass list of a schedule.  Returns a dft3d status; on success
+// fills passes and the workspace size in bytes.
+int build_passes(const int64_t n[3], int schedule, int layout, const Options& opt,
+                 std::vector<Pass>& passes, size_t& ws_bytes, int& resolved_schedule);
+
+std::string describe_passes(const int64_t n[3], int schedule,
+                            const std::vector<Pass>& passes, size_t ws_bytes);
+
+}  // namespace dft3d

@@ -1,0 +1,9 @@
+// Pass kernels for transform length 1024.
+#include "pass_kernel.h"
+
+namespace dft3d {
+void register_kernels_1k(std::vector<KernelInfo>& v) {
+  add_kernels<1024, 8>(v);
+  add_kernels<1024, 16>(v);
+}
+}  // namespace dft3d

@@ -1,0 +1,314 @@
+// Schedule planner: turns (n0, n1, n2, schedule) into a list of batched-1D
+// FFT passes.  Pure host code; touches no device, so plans can be described
+// and checked on a machine without a GPU.
+//
+//   PENCIL (eq. (8), Section 2.4): three passes; each transforms the
+//     contiguous axis of the current (c0, c1, c2) array, seen as a (B, c2)
+//     matrix, and writes the result transposed, (c2, B), so the data turns
+//     xyz -> yzx -> zxy and is back in natural order after the third pass.
+//   SLAB (eq. (6), Fig. 5): natural layout throughout; the 2D DFT of each
+//     (n1, n2) plane (rows, then columns), then the 1D DFT along n0.
+//   VOLUMETRIC (Fig. 9, eqs. (13)-(17)): natural layout; every axis of
+//     length n = A * Bf is split four-step style: V1 = DFT_Bf over the
+//     stride-A subsequences x[l + A k] of each residue l, times w_n^{l k'},
+//     stored exchanged as T0[k'][l]; V2 = DFT_A over l, stored at
+//     y[k' + Bf l'].
+//   AUTO: the pencil rotation, with axes longer than a threshold split into
+//     V1 + V2 as in the volumetric schedule.
+#include <algorithm>
+#include <cstdio>
+#include <sstream>
+
+#include "../../include/dft3d.h"
+#include "internal.h"
+
+namespace dft3d {
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+constexpr int kNoSplit = 62;  // bit position beyond any pencil index
+
+// Default pencils per workgroup for a transform length.
+int default_tile(int n) {
+  switch (n) {
+    case 1: case 2: case 4: case 8: case 16: return 256;
+    case 32: return 128;
+    case 64: return 64;
+    case 128: return 32;
+    case 256: return 32;
+    case 512: return 16;
+    case 1024: return 16;
+    case 2048: return 8;
+    default: return 4;
+  }
+}
+
+const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options& opt) {
+  if (opt.tile > 0) {
+    if (const KernelInfo* k = find_kernel(n, opt.tile, lmode, smode, tw)) return k;
+  }
+  if (const KernelInfo* k = find_kernel(n, default_tile(n), lmode, smode, tw)) return k;
+  // any available tile for this length
+  for (const KernelInfo& k : kernel_registry())
+    if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw) return &k;
+  return nullptr;
+}
+
+struct Field {  // one bit field of the pencil index
+  int64_t count;
+  int64_t in_stride, out_stride;
+};
+
+// Fills the pencil-index decomposition of a pass from up to three fields,
+// listed fastest first.
+void set_fields(PassArgs& a, const Field* f, int nf) {
+  int64_t c0 = nf > 0 ? f[0].count : 1, c1 = nf > 1 ? f[1].count : 1;
+  a.B = 1;
+  for (int i = 0; i < nf; ++i) a.B *= f[i].count;
+  a.s0 = nf > 1 ? ilog2(c0) : kNoSplit;
+  a.m0 = nf > 1 ? c0 - 1 : (int64_t(1) << kNoSplit) - 1;
+  a.is0 = nf > 0 ? f[0].in_stride : 0;
+  a.os0 = nf > 0 ? f[0].out_stride : 0;
+  a.s1 = nf > 2 ? a.s0 + ilog2(c1) : kNoSplit;
+  a.m1 = nf > 2 ? c1 - 1 : (nf > 1 ? (int64_t(1) << (kNoSplit - a.s0)) - 1 : 0);
+  a.is1 = nf > 1 ? f[1].in_stride : 0;
+  a.os1 = nf > 1 ? f[1].out_stride : 0;
+  a.is2 = nf > 2 ? f[2].in_stride : 0;
+  a.os2 = nf > 2 ? f[2].out_stride : 0;
+}
+
+struct Builder {
+  const Options& opt;
+  std::vector<Pass>& passes;
+  int status = DFT3D_OK;
+
+  void add(int n, int lmode, int smode, int tw, const Field* f, int nf, int64_t ijs,
+           int64_t oks, int64_t twp_len, int res_shift, int64_t res_mask,
+           const std::string& label) {
+    const KernelInfo* k = pick_kernel(n, lmode, smode, tw, opt);
+    if (!k) {
+      status = DFT3D_ERR_UNSUPPORTED_SIZE;
+      return;
+    }
+    Pass p;
+    p.k = k;
+    set_fields(p.args, f, nf);
+    p.args.ijs = ijs;
+    p.args.oks = oks;
+    p.args.xcd_remap = opt.xcd_remap;
+    p.tw_len = n;
+    p.twp_len = twp_len;
+    if (tw) {
+      p.args.res_shift = res_shift;
+      p.args.res_mask = res_mask;
+      p.args.twp_mask = twp_len - 1;
+    }
+    p.label = label;
+    passes.push_back(p);
+  }
+};
+
+// Four-step factor choice for a split axis: n = A * Bf with A the number of
+// residues (the stride of the V1 subsequences) and Bf the V1 length.
+void split_axis(int64_t n, int64_t& A, int64_t& Bf) {
+  const int l = ilog2(n);
+  A = int64_t(1) << ((l + 1) / 2);
+  Bf = n / A;
+}
+
+// V1 + V2 of one axis in natural layout: the array is [outer][n][inner].
+void volumetric_axis(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis) {
+  int64_t A, Bf;
+  split_axis(n, A, Bf);
+  const int64_t slab = n * inner;
+  char lab[64];
+  {  // V1: pencils (o, l, c) with m = l * inner + c contiguous
+    Field f[2] = {{A * inner, 1, 1}, {outer, slab, slab}};
+    std::snprintf(lab, sizeof lab, "vol%d.V1 DFT%lld x%lld", axis, (long long)Bf,
+                  (long long)(outer * A * inner));
+    b.add((int)Bf, MODE_COL, MODE_COL, 1, f, 2, A * inner, A * inner, n,
+          ilog2(inner), A - 1, lab);
+  }
+  {  // V2: pencils (o, k', c); elements l at stride inner
+    std::snprintf(lab, sizeof lab, "vol%d.V2 DFT%lld x%lld", axis, (long long)A,
+                  (long long)(outer * Bf * inner));
+    if (inner == 1) {
+      Field f[2] = {{Bf, A, 1}, {outer, slab, slab}};
+      b.add((int)A, MODE_ROW, MODE_COL, 0, f, 2, 1, Bf, 0, 0, 0, lab);
+    } else {
+      Field f[3] = {{inner, 1, 1}, {Bf, A * inner, inner}, {outer, slab, slab}};
+      b.add((int)A, MODE_COL, MODE_COL, 0, f, 3, inner, Bf * inner, 0, 0, 0, lab);
+    }
+  }
+}
+
+// One rotate-on-write step of the pencil schedule on a (c0, c1, c2) array:
+// transform along c2 and write (c2, c0, c1).  With split, the c2 axis goes
+// through V1 (natural) and a rotating V2.
+void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
+  const int64_t n = cur[2], B = cur[0] * cur[1];
+  char lab[64];
+  if (!split) {
+    Field f[1] = {{B, n, 1}};
+    std::snprintf(lab, sizeof lab, "pencil%d DFT%lld x%lld rot", axis, (long long)n,
+                  (long long)B);
+    b.add((int)n, MODE_ROW, MODE_COL, 0, f, 1, 1, B, 0, 0, 0, lab);
+    return;
+  }
+  int64_t A, Bf;
+  split_axis(n, A, Bf);
+  {  // V1: pencils (o, l), elements x[o][l + A k]; T0[o][k'][l]
+    Field f[2] = {{A, 1, 1}, {B, n, n}};
+    std::snprintf(lab, sizeof lab, "pencil%d.V1 DFT%lld x%lld", axis, (long long)Bf,
+                  (long long)(B * A));
+    b.add((int)Bf, MODE_COL, MODE_COL, 1, f, 2, A, A, n, 0, A - 1, lab);
+  }
+  {  // V2 rotating: pencils (o fastest, k'); y[k' + Bf l'] goes to row
+     // (k' + Bf l') of the (n, B) output
+    Field f[2] = {{B, n, 1}, {Bf, A, B}};
+    std::snprintf(lab, sizeof lab, "pencil%d.V2 DFT%lld x%lld rot", axis,
+                  (long long)A, (long long)(B * Bf));
+    b.add((int)A, MODE_ROW, MODE_COL, 0, f, 2, 1, Bf * B, 0, 0, 0, lab);
+  }
+}
+
+// Buffers for a chain of passes from IN to OUT that never writes IN and
+// never reads and writes the same buffer in one (not in-place-safe) pass.
+void assign_chain(std::vector<Pass>& passes, size_t first, size_t& ws_needed_flag) {
+  const size_t cnt = passes.size() - first;
+  // Alternate OUT / WS so that the last pass writes OUT.
+  int dst = (cnt % 2 == 1) ? BUF_OUT : BUF_WS;
+  int src = BUF_IN;
+  for (size_t i = first; i < passes.size(); ++i) {
+    passes[i].src = src;
+    passes[i].dst = dst;
+    if (dst == BUF_WS) ws_needed_flag = 1;
+    src = dst;
+    dst = (dst == BUF_OUT) ? BUF_WS : BUF_OUT;
+  }
+}
+
+}  // namespace
+
+int build_passes(const int64_t n[3], int schedule, int layout, const Options& opt,
+                 std::vector<Pass>& passes, size_t& ws_bytes, int& resolved) {
+  passes.clear();
+  ws_bytes = 0;
+  for (int d = 0; d < 3; ++d)
+    if (!is_pow2(n[d]) || n[d] > 4096) return DFT3D_ERR_UNSUPPORTED_SIZE;
+  if (schedule < DFT3D_SCHED_AUTO || schedule > DFT3D_SCHED_VOLUMETRIC)
+    return DFT3D_ERR_INVALID_ARG;
+  if (layout != DFT3D_LAYOUT_NATURAL && layout != DFT3D_LAYOUT_SHUFFLED)
+    return DFT3D_ERR_INVALID_ARG;
+  if (layout != DFT3D_LAYOUT_NATURAL) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+  if (opt.precision != DFT3D_PREC_FP32) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+
+  const int64_t total = n[0] * n[1] * n[2];
+  Builder b{opt, passes};
+  resolved = schedule;
+  if (schedule == DFT3D_SCHED_AUTO) resolved = DFT3D_SCHED_PENCIL;
+  const int64_t split_max =
+      opt.split_max > 0 ? opt.split_max
+                        : (schedule == DFT3D_SCHED_AUTO ? 1024 : int64_t(1) << 20);
+
+  size_t need_ws = 0;
+  if (resolved == DFT3D_SCHED_PENCIL) {
+    int64_t cur[3] = {n[0], n[1], n[2]};
+    for (int step = 0; step < 3; ++step) {
+      const int axis = 2 - step;
+      pencil_axis(b, cur, cur[2] > split_max && cur[2] >= 4, axis);
+      const int64_t c2 = cur[2];
+      cur[2] = cur[1];
+      cur[1] = cur[0];
+      cur[0] = c2;
+    }
+    assign_chain(passes, 0, need_ws);
+  } else if (resolved == DFT3D_SCHED_SLAB) {
+    // rows (axis 2) IN -> OUT, then columns (axis 1) and axis 0 in place
+    char lab[64];
+    {
+      Field f[1] = {{n[0] * n[1], n[2], n[2]}};
+      std::snprintf(lab, sizeof lab, "slab.rows DFT%lld", (long long)n[2]);
+      b.add((int)n[2], MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
+    }
+    {
+      Field f[2] = {{n[2], 1, 1}, {n[0], n[1] * n[2], n[1] * n[2]}};
+      std::snprintf(lab, sizeof lab, "slab.cols DFT%lld", (long long)n[1]);
+      b.add((int)n[1], MODE_COL, MODE_COL, 0, f, 2, n[2], n[2], 0, 0, 0, lab);
+    }
+    {
+      Field f[1] = {{n[1] * n[2], 1, 1}};
+      std::snprintf(lab, sizeof lab, "slab.depth DFT%lld", (long long)n[0]);
+      b.add((int)n[0], MODE_COL, MODE_COL, 0, f, 1, n[1] * n[2], n[1] * n[2], 0, 0, 0,
+            lab);
+    }
+    if (b.status == DFT3D_OK) {
+      passes[0].src = BUF_IN;
+      passes[0].dst = BUF_OUT;
+      for (size_t i = 1; i < passes.size(); ++i) passes[i].src = passes[i].dst = BUF_OUT;
+    }
+  } else {  // VOLUMETRIC
+    for (int axis = 2; axis >= 0; --axis) {
+      int64_t outer = 1, inner = 1;
+      for (int d = 0; d < axis; ++d) outer *= n[d];
+      for (int d = axis + 1; d < 3; ++d) inner *= n[d];
+      if (n[axis] >= 4) {
+        volumetric_axis(b, outer, n[axis], inner, axis);
+      } else {  // too short to split: one in-layout pass
+        char lab[64];
+        std::snprintf(lab, sizeof lab, "vol%d DFT%lld", axis, (long long)n[axis]);
+        if (inner == 1) {
+          Field f[1] = {{outer, n[axis], n[axis]}};
+          b.add((int)n[axis], MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
+        } else {
+          Field f[2] = {{inner, 1, 1}, {outer, n[axis] * inner, n[axis] * inner}};
+          b.add((int)n[axis], MODE_COL, MODE_COL, 0, f, 2, inner, inner, 0, 0, 0, lab);
+        }
+      }
+    }
+    assign_chain(passes, 0, need_ws);
+  }
+  if (b.status != DFT3D_OK) {
+    passes.clear();
+    return b.status;
+  }
+  ws_bytes = need_ws ? (size_t)total * 8 : 0;
+  return DFT3D_OK;
+}
+
+std::string describe_passes(const int64_t n[3], int schedule,
+                            const std::vector<Pass>& passes, size_t ws_bytes) {
+  static const char* kSched[] = {"auto", "slab", "pencil", "volumetric"};
+  static const char* kBuf[] = {"in", "out", "ws"};
+  std::ostringstream os;
+  os << "{\"shape\":[" << n[0] << "," << n[1] << "," << n[2] << "],\"schedule\":\""
+     << kSched[schedule] << "\",\"workspace_bytes\":" << ws_bytes << ",\"passes\":[";
+  for (size_t i = 0; i < passes.size(); ++i) {
+    const Pass& p = passes[i];
+    if (i) os << ",";
+    os << "{\"label\":\"" << p.label << "\",\"n\":" << p.k->n << ",\"tile\":" << p.k->tile
+       << ",\"load\":\"" << (p.k->lmode == MODE_ROW ? "row" : "col") << "\",\"store\":\""
+       << (p.k->smode == MODE_ROW ? "row" : "col") << "\",\"post_twiddle\":"
+       << p.k->post_twiddle << ",\"threads\":" << p.k->threads
+       << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
+       << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""
+       << ",\"args\":{\"B\":" << p.args.B << ",\"m0\":" << p.args.m0
+       << ",\"m1\":" << p.args.m1 << ",\"s0\":" << p.args.s0 << ",\"s1\":" << p.args.s1
+       << ",\"is\":[" << p.args.is0 << "," << p.args.is1 << "," << p.args.is2 << "]"
+       << ",\"os\":[" << p.args.os0 << "," << p.args.os1 << "," << p.args.os2 << "]"
+       << ",\"ijs\":" << p.args.ijs << ",\"oks\":" << p.args.oks
+       << ",\"res_shift\":" << p.args.res_shift << ",\"res_mask\":" << p.args.res_mask
+       << ",\"twp_len\":" << p.twp_len << "}}";
+  }
+  os << "]}";
+  return os.str();
+}
+
+}  // namespace dft3d

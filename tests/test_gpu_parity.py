@@ -1,0 +1,155 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element,
+on seeded inputs (paper_1904_10119_amd.inputs), through the C ABI.
+
+Tolerance: relative L2 error <= tol(N) = 1e-6 * log2(N) / 18 (1e-6 at 64^3,
+growing with log N); the inverse round trip gets 2 * tol(N)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_10119_amd import dft3d, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_and_native_library():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dft3d.lib()
+    maps = open("/proc/self/maps").read()
+    assert "libdft3d.so" in maps, "native library not loaded"
+    runtimes = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(runtimes) == 1, runtimes
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_fftn(x_np, schedule, inverse=False, **opts):
+    x = torch.from_numpy(x_np).cuda()
+    y = dft3d.fftn(x, schedule=schedule, inverse=inverse, **opts)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def ref_fftn(x_np, sign):
+    n = x_np.size
+    method = "direct" if n <= (1 << 15) else "fft"
+    return oracle.dft3d(x_np.astype(np.complex128), sign, method)
+
+
+SCHEDULES = ["pencil", "slab", "volumetric", "auto"]
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_64cubed_forward_inverse_roundtrip(schedule):
+    """The 64^3 workload: forward within 1e-6 of the FP64 oracle, inverse
+    within tol, round trip inv(fwd(x)) / N within 2 tol."""
+    shape = (64, 64, 64)
+    say("case 64^3", schedule)
+    x = inputs.uniform_c64(shape, 1)
+    y = gpu_fftn(x, schedule)
+    ref = oracle.dft3d(x.astype(np.complex128), -1, "fft")
+    err = oracle.rel_l2(y, ref)
+    say("  fwd rel_l2", err)
+    assert err <= 1e-6
+    yi = gpu_fftn(x, schedule, inverse=True)
+    refi = oracle.dft3d(x.astype(np.complex128), +1, "fft")
+    assert oracle.rel_l2(yi, refi) <= 1e-6
+    back = gpu_fftn(y, schedule, inverse=True) / x.size
+    assert oracle.rel_l2(back, x) <= 2e-6
+
+
+SHAPES = [
+    (1, 1, 1), (2, 2, 2), (1, 4, 1), (8, 16, 4), (4, 8, 16), (32, 2, 64),
+    (128, 64, 32), (32, 64, 128), (16, 512, 8), (1024, 4, 2), (2, 2, 1024),
+    (2048, 2, 4), (4, 2048, 2), (2, 4, 4096), (4096, 2, 2),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_shapes_and_lengths(shape, schedule):
+    """Every transform length 1..4096 on every schedule, anisotropic shapes
+    (catch axis mix-ups), tiles larger than the batch (ragged tails)."""
+    say("case", shape, schedule)
+    x = inputs.uniform_c64(shape, 21)
+    n = x.size
+    for sign, inv in ((-1, False), (1, True)):
+        y = gpu_fftn(x, schedule, inverse=inv)
+        err = oracle.rel_l2(y, ref_fftn(x, sign))
+        assert err <= oracle.tol(n), (shape, schedule, sign, err)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32, 64, 128, 256])
+def test_tile_variants(tile):
+    shape = (64, 128, 32)
+    x = inputs.uniform_c64(shape, 22)
+    ref = ref_fftn(x, -1)
+    for sched in ("pencil", "slab", "volumetric"):
+        y = gpu_fftn(x, sched, tile=tile)
+        assert oracle.rel_l2(y, ref) <= oracle.tol(x.size), (tile, sched)
+
+
+@pytest.mark.parametrize("split_max", [2, 16, 64])
+def test_pencil_with_split_axes(split_max):
+    """Pencil rotation with every long axis split four-step (V1 + V2)."""
+    shape = (256, 128, 64)
+    x = inputs.uniform_c64(shape, 23)
+    ref = ref_fftn(x, -1)
+    y = gpu_fftn(x, "auto", split_max=split_max)
+    assert oracle.rel_l2(y, ref) <= oracle.tol(x.size)
+
+
+def test_256cubed_all_schedules():
+    shape = (256, 256, 256)
+    x = inputs.uniform_c64(shape, 3)
+    ref = oracle.dft3d(x.astype(np.complex128), -1, "fft")
+    for sched in SCHEDULES:
+        say("case 256^3", sched)
+        y = gpu_fftn(x, sched)
+        err = oracle.rel_l2(y, ref)
+        say("  rel_l2", err)
+        assert err <= oracle.tol(x.size)
+
+
+def test_deterministic_and_input_untouched():
+    x = inputs.uniform_c64((128, 128, 128), 24)
+    xt = torch.from_numpy(x).cuda()
+    a = dft3d.fftn(xt, schedule="pencil")
+    b = dft3d.fftn(xt, schedule="pencil")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert np.array_equal(xt.cpu().numpy(), x)
+
+
+def test_schedules_agree():
+    x = inputs.uniform_c64((128, 256, 64), 25)
+    xt = torch.from_numpy(x).cuda()
+    outs = {s: dft3d.fftn(xt, schedule=s).cpu().numpy() for s in SCHEDULES}
+    for s in SCHEDULES:
+        assert oracle.rel_l2(outs[s], outs["pencil"]) <= 2 * oracle.tol(x.size)
+
+
+def test_execute_rejects_aliasing_and_bad_sign():
+    p = dft3d.Plan((8, 8, 8), "pencil")
+    x = torch.zeros((8, 8, 8), dtype=torch.complex64, device="cuda")
+    L = dft3d.lib()
+    assert L.dft3d_execute(p.handle, x.data_ptr(), x.data_ptr(), -1, None) == \
+        dft3d.ERR_INVALID_ARG
+    y = torch.empty_like(x)
+    assert L.dft3d_execute(p.handle, x.data_ptr(), y.data_ptr(), 0, None) == \
+        dft3d.ERR_INVALID_ARG
+    p.bind_workspace(x.device)
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    assert L.dft3d_set_workspace(p.handle, ws.data_ptr(), 16) == \
+        dft3d.ERR_WORKSPACE_TOO_SMALL
+    p.close()

@@ -1,0 +1,95 @@
+"""CPU model of the planner's index arithmetic.
+
+For every pass of every schedule the library plans, the kernel reads
+element j of pencil b at
+  (b >> s1) is2 + ((b >> s0) & m1) is1 + (b & m0) is0 + j ijs
+and writes output k at the same form with the output strides.  These tests
+check (a) that each pass's read and write maps are bijections onto
+[0, N) -- so no kernel can touch memory outside its buffers -- and (b) that
+running the pass list with a plain per-pencil DFT reproduces the oracle's 3D
+DFT, which checks the schedules' index math without a GPU."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_10119_amd import dft3d
+
+SCHEDULES = ["auto", "slab", "pencil", "volumetric"]
+SHAPES = [(1, 1, 1), (2, 4, 8), (8, 2, 4), (16, 16, 16), (32, 4, 64), (4, 64, 2),
+          (2, 256, 8), (64, 1, 32), (4096, 2, 1), (1, 2, 2048)]
+
+
+def addresses(args, n, inp):
+    B = args["B"]
+    b = np.arange(B, dtype=np.int64)
+    st = args["is"] if inp else args["os"]
+    js = args["ijs"] if inp else args["oks"]
+    base = ((b >> args["s1"]) * st[2] + ((b >> args["s0"]) & args["m1"]) * st[1]
+            + (b & args["m0"]) * st[0])
+    j = np.arange(n, dtype=np.int64)
+    return base[:, None] + j[None, :] * js        # (B, n)
+
+
+def run_model(x, d, sign):
+    n_total = x.size
+    bufs = {"in": x.reshape(-1).astype(np.complex128),
+            "out": np.full(n_total, np.nan, np.complex128),
+            "ws": np.full(n_total, np.nan, np.complex128)}
+    passes = d["passes"]
+    for i, p in enumerate(passes):
+        a = p["args"]
+        ia = addresses(a, p["n"], True)
+        oa = addresses(a, p["n"], False)
+        v = bufs[p["src"]][ia]
+        if sign == 1 and i == 0:
+            v = np.conj(v)
+        y = np.fft.fft(v, axis=1)
+        if p["post_twiddle"]:
+            L = a["twp_len"]
+            res = (np.arange(a["B"]) >> a["res_shift"]) & a["res_mask"]
+            k = np.arange(p["n"])
+            y = y * np.exp(-2j * np.pi * ((res[:, None] * k[None, :]) % L) / L)
+        if sign == 1 and i == len(passes) - 1:
+            y = np.conj(y)
+        bufs[p["dst"]][oa] = y
+    return bufs["out"].reshape(x.shape)
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(1024, 1024, 1024), (2048, 1024, 512),
+                                            (4096, 4096, 4)])
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_pass_maps_are_bijections(shape, schedule):
+    d = dft3d.describe(shape, schedule)
+    N = shape[0] * shape[1] * shape[2]
+    for p in d["passes"]:
+        a = p["args"]
+        if a["B"] * p["n"] > (1 << 22):
+            # sampled: the first, last and a middle block of pencils
+            B = a["B"]
+            for lo in (0, B // 2, B - 64):
+                sub = dict(a, B=B)
+                b = np.arange(lo, lo + 64, dtype=np.int64)
+                for inp in (True, False):
+                    st = a["is"] if inp else a["os"]
+                    js = a["ijs"] if inp else a["oks"]
+                    base = ((b >> a["s1"]) * st[2] + ((b >> a["s0"]) & a["m1"]) * st[1]
+                            + (b & a["m0"]) * st[0])
+                    hi = base.max() + (p["n"] - 1) * js
+                    assert base.min() >= 0 and hi < N, (p["label"], inp)
+            continue
+        for inp in (True, False):
+            addr = addresses(a, p["n"], inp).reshape(-1)
+            assert addr.min() >= 0 and addr.max() < N, (p["label"], inp)
+            assert np.unique(addr).size == N, (p["label"], inp)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_pass_list_computes_the_dft(shape, schedule):
+    g = np.random.default_rng(sum(shape))
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    d = dft3d.describe(shape, schedule)
+    for sign in (-1, 1):
+        got = run_model(x, d, sign)
+        ref = oracle.dft3d(x, sign, "fft")
+        assert oracle.rel_l2(got, ref) < 1e-13, (shape, schedule, sign)
