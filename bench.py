@@ -52,7 +52,7 @@ def time_plan(plan, x, out, steps, warmup, inverse=False):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(x_host, frac_den=16):
+def cpu_baseline(x_host, frac_den=4):
     """The oracle (O2, FP64) on 1/frac_den of the pencils of every axis."""
     import oracle
     n0, n1, n2 = x_host.shape
@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--breakdown", action="store_true",
                     help="also time every schedule forward and inverse")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a plain device copy of the array (the "
+                         "reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -147,6 +150,23 @@ def main():
             log(f"bench: {s}: {sched[s]}")
             p.close()
         result["schedules"] = sched
+    if args.copy_calibration:
+        for _ in range(2):
+            out.copy_(x)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        for _ in range(args.steps):
+            out.copy_(x)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1) / args.steps
+        result["copy_calibration"] = {"bytes_per_launch": 16 * N,
+                                      "avg_launch_ms": round(cms, 4),
+                                      "gbs": round(16.0 * N / (cms * 1e-3) / 1e9, 1)}
+        log(f"bench: device copy {result['copy_calibration']}")
     del x, out
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

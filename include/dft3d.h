@@ -92,6 +92,12 @@ enum dft3d_option {
   DFT3D_OPT_XCD_REMAP = 3,   /* 1 = map consecutive tiles to one XCD; default 1 */
   DFT3D_OPT_SPLIT_MAX = 4,   /* longest axis done in one pass; longer axes
                                 are split four-step; 0 = default */
+  DFT3D_OPT_NONTEMPORAL = 5, /* streaming (non-temporal) loads and stores:
+                                0 off, 1 on, 2 automatic (default): on with
+                                the persistent kernels for arrays of 256 MiB
+                                or more, off otherwise */
+  DFT3D_OPT_PERSISTENT = 6,  /* 1 = persistent prefetching pass kernels
+                                where compiled (default 1) */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

@@ -206,6 +206,14 @@ int dft3d_plan_set_option(dft3d_plan_t p, int key, int64_t value) {
       if (value < 0 || value > 4096) return DFT3D_ERR_INVALID_ARG;
       p->opt.split_max = (int)value;
       break;
+    case DFT3D_OPT_NONTEMPORAL:
+      if (value < 0 || value > 2) return DFT3D_ERR_INVALID_ARG;
+      p->opt.nontemporal = (int)value;
+      break;
+    case DFT3D_OPT_PERSISTENT:
+      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
+      p->opt.persistent = (int)value;
+      break;
     default:
       return DFT3D_ERR_INVALID_ARG;
   }
@@ -221,6 +229,8 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_TILE: *value = p->opt.tile; break;
     case DFT3D_OPT_XCD_REMAP: *value = p->opt.xcd_remap; break;
     case DFT3D_OPT_SPLIT_MAX: *value = p->opt.split_max; break;
+    case DFT3D_OPT_NONTEMPORAL: *value = p->opt.nontemporal; break;
+    case DFT3D_OPT_PERSISTENT: *value = p->opt.persistent; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }

@@ -49,11 +49,14 @@ struct KernelInfo {
   int threads;       // workgroup size
   int lds_bytes;     // static LDS per workgroup
   LaunchFn launch;
+  int persistent;    // 1: grid of resident workgroups walking all tiles
+  int nontemporal;   // 1: streaming (non-temporal) loads and stores
 };
 
 // All compiled pass kernels.
 const std::vector<KernelInfo>& kernel_registry();
-const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle);
+const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle,
+                              int persistent, int nontemporal);
 
 // Roots w_n^m = exp(-2 pi i m / n), m < n, computed in FP64 with exact
 // octant reduction and rounded once to FP32 (eq. (4) entries).
@@ -75,6 +78,8 @@ struct Options {
   int tile = 0;        // 0: default per pass
   int xcd_remap = 1;
   int split_max = 0;   // 0: default
+  int nontemporal = 2; // 0 off, 1 on, 2 on for arrays above kStreamBytes
+  int persistent = 1;  // use the persistent form where one exists
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

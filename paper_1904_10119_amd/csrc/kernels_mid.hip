@@ -11,5 +11,7 @@ void register_kernels_mid(std::vector<KernelInfo>& v) {
   add_kernels<512, 8>(v);
   add_kernels<512, 16>(v);
   add_kernels<512, 32>(v);
+  add_persistent_kernels<512, 16, Blocking<512>>(v);
+  add_persistent_kernels<512, 32, Blocking<512>>(v);
 }
 }  // namespace dft3d

@@ -48,8 +48,23 @@ DFT3D_BLOCKING(2048, 32, 32, 8, 8)
 DFT3D_BLOCKING(4096, 32, 32, 16, 8)
 #undef DFT3D_BLOCKING
 
-template <int N> constexpr int num_stages() {
-  return Blocking<N>::R1 == 1 ? 1 : (Blocking<N>::R2 == 1 ? 2 : 3);
+// Blocking with 16 elements per thread (three radix stages for the longest
+// lengths): half the registers per pencil element, used by the persistent
+// form, which keeps a second tile in flight in registers.
+template <int N> struct BlockingLow;
+#define DFT3D_BLOCKING_LOW(N_, E_, R0_, R1_, R2_)                           \
+  template <> struct BlockingLow<N_> {                                      \
+    static constexpr int E = E_, R0 = R0_, R1 = R1_, R2 = R2_;              \
+  };
+DFT3D_BLOCKING_LOW(256, 16, 16, 16, 1)
+DFT3D_BLOCKING_LOW(512, 16, 16, 16, 2)
+DFT3D_BLOCKING_LOW(1024, 16, 16, 16, 4)
+DFT3D_BLOCKING_LOW(2048, 16, 16, 16, 8)
+DFT3D_BLOCKING_LOW(4096, 16, 16, 16, 16)
+#undef DFT3D_BLOCKING_LOW
+
+template <class BL> constexpr int num_stages() {
+  return BL::R1 == 1 ? 1 : (BL::R2 == 1 ? 2 : 3);
 }
 
 // LDS: pencil-major, one pad element per 32 so that the stride-R writes of
@@ -89,6 +104,25 @@ __device__ __forceinline__ int64_t tile_index(int64_t bid, int64_t nb, int remap
   const int64_t full = nb & ~int64_t(7);
   if (bid >= full) return bid;
   return (bid & 7) * (full >> 3) + (bid >> 3);
+}
+
+// 8-byte global accesses, optionally marked non-temporal (streamed through
+// the caches without being kept).
+__device__ __forceinline__ float2 load_c64(const float2* p, bool nt) {
+  if (nt) {
+    const unsigned long long u =
+        __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+    return __builtin_bit_cast(float2, u);
+  }
+  return *p;
+}
+__device__ __forceinline__ void store_c64(float2* p, float2 v, bool nt) {
+  if (nt) {
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v),
+                                reinterpret_cast<unsigned long long*>(p));
+  } else {
+    *p = v;
+  }
 }
 
 template <int N, int E, int P, int NS, int R>
@@ -133,43 +167,38 @@ __device__ __forceinline__ void lds_exchange(float2 (&v)[E], float2* lds, int ti
   for (int e = 0; e < E; ++e) v[e] = theirs[lds_pad_index(p + P * e)];
 }
 
-template <int N, int T, int LM, int SM, int TW>
-__global__ void __launch_bounds__(T*(N / Blocking<N>::E))
-fft_pass_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
-                const float2* __restrict__ twp, const PassArgs a) {
-  // src and dst may be the same buffer (in-place passes): every element of a
-  // tile is read before any element of it is written, and tiles are disjoint.
-  constexpr int E = Blocking<N>::E;
-  constexpr int P = N / E;
-  constexpr int NST = num_stages<N>();
-  constexpr int R0 = Blocking<N>::R0, R1 = Blocking<N>::R1, R2 = Blocking<N>::R2;
-  constexpr int SQ = lds_pencil_stride<N, T>();
-  constexpr int LDS_ELEMS = NST > 1 ? T * SQ : 1;
-  __shared__ float2 lds[LDS_ELEMS];
+// Load the tile's T pencils (thread (q, p) gets elements p + P e).  In ROW
+// mode the pencil is contiguous (element stride 1 by construction).  Pencils
+// past the end of a ragged last tile read the last pencil instead (always in
+// bounds; their results are never stored), so the loads carry no branch.
+// Inputs are conjugated (inverse transform) later, in transform_store_tile.
+template <int N, int T, int E, int P, int LM, int NT>
+__device__ __forceinline__ void load_tile(float2 (&v)[E], const float2* src, const PassArgs& a,
+                                          int64_t tile, int q, int p) {
+  int64_t b = tile * T + q;
+  b = b < a.B ? b : a.B - 1;
+  const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+  const int64_t step = LM == MODE_ROW ? P : (int64_t)P * a.ijs;
+  s += LM == MODE_ROW ? (int64_t)p : (int64_t)p * a.ijs;
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = load_c64(s + e * step, NT != 0);
+}
 
-  const int tid = threadIdx.x;
-  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
-  int q, p;
-  thread_map<(NST > 1 ? LM : SM), T, P>(tid, q, p);
-
-  float2 v[E];
-  {
-    const int64_t b = tile * T + q;
-    if (b < a.B) {
-      const float2* s =
-          src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+// Radix stages, LDS exchanges and the store of one tile whose elements are
+// already in v (load mapping).  tw may point to global memory or to LDS.
+template <int N, class BL, int T, int LM, int SM, int TW, int NT, int E, int P, int SQ>
+__device__ __forceinline__ void transform_store_tile(float2 (&v)[E], float2* dst,
+                                                     const float2* tw, const float2* twp,
+                                                     float2* lds, const PassArgs& a,
+                                                     int64_t tile, int tid, int q, int p) {
+  constexpr int NST = num_stages<BL>();
+  constexpr int R0 = BL::R0, R1 = BL::R1, R2 = BL::R2;
+  // inverse as conj(DFT(conj(x))); applied here, where the tile is first
+  // used, so that a prefetched tile is not waited for early
+  if (a.conj_in) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = s[(int64_t)(p + P * e) * a.ijs];
-      if (a.conj_in) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = make_float2(0.f, 0.f);
-    }
+    for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
   }
-
   radix_stage<N, E, P, 1, R0>(v, p, tw);
   if constexpr (NST == 2) {
     lds_exchange<N, E, P, T, SQ, 1, R0, SM>(v, lds, tid, q, p);
@@ -181,43 +210,164 @@ fft_pass_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
     lds_exchange<N, E, P, T, SQ, R0, R1, SM>(v, lds, tid, q, p);
     radix_stage<N, E, P, R0 * R1, R2>(v, p, tw);
   }
-
   const int64_t b = tile * T + q;
   if (b < a.B) {
     float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
     int64_t res = 0;
     if constexpr (TW) res = (b >> a.res_shift) & a.res_mask;
+    const int64_t step = SM == MODE_ROW ? P : (int64_t)P * a.oks;
+    d += SM == MODE_ROW ? (int64_t)p : (int64_t)p * a.oks;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = p + P * e;
-      float2 val = v[e];
-      if constexpr (TW) val = cmul(val, twp[(res * k) & a.twp_mask]);
-      if (a.conj_out) val.y = -val.y;
-      d[(int64_t)k * a.oks] = val;
+      if constexpr (TW) v[e] = cmul(v[e], twp[(res * k) & a.twp_mask]);
+      if (a.conj_out) v[e].y = -v[e].y;
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e) store_c64(d + e * step, v[e], NT != 0);
   }
 }
 
-template <int N, int T, int LM, int SM, int TW>
+// One workgroup per tile.
+template <int N, int T, int LM, int SM, int TW, int NT>
+__global__ void __launch_bounds__(T*(N / Blocking<N>::E))
+fft_pass_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
+                const float2* __restrict__ twp, const PassArgs a) {
+  // src and dst may be the same buffer (in-place passes): every element of a
+  // tile is read before any element of it is written, and tiles are disjoint.
+  using BL = Blocking<N>;
+  constexpr int E = BL::E;
+  constexpr int P = N / E;
+  constexpr int NST = num_stages<BL>();
+  constexpr int SQ = lds_pencil_stride<N, T>();
+  constexpr int LDS_ELEMS = NST > 1 ? T * SQ : 1;
+  __shared__ float2 lds[LDS_ELEMS];
+
+  const int tid = threadIdx.x;
+  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
+  int q, p;
+  thread_map<(NST > 1 ? LM : SM), T, P>(tid, q, p);
+  float2 v[E];
+  load_tile<N, T, E, P, LM, NT>(v, src, a, tile, q, p);
+  transform_store_tile<N, BL, T, LM, SM, TW, NT, E, P, SQ>(v, dst, tw, twp, lds, a, tile,
+                                                           tid, q, p);
+}
+
+// Persistent form: a grid of about one resident workgroup per CU walks the
+// tiles (virtual tile w, w + G, w + 2G, ... for workgroup w, remapped so
+// that each XCD takes a contiguous range) and loads tile i+1 into registers
+// while tile i goes through its stages, so the memory system never waits
+// for a workgroup to finish its arithmetic.  The stage twiddles are copied
+// to LDS once, keeping their reads off the vector-memory queue.
+template <int N, int T, int LM, int SM, int TW, int NT, class BL>
+__global__ void __launch_bounds__(T*(N / BL::E))
+fft_pass_persistent(const float2* src, float2* dst, const float2* __restrict__ tw,
+                    const float2* __restrict__ twp, const PassArgs a) {
+  constexpr int E = BL::E;
+  constexpr int P = N / E;
+  constexpr int NTHR = T * P;
+  constexpr int NST = num_stages<BL>();
+  static_assert(NST > 1, "persistent form is for multi-stage lengths");
+  constexpr int SQ = lds_pencil_stride<N, T>();
+  __shared__ float2 lds[T * SQ];
+  __shared__ float2 ltw[N];
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NTHR) ltw[i] = tw[i];
+  __syncthreads();
+
+  const int64_t ntiles = (a.B + T - 1) / T;
+  const int64_t G = gridDim.x;
+  int64_t w = blockIdx.x;
+  if (w >= ntiles) return;
+  int q0, p0;
+  thread_map<LM, T, P>(tid, q0, p0);
+  // Two register tiles in alternation (loop unrolled by two, so no copies):
+  // the next tile's loads are issued before the current tile's arithmetic.
+  // Past the last tile the prefetch re-reads the last tile (in bounds).
+  const int64_t last = ntiles - 1;
+  float2 ra[E], rb[E];
+  load_tile<N, T, E, P, LM, NT>(ra, src, a, tile_index(w, ntiles, a.xcd_remap), q0, p0);
+  while (true) {
+    int64_t wn = w + G;
+    load_tile<N, T, E, P, LM, NT>(rb, src, a, tile_index(wn < last ? wn : last, ntiles, a.xcd_remap),
+                              q0, p0);
+    {
+      int q = q0, p = p0;
+      transform_store_tile<N, BL, T, LM, SM, TW, NT, E, P, SQ>(
+          ra, dst, ltw, twp, lds, a, tile_index(w, ntiles, a.xcd_remap), tid, q, p);
+    }
+    __syncthreads();  // LDS of this tile fully read before the next writes
+    w = wn;
+    if (w >= ntiles) break;
+    wn = w + G;
+    load_tile<N, T, E, P, LM, NT>(ra, src, a, tile_index(wn < last ? wn : last, ntiles, a.xcd_remap),
+                              q0, p0);
+    {
+      int q = q0, p = p0;
+      transform_store_tile<N, BL, T, LM, SM, TW, NT, E, P, SQ>(
+          rb, dst, ltw, twp, lds, a, tile_index(w, ntiles, a.xcd_remap), tid, q, p);
+    }
+    __syncthreads();
+    w = wn;
+    if (w >= ntiles) break;
+  }
+}
+
+template <int N, int T, int LM, int SM, int TW, int NT>
 hipError_t launch_pass(const PassArgs& a, const float2* src, float2* dst,
                        const float2* tw, const float2* twp, hipStream_t stream) {
   constexpr int THREADS = T * (N / Blocking<N>::E);
   const int64_t blocks = (a.B + T - 1) / T;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((fft_pass_kernel<N, T, LM, SM, TW>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((fft_pass_kernel<N, T, LM, SM, TW, NT>), dim3((unsigned)blocks),
                      dim3(THREADS), 0, stream, src, dst, tw, twp, a);
   return hipGetLastError();
 }
 
-template <int N, int T, int LM, int SM, int TW>
+int device_cu_count();
+
+template <int N, int T, int LM, int SM, int TW, int NT, class BL>
+hipError_t launch_persistent(const PassArgs& a, const float2* src, float2* dst,
+                             const float2* tw, const float2* twp, hipStream_t stream) {
+  constexpr int THREADS = T * (N / BL::E);
+  const int64_t tiles = (a.B + T - 1) / T;
+  if (tiles <= 0) return hipSuccess;
+  static int per_cu = -1;  // resident workgroups per CU for this kernel
+  if (per_cu < 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, fft_pass_persistent<N, T, LM, SM, TW, NT, BL>, THREADS, 0) != hipSuccess)
+      return hipGetLastError();
+    per_cu = nb > 0 ? nb : 1;
+  }
+  int64_t grid = (int64_t)device_cu_count() * per_cu;
+  if (grid > tiles) grid = tiles;
+  hipLaunchKernelGGL((fft_pass_persistent<N, T, LM, SM, TW, NT, BL>), dim3((unsigned)grid),
+                     dim3(THREADS), 0, stream, src, dst, tw, twp, a);
+  return hipGetLastError();
+}
+
+template <int N, int T, int LM, int SM, int TW, int NT, class BL>
+KernelInfo kernel_info_persistent() {
+  constexpr int E = BL::E;
+  constexpr int SQ = lds_pencil_stride<N, T>();
+  constexpr int LDS = (T * SQ + N) * 8;
+  static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
+  return KernelInfo{N, T, LM, SM, TW, T * (N / E), LDS,
+                    &launch_persistent<N, T, LM, SM, TW, NT, BL>, 1, NT};
+}
+
+template <int N, int T, int LM, int SM, int TW, int NT>
 KernelInfo kernel_info() {
   constexpr int E = Blocking<N>::E;
   constexpr int SQ = lds_pencil_stride<N, T>();
-  constexpr int LDS = num_stages<N>() > 1 ? T * SQ * 8 : 8;
+  constexpr int LDS = num_stages<Blocking<N>>() > 1 ? T * SQ * 8 : 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(T * (N / E) <= 1024, "workgroup too large");
-  return KernelInfo{N, T, LM, SM, TW, T * (N / E), LDS, &launch_pass<N, T, LM, SM, TW>};
+  return KernelInfo{N, T, LM, SM, TW, T * (N / E), LDS, &launch_pass<N, T, LM, SM, TW, NT>, 0,
+                    NT};
 }
 
 // All four layout combinations used by the schedules for one (N, T):
@@ -225,12 +375,25 @@ KernelInfo kernel_info() {
 //   ROW->ROW  contiguous axis in place (slab rows);
 //   COL->COL  strided axis in place (slab columns, four-step halves);
 //   COL->COL with the four-step twiddle (first half of a split axis).
+template <int N, int T, int NT>
+void add_kernels_nt(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info<N, T, MODE_ROW, MODE_COL, 0, NT>());
+  v.push_back(kernel_info<N, T, MODE_ROW, MODE_ROW, 0, NT>());
+  v.push_back(kernel_info<N, T, MODE_COL, MODE_COL, 0, NT>());
+  v.push_back(kernel_info<N, T, MODE_COL, MODE_COL, 1, NT>());
+}
 template <int N, int T>
 void add_kernels(std::vector<KernelInfo>& v) {
-  v.push_back(kernel_info<N, T, MODE_ROW, MODE_COL, 0>());
-  v.push_back(kernel_info<N, T, MODE_ROW, MODE_ROW, 0>());
-  v.push_back(kernel_info<N, T, MODE_COL, MODE_COL, 0>());
-  v.push_back(kernel_info<N, T, MODE_COL, MODE_COL, 1>());
+  add_kernels_nt<N, T, 0>(v);
+  add_kernels_nt<N, T, 1>(v);
+}
+
+// Persistent forms stream through HBM by design: non-temporal accesses only.
+template <int N, int T, class BL = Blocking<N>>
+void add_persistent_kernels(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_COL, 0, 1, BL>());
+  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_ROW, 0, 1, BL>());
+  v.push_back(kernel_info_persistent<N, T, MODE_COL, MODE_COL, 0, 1, BL>());
 }
 
 }  // namespace dft3d

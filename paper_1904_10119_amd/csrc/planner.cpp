@@ -50,14 +50,43 @@ int default_tile(int n) {
   }
 }
 
-const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options& opt) {
-  if (opt.tile > 0) {
-    if (const KernelInfo* k = find_kernel(n, opt.tile, lmode, smode, tw)) return k;
+// Arrays at least this large stream through HBM on every pass; below it the
+// data may stay in the 256 MB Infinity Cache between passes.
+constexpr int64_t kStreamBytes = int64_t(256) << 20;
+
+// Kernel choice for one pass.  Measured on MI355X at 1024^3: the persistent
+// prefetching kernels run best with streaming (non-temporal) accesses, the
+// one-tile-per-workgroup kernels with ordinary ones.  Automatic mode uses
+// the persistent form with streaming accesses for arrays that cannot stay
+// in the caches, and the one-tile form with ordinary accesses otherwise.
+const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options& opt,
+                              int64_t total_points) {
+  struct Choice {
+    int pers, nt;
+  };
+  Choice order[2];
+  int nchoice = 0;
+  if (opt.nontemporal == 2) {
+    if (opt.persistent && total_points * 8 >= kStreamBytes) order[nchoice++] = {1, 1};
+    order[nchoice++] = {0, 0};
+  } else {
+    if (opt.persistent) order[nchoice++] = {1, opt.nontemporal};
+    order[nchoice++] = {0, opt.nontemporal};
   }
-  if (const KernelInfo* k = find_kernel(n, default_tile(n), lmode, smode, tw)) return k;
+  for (int c = 0; c < nchoice; ++c) {
+    const int pers = order[c].pers, nt = order[c].nt;
+    if (opt.tile > 0) {
+      if (const KernelInfo* k = find_kernel(n, opt.tile, lmode, smode, tw, pers, nt)) return k;
+    }
+    if (const KernelInfo* k = find_kernel(n, default_tile(n), lmode, smode, tw, pers, nt))
+      return k;
+  }
   // any available tile for this length
+  const int nt = order[nchoice - 1].nt;
   for (const KernelInfo& k : kernel_registry())
-    if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw) return &k;
+    if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw &&
+        k.persistent == 0 && k.nontemporal == nt)
+      return &k;
   return nullptr;
 }
 
@@ -87,12 +116,13 @@ void set_fields(PassArgs& a, const Field* f, int nf) {
 struct Builder {
   const Options& opt;
   std::vector<Pass>& passes;
+  int64_t total_points;
   int status = DFT3D_OK;
 
   void add(int n, int lmode, int smode, int tw, const Field* f, int nf, int64_t ijs,
            int64_t oks, int64_t twp_len, int res_shift, int64_t res_mask,
            const std::string& label) {
-    const KernelInfo* k = pick_kernel(n, lmode, smode, tw, opt);
+    const KernelInfo* k = pick_kernel(n, lmode, smode, tw, opt, total_points);
     if (!k) {
       status = DFT3D_ERR_UNSUPPORTED_SIZE;
       return;
@@ -211,7 +241,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
   if (opt.precision != DFT3D_PREC_FP32) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
 
   const int64_t total = n[0] * n[1] * n[2];
-  Builder b{opt, passes};
+  Builder b{opt, passes, total};
   resolved = schedule;
   if (schedule == DFT3D_SCHED_AUTO) resolved = DFT3D_SCHED_PENCIL;
   const int64_t split_max =
@@ -296,7 +326,9 @@ std::string describe_passes(const int64_t n[3], int schedule,
     os << "{\"label\":\"" << p.label << "\",\"n\":" << p.k->n << ",\"tile\":" << p.k->tile
        << ",\"load\":\"" << (p.k->lmode == MODE_ROW ? "row" : "col") << "\",\"store\":\""
        << (p.k->smode == MODE_ROW ? "row" : "col") << "\",\"post_twiddle\":"
-       << p.k->post_twiddle << ",\"threads\":" << p.k->threads
+       << p.k->post_twiddle << ",\"persistent\":" << p.k->persistent
+       << ",\"nontemporal\":" << p.k->nontemporal
+       << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""
        << ",\"args\":{\"B\":" << p.args.B << ",\"m0\":" << p.args.m0

@@ -20,12 +20,29 @@ const std::vector<KernelInfo>& kernel_registry() {
   return table;
 }
 
-const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle) {
+const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle,
+                              int persistent, int nontemporal) {
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
-        k.post_twiddle == post_twiddle)
+        k.post_twiddle == post_twiddle && k.persistent == persistent &&
+        k.nontemporal == nontemporal)
       return &k;
   return nullptr;
+}
+
+int device_cu_count() {
+  // One entry per device; CU counts do not change while the process runs.
+  static int counts[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (counts[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    counts[dev] = n;
+  }
+  return counts[dev];
 }
 
 }  // namespace dft3d

@@ -17,7 +17,8 @@ SCHEDULES = {"auto": 0, "slab": 1, "pencil": 2, "volumetric": 3}
 LAYOUTS = {"natural": 0, "shuffled": 1}
 PRECISIONS = {"fp32": 0, "bf16x1": 1, "fp16x1": 2, "bf16x6": 3, "bf16x9": 4,
               "fp16x3": 5}
-OPT_PRECISION, OPT_TILE, OPT_XCD_REMAP, OPT_SPLIT_MAX = 1, 2, 3, 4
+OPT_PRECISION, OPT_TILE, OPT_XCD_REMAP, OPT_SPLIT_MAX, OPT_NONTEMPORAL = 1, 2, 3, 4, 5
+OPT_PERSISTENT = 6
 OPT_NUM_PASSES = 100
 
 OK = 0
@@ -103,7 +104,8 @@ class Plan:
 
     def __init__(self, shape: Sequence[int], schedule: str = "auto",
                  layout: str = "natural", precision: str = "fp32",
-                 tile: int = 0, split_max: int = 0, xcd_remap: int = 1):
+                 tile: int = 0, split_max: int = 0, xcd_remap: int = 1,
+                 nontemporal: int = -1, persistent: int = -1):
         self.shape = tuple(int(s) for s in shape)
         self.schedule = schedule
         h = ctypes.c_void_p()
@@ -121,6 +123,10 @@ class Plan:
                 self.set_option(OPT_SPLIT_MAX, split_max)
             if xcd_remap != 1:
                 self.set_option(OPT_XCD_REMAP, xcd_remap)
+            if nontemporal >= 0:
+                self.set_option(OPT_NONTEMPORAL, nontemporal)
+            if persistent >= 0:
+                self.set_option(OPT_PERSISTENT, persistent)
         except Exception:
             self.close()
             raise

@@ -153,3 +153,26 @@ def test_execute_rejects_aliasing_and_bad_sign():
     assert L.dft3d_set_workspace(p.handle, ws.data_ptr(), 16) == \
         dft3d.ERR_WORKSPACE_TOO_SMALL
     p.close()
+
+
+@pytest.mark.parametrize("shape", [(1024, 16, 512), (512, 1024, 8), (64, 1024, 64)])
+@pytest.mark.parametrize("schedule", ["pencil", "slab"])
+def test_persistent_matches_one_tile_per_workgroup(shape, schedule):
+    """The persistent prefetching kernels and the one-tile-per-workgroup
+    kernels both meet the oracle tolerance and agree with each other (the
+    compiler may contract the same butterflies differently, so they are not
+    compared bit for bit)."""
+    x = inputs.uniform_c64(shape, 26)
+    xt = torch.from_numpy(x).cuda()
+    outs = []
+    for pers in (0, 1):
+        p = dft3d.Plan(shape, schedule, persistent=pers)
+        y = torch.empty_like(xt)
+        p.execute(xt, y)
+        torch.cuda.synchronize()
+        outs.append(y.cpu().numpy())
+        p.close()
+    ref = ref_fftn(x, -1)
+    for o in outs:
+        assert oracle.rel_l2(o, ref) <= oracle.tol(x.size)
+    assert oracle.rel_l2(outs[0], outs[1]) <= oracle.tol(x.size)
