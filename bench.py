@@ -8,8 +8,11 @@ plan's schedule (default: auto).  value = 5 N log2 N / step time in GFLOP/s.
 The JSON line also carries:
   roofline      the pass kernel (every pass reads and writes the whole
                 array: 16 N algorithmic bytes per launch) against 8 TB/s;
-                its average launch time is measured with HIP events on the
-                launch stream over the timed region;
+                its average launch time is the step time (HIP events on the
+                launch stream over the timed region) over the passes per
+                step; traffic is the HBM bytes per launch from the rocprofv3
+                byte counters recorded in profiles/ (null once the kernel
+                source differs from the one profiled);
   cpu_baseline  the FP64 oracle (recursive radix-2 FFT, all host threads)
                 timed on a bounded sample of the same pencils;
   schedules     (with --breakdown) forward and inverse time of every
@@ -52,24 +55,48 @@ def time_plan(plan, x, out, steps, warmup, inverse=False):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(x_host, frac_den=4):
-    """The oracle (O2, FP64) on 1/frac_den of the pencils of every axis."""
+def cpu_baseline(x_host, budget_s=25.0, chunk=32768):
+    """The oracle (O2, FP64, all host threads) on the pencils of every axis
+    of the same input, in chunks, until all are done or the time budget is
+    spent; GFLOP/s over the pencils it finished (5 n log2 n per pencil)."""
     import oracle
     n0, n1, n2 = x_host.shape
     flops = 0.0
     t = 0.0
-    parts = []
+    done = []
     for axis, n in ((2, n2), (1, n1), (0, n0)):
-        count = max(1, x_host.size // n // frac_den)
-        t0 = time.perf_counter()
-        oracle.fft_pencils(x_host, axis, 0, count, -1)
-        t += time.perf_counter() - t0
-        flops += 5.0 * n * math.log2(n) * count
-        parts.append(f"{count} pencils of length {n} along axis {axis}")
+        total = x_host.size // n
+        first = 0
+        while first < total and t < budget_s:
+            count = min(chunk, total - first)
+            t0 = time.perf_counter()
+            oracle.fft_pencils(x_host, axis, first, count, -1)
+            t += time.perf_counter() - t0
+            flops += 5.0 * n * math.log2(n) * count
+            first += count
+        done.append(f"{first}/{total} pencils of length {n} along axis {axis}")
     return {"value": round(flops / t / 1e9, 3), "unit": "GFLOP/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "O2 radix-2 FP64 on " + ", ".join(parts) +
-                      f" of the same input ({t:.1f} s)"}
+            "sample": "O2 recursive radix-2 FFT in FP64 on " + "; ".join(done) +
+                      f" of the benchmark input ({t:.1f} s)"}
+
+
+def traffic_from_profile(path):
+    """HBM bytes per launch of the pass kernel recorded in a profiles/
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = dict(l.split(": ", 1) for l in text.splitlines()
+                  if l.startswith(("traffic_bytes_per_launch: ",
+                                   "kernel_source_sha256_16: ")))
+    src = b"".join(open(os.path.join(ROOT, "paper_1904_10119_amd", "csrc", f),
+                        "rb").read() for f in ("pass_kernel.h", "fft_device.h"))
+    if hashlib.sha256(src).hexdigest()[:16] != fields.get("kernel_source_sha256_16"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def main():
@@ -112,6 +139,10 @@ def main():
 
     per_launch_ms = ms / npass
     achieved = 16.0 * N / (per_launch_ms * 1e-3) / 1e9
+    traffic = None
+    if shape == (1024, 1024, 1024) and desc["schedule"] == "pencil":
+        traffic = traffic_from_profile(
+            os.path.join(ROOT, "profiles", "pencil_pass1024_1024cubed.md"))
     result = {
         "metric": METRIC,
         "value": round(flops / (ms * 1e-3) / 1e9, 2),
@@ -131,7 +162,7 @@ def main():
         "hbm_gbs_per_step": round(16.0 * N * npass / (ms * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": desc["passes"][0]["label"],
                      "bytes_per_launch": 16 * N,
                      "avg_launch_ms": round(per_launch_ms, 4)},

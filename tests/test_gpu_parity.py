@@ -176,3 +176,45 @@ def test_persistent_matches_one_tile_per_workgroup(shape, schedule):
     for o in outs:
         assert oracle.rel_l2(o, ref) <= oracle.tol(x.size)
     assert oracle.rel_l2(outs[0], outs[1]) <= oracle.tol(x.size)
+
+
+def full_size_check(shape, schedule, seed, nsamp=12):
+    """Full-size transform in the launch configuration bench.py times:
+    sampled output pencils y[k0, k1, :] against the oracle's direct sums,
+    Parseval over the whole array, and the inverse round trip."""
+    say("case full size", shape, schedule)
+    x = inputs.uniform_c64(shape, seed)
+    xt = torch.from_numpy(x).cuda()
+    y = dft3d.fftn(xt, schedule=schedule)
+    torch.cuda.synchronize()
+    N = x.size
+    g = np.random.default_rng(seed)
+    k0 = np.concatenate([[0, shape[0] - 1], g.integers(0, shape[0], nsamp - 2)])
+    k1 = np.concatenate([[0, shape[1] // 2], g.integers(0, shape[1], nsamp - 2)])
+    got = y[torch.from_numpy(k0).cuda(), torch.from_numpy(k1).cuda(), :].cpu().numpy()
+    ref = oracle.sample_pencils(x, k0, k1, -1)
+    err = oracle.rel_l2(got, ref)
+    say("  sampled pencils rel_l2", err)
+    assert err <= oracle.tol(N)
+    # Parseval: sum |y|^2 = N sum |x|^2 (float64 sums on the device)
+    ex = torch.sum(torch.view_as_real(xt).double() ** 2).item()
+    ey = torch.sum(torch.view_as_real(y).double() ** 2).item()
+    assert abs(ey / (N * ex) - 1.0) <= 2 * oracle.tol(N)
+    # round trip: inverse(forward(x)) / N == x
+    back = dft3d.fftn(y, schedule=schedule, inverse=True)
+    d = torch.view_as_real(back).double() / N - torch.view_as_real(xt).double()
+    rt = (torch.linalg.vector_norm(d) /
+          torch.linalg.vector_norm(torch.view_as_real(xt).double())).item()
+    say("  round trip rel_l2", rt)
+    assert rt <= 2 * oracle.tol(N)
+    del xt, y, back, d
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("schedule", ["auto", "pencil", "slab", "volumetric"])
+def test_full_1024_cubed(schedule):
+    full_size_check((1024, 1024, 1024), schedule, 2)
+
+
+def test_full_2048x1024x512():
+    full_size_check((2048, 1024, 512), "auto", 5)
