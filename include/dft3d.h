@@ -98,6 +98,8 @@ enum dft3d_option {
                                 or more, off otherwise */
   DFT3D_OPT_PERSISTENT = 6,  /* 1 = persistent prefetching pass kernels
                                 where compiled (default 1) */
+  DFT3D_OPT_SLAB_GROUP = 7,  /* slab: planes per row/column group, 0 = all
+                                planes, -1 = automatic (default) */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 
@@ -113,12 +115,15 @@ const char* dft3d_status_string(int status);
 int dft3d_plan(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
                dft3d_plan_t* out);
 
-/* Describe the pass list a plan would use, without touching any device:
- * writes a NUL-terminated JSON text into buf (at most len bytes, truncated
- * if needed) and stores the full length in *needed (may be NULL).  Same
- * argument validation as dft3d_plan. */
+/* Describe the pass list a plan with the given options would use, without
+ * touching any device: keys[i] / values[i] (nopts pairs, as for
+ * dft3d_plan_set_option; both may be NULL when nopts == 0) are applied to the
+ * default options, then a NUL-terminated JSON text is written into buf (at
+ * most len bytes, truncated if needed) and the full length is stored in
+ * *needed (may be NULL).  Same argument validation as dft3d_plan. */
 int dft3d_plan_describe(int64_t n0, int64_t n1, int64_t n2, int schedule,
-                        int layout, char* buf, size_t len, size_t* needed);
+                        int layout, const int* keys, const int64_t* values,
+                        int nopts, char* buf, size_t len, size_t* needed);
 
 int dft3d_plan_set_option(dft3d_plan_t plan, int key, int64_t value);
 int dft3d_plan_get_option(dft3d_plan_t plan, int key, int64_t* value);
@@ -142,12 +147,16 @@ int dft3d_set_workspace(dft3d_plan_t plan, void* dev_ptr, size_t bytes);
 int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
                   void* stream);
 
-/* Enqueue `count` transforms of possibly different shapes as one persistent
- * launch captured in a HIP graph.  plans[i] describes problem i, in[i] and
- * out[i] are its device buffers (same rules as dft3d_execute).  The first
- * call for a given sequence of plans captures the graph; later calls with
- * the same plans replay it after refreshing the pointer descriptors.
- * count == 0 is a no-op.  Plans must use the NATURAL layout and FP32. */
+/* Enqueue `count` transforms of possibly different shapes together: one
+ * kernel launch per pass level covers the tiles of every problem at that
+ * level.  plans[i] describes problem i (the same plan may appear more than
+ * once), in[i] and out[i] are its device buffers (same rules as
+ * dft3d_execute; distinct problems must not share buffers).  The first call
+ * for a given sequence of plans builds the work descriptors (and workspaces
+ * for repeated plans); later calls with the same sequence only refresh the
+ * buffer pointers.  Plans whose passes exceed length 256 run one after
+ * another.  count == 0 is a no-op.  Plans must use the NATURAL layout and
+ * FP32.  Not thread-safe for concurrent calls with overlapping plans. */
 int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
                           void* const* out, int count, int sign, void* stream);
 

@@ -11,22 +11,6 @@
 
 using namespace dft3d;
 
-struct dft3d_plan_s {
-  int64_t n[3] = {0, 0, 0};
-  int schedule = 0;
-  int resolved = 0;
-  int layout = 0;
-  Options opt;
-  std::vector<Pass> passes;
-  std::vector<int64_t> tw_off, twp_off;  // per pass, element offsets in tables
-  int device = -1;
-  float2* tables = nullptr;
-  size_t ws_need = 0;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  bool ws_owned = false;
-};
-
 namespace {
 
 // Test hook: DFT3D_FAULT_INJECT=alloc|upload|launch forces that step to
@@ -104,6 +88,7 @@ int rebuild(dft3d_plan_s* p) {
     p->twp_off.push_back(ps.twp_len > 0 ? offsets[ps.twp_len] : 0);
   }
   p->resolved = resolved;
+  p->uid = next_plan_uid();
   if (ws > p->ws_need && p->ws_owned) free_workspace(p);  // regrown lazily
   p->ws_need = ws;
   return DFT3D_OK;
@@ -115,7 +100,61 @@ bool overlaps(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// Applies one option to an Options value; returns a status.
+int apply_option(Options& o, int key, int64_t value) {
+  switch (key) {
+    case DFT3D_OPT_PRECISION:
+      if (value < DFT3D_PREC_FP32 || value > DFT3D_PREC_FP16X3) return DFT3D_ERR_INVALID_ARG;
+      o.precision = (int)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_TILE:
+      if (value < 0 || value > 4096 || (value & (value - 1)) != 0) return DFT3D_ERR_INVALID_ARG;
+      o.tile = (int)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_XCD_REMAP:
+      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
+      o.xcd_remap = (int)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_SPLIT_MAX:
+      if (value < 0 || value > 4096) return DFT3D_ERR_INVALID_ARG;
+      o.split_max = (int)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_NONTEMPORAL:
+      if (value < 0 || value > 2) return DFT3D_ERR_INVALID_ARG;
+      o.nontemporal = (int)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_PERSISTENT:
+      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
+      o.persistent = (int)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_SLAB_GROUP:
+      if (value < -1 || value > 4096) return DFT3D_ERR_INVALID_ARG;
+      o.slab_group = (int)value;
+      return DFT3D_OK;
+    default:
+      return DFT3D_ERR_INVALID_ARG;
+  }
+}
+
 }  // namespace
+
+namespace dft3d {
+int ensure_workspace(dft3d_plan_s* p) {
+  if (p->ws_need > 0 && (!p->ws || p->ws_bytes < p->ws_need)) {
+    if (!p->ws_owned && p->ws) return DFT3D_ERR_WORKSPACE_TOO_SMALL;
+    free_workspace(p);
+    void* w = nullptr;
+    if (fault("alloc") || hipMalloc(&w, p->ws_need) != hipSuccess) {
+      (void)hipGetLastError();
+      return DFT3D_ERR_OUT_OF_MEMORY;
+    }
+    p->ws = w;
+    p->ws_bytes = p->ws_need;
+    p->ws_owned = true;
+  }
+  return DFT3D_OK;
+}
+}  // namespace dft3d
 
 extern "C" {
 
@@ -134,14 +173,21 @@ const char* dft3d_status_string(int status) {
 }
 
 int dft3d_plan_describe(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
-                        char* buf, size_t len, size_t* needed) {
+                        const int* keys, const int64_t* values, int nopts, char* buf,
+                        size_t len, size_t* needed) {
   int st = validate(n0, n1, n2, schedule, layout);
   if (st != DFT3D_OK) return st;
+  if (nopts < 0 || (nopts > 0 && (!keys || !values))) return DFT3D_ERR_INVALID_ARG;
+  Options opt;
+  for (int i = 0; i < nopts; ++i) {
+    st = apply_option(opt, keys[i], values[i]);
+    if (st != DFT3D_OK) return st;
+  }
   const int64_t n[3] = {n0, n1, n2};
   std::vector<Pass> passes;
   size_t ws = 0;
   int resolved = 0;
-  st = build_passes(n, schedule, layout, Options{}, passes, ws, resolved);
+  st = build_passes(n, schedule, layout, opt, passes, ws, resolved);
   if (st != DFT3D_OK) return st;
   const std::string s = describe_passes(n, resolved, passes, ws);
   if (needed) *needed = s.size() + 1;
@@ -189,35 +235,9 @@ int dft3d_plan(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
 int dft3d_plan_set_option(dft3d_plan_t p, int key, int64_t value) {
   if (!p) return DFT3D_ERR_INVALID_ARG;
   Options saved = p->opt;
-  switch (key) {
-    case DFT3D_OPT_PRECISION:
-      if (value < DFT3D_PREC_FP32 || value > DFT3D_PREC_FP16X3) return DFT3D_ERR_INVALID_ARG;
-      p->opt.precision = (int)value;
-      break;
-    case DFT3D_OPT_TILE:
-      if (value < 0 || value > 4096 || (value & (value - 1)) != 0) return DFT3D_ERR_INVALID_ARG;
-      p->opt.tile = (int)value;
-      break;
-    case DFT3D_OPT_XCD_REMAP:
-      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
-      p->opt.xcd_remap = (int)value;
-      break;
-    case DFT3D_OPT_SPLIT_MAX:
-      if (value < 0 || value > 4096) return DFT3D_ERR_INVALID_ARG;
-      p->opt.split_max = (int)value;
-      break;
-    case DFT3D_OPT_NONTEMPORAL:
-      if (value < 0 || value > 2) return DFT3D_ERR_INVALID_ARG;
-      p->opt.nontemporal = (int)value;
-      break;
-    case DFT3D_OPT_PERSISTENT:
-      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
-      p->opt.persistent = (int)value;
-      break;
-    default:
-      return DFT3D_ERR_INVALID_ARG;
-  }
-  int st = rebuild(p);
+  int st = apply_option(p->opt, key, value);
+  if (st != DFT3D_OK) return st;
+  st = rebuild(p);
   if (st != DFT3D_OK) p->opt = saved;  // previous pass list stays in force
   return st;
 }
@@ -231,6 +251,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_SPLIT_MAX: *value = p->opt.split_max; break;
     case DFT3D_OPT_NONTEMPORAL: *value = p->opt.nontemporal; break;
     case DFT3D_OPT_PERSISTENT: *value = p->opt.persistent; break;
+    case DFT3D_OPT_SLAB_GROUP: *value = p->opt.slab_group; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }
@@ -260,21 +281,14 @@ int dft3d_set_workspace(dft3d_plan_t p, void* dev_ptr, size_t bytes) {
   return DFT3D_OK;
 }
 
+
 int dft3d_execute(dft3d_plan_t p, const void* in, void* out, int sign, void* stream) {
   if (!p || !in || !out || (sign != -1 && sign != 1)) return DFT3D_ERR_INVALID_ARG;
   const size_t bytes = (size_t)(p->n[0] * p->n[1] * p->n[2]) * sizeof(float2);
   if (overlaps(in, out, bytes)) return DFT3D_ERR_INVALID_ARG;
-  if (p->ws_need > 0 && (!p->ws || p->ws_bytes < p->ws_need)) {
-    if (!p->ws_owned && p->ws) return DFT3D_ERR_WORKSPACE_TOO_SMALL;
-    free_workspace(p);
-    void* w = nullptr;
-    if (fault("alloc") || hipMalloc(&w, p->ws_need) != hipSuccess) {
-      (void)hipGetLastError();
-      return DFT3D_ERR_OUT_OF_MEMORY;
-    }
-    p->ws = w;
-    p->ws_bytes = p->ws_need;
-    p->ws_owned = true;
+  {
+    const int st = ensure_workspace(p);
+    if (st != DFT3D_OK) return st;
   }
   if (p->ws_need > 0 && (overlaps(p->ws, in, bytes) || overlaps(p->ws, out, bytes)))
     return DFT3D_ERR_INVALID_ARG;
@@ -286,11 +300,14 @@ int dft3d_execute(dft3d_plan_t p, const void* in, void* out, int sign, void* str
   for (size_t i = 0; i < np; ++i) {
     const Pass& ps = p->passes[i];
     PassArgs a = ps.args;
-    a.conj_in = (sign == 1 && i == 0) ? 1 : 0;
+    // inverse as conj(DFT(conj(x))): every pass reading the input conjugates
+    // it; the last pass writes every output element and conjugates them
+    a.conj_in = (sign == 1 && ps.src == BUF_IN) ? 1 : 0;
     a.conj_out = (sign == 1 && i + 1 == np) ? 1 : 0;
     const float2* tw = p->tables + p->tw_off[i];
     const float2* twp = p->tables + p->twp_off[i];
-    hipError_t e = ps.k->launch(a, bufs[ps.src], bufs[ps.dst], tw, twp, s);
+    hipError_t e =
+        ps.k->launch(a, bufs[ps.src] + ps.in_off, bufs[ps.dst] + ps.out_off, tw, twp, s);
     if (e != hipSuccess) return DFT3D_ERR_HIP;
   }
   return DFT3D_OK;
@@ -305,16 +322,16 @@ int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
     if (!plans[i] || !in[i] || !out[i]) return DFT3D_ERR_INVALID_ARG;
     if (plans[i]->layout != DFT3D_LAYOUT_NATURAL || plans[i]->opt.precision != 0)
       return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+    const size_t bytes =
+        (size_t)(plans[i]->n[0] * plans[i]->n[1] * plans[i]->n[2]) * sizeof(float2);
+    if (overlaps(in[i], out[i], bytes)) return DFT3D_ERR_INVALID_ARG;
   }
-  for (int i = 0; i < count; ++i) {
-    int st = dft3d_execute(plans[i], in[i], out[i], sign, stream);
-    if (st != DFT3D_OK) return st;
-  }
-  return DFT3D_OK;
+  return batch_execute(plans, in, out, count, sign, static_cast<hipStream_t>(stream));
 }
 
 int dft3d_destroy(dft3d_plan_t p) {
   if (!p) return DFT3D_OK;
+  batch_forget_plan(p);
   free_workspace(p);
   free_tables(p);
   delete p;

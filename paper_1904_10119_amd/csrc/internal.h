@@ -68,6 +68,7 @@ struct Pass {
   const KernelInfo* k = nullptr;
   int src = BUF_IN, dst = BUF_OUT;
   PassArgs args{};
+  int64_t in_off = 0, out_off = 0;  // element offsets into src / dst
   int64_t tw_len = 0;   // root table of the transform length (== k->n)
   int64_t twp_len = 0;  // post-twiddle table length, 0 if none
   std::string label;
@@ -80,6 +81,7 @@ struct Options {
   int split_max = 0;   // 0: default
   int nontemporal = 2; // 0 off, 1 on, 2 on for arrays above kStreamBytes
   int persistent = 1;  // use the persistent form where one exists
+  int slab_group = -1; // slab: planes per row/column group (0 = all, -1 = auto)
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success
@@ -90,4 +92,33 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
 std::string describe_passes(const int64_t n[3], int schedule,
                             const std::vector<Pass>& passes, size_t ws_bytes);
 
+uint64_t next_plan_uid();
+
+}  // namespace dft3d
+
+// The plan behind the opaque dft3d_plan_t handle.
+struct dft3d_plan_s {
+  int64_t n[3] = {0, 0, 0};
+  int schedule = 0;
+  int resolved = 0;
+  int layout = 0;
+  dft3d::Options opt;
+  std::vector<dft3d::Pass> passes;
+  std::vector<int64_t> tw_off, twp_off;  // per pass, element offsets in tables
+  int device = -1;
+  float2* tables = nullptr;
+  size_t ws_need = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  uint64_t uid = 0;  // changes whenever the pass list is rebuilt
+};
+
+namespace dft3d {
+// Allocates the plan-owned workspace if needed (dft3d status).
+int ensure_workspace(dft3d_plan_s* p);
+// Batched execution (batch.hip) and its cache upkeep.
+int batch_execute(dft3d_plan_s* const* plans, const void* const* in,
+                  void* const* out, int count, int sign, hipStream_t stream);
+void batch_forget_plan(const dft3d_plan_s* p);
 }  // namespace dft3d

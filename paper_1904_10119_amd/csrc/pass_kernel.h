@@ -388,12 +388,16 @@ void add_kernels(std::vector<KernelInfo>& v) {
   add_kernels_nt<N, T, 1>(v);
 }
 
-// Persistent forms stream through HBM by design: non-temporal accesses only.
+template <int N, int T, int NT, class BL>
+void add_persistent_kernels_nt(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_COL, 0, NT, BL>());
+  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_ROW, 0, NT, BL>());
+  v.push_back(kernel_info_persistent<N, T, MODE_COL, MODE_COL, 0, NT, BL>());
+}
 template <int N, int T, class BL = Blocking<N>>
 void add_persistent_kernels(std::vector<KernelInfo>& v) {
-  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_COL, 0, 1, BL>());
-  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_ROW, 0, 1, BL>());
-  v.push_back(kernel_info_persistent<N, T, MODE_COL, MODE_COL, 0, 1, BL>());
+  add_persistent_kernels_nt<N, T, 0, BL>(v);
+  add_persistent_kernels_nt<N, T, 1, BL>(v);
 }
 
 }  // namespace dft3d

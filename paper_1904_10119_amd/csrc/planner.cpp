@@ -261,28 +261,42 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
     }
     assign_chain(passes, 0, need_ws);
   } else if (resolved == DFT3D_SCHED_SLAB) {
-    // rows (axis 2) IN -> OUT, then columns (axis 1) and axis 0 in place
+    // 2D DFT of every (n1, n2) plane: rows (axis 2) IN -> OUT, columns
+    // (axis 1) in place.  Planes go in groups, rows then columns per group,
+    // so that a group written by the row pass can still be in the Infinity
+    // Cache when its column pass reads it.  Then axis 0 in place.
+    const int64_t plane = n[1] * n[2];
+    int64_t group = opt.slab_group;
+    if (group < 0) group = 0;  // automatic: all planes in one pass each
+    if (group == 0 || group > n[0]) group = n[0];
+    while (n[0] % group) --group;
     char lab[64];
-    {
-      Field f[1] = {{n[0] * n[1], n[2], n[2]}};
-      std::snprintf(lab, sizeof lab, "slab.rows DFT%lld", (long long)n[2]);
-      b.add((int)n[2], MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
-    }
-    {
-      Field f[2] = {{n[2], 1, 1}, {n[0], n[1] * n[2], n[1] * n[2]}};
-      std::snprintf(lab, sizeof lab, "slab.cols DFT%lld", (long long)n[1]);
-      b.add((int)n[1], MODE_COL, MODE_COL, 0, f, 2, n[2], n[2], 0, 0, 0, lab);
-    }
-    {
-      Field f[1] = {{n[1] * n[2], 1, 1}};
-      std::snprintf(lab, sizeof lab, "slab.depth DFT%lld", (long long)n[0]);
-      b.add((int)n[0], MODE_COL, MODE_COL, 0, f, 1, n[1] * n[2], n[1] * n[2], 0, 0, 0,
-            lab);
+    for (int64_t g0 = 0; g0 < n[0]; g0 += group) {
+      {
+        Field f[1] = {{group * n[1], n[2], n[2]}};
+        std::snprintf(lab, sizeof lab, "slab.rows DFT%lld planes %lld+%lld", (long long)n[2],
+                      (long long)g0, (long long)group);
+        b.add((int)n[2], MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
+        if (b.status != DFT3D_OK) break;
+        passes.back().src = BUF_IN;
+        passes.back().dst = BUF_OUT;
+        passes.back().in_off = passes.back().out_off = g0 * plane;
+      }
+      {
+        Field f[2] = {{n[2], 1, 1}, {group, plane, plane}};
+        std::snprintf(lab, sizeof lab, "slab.cols DFT%lld planes %lld+%lld", (long long)n[1],
+                      (long long)g0, (long long)group);
+        b.add((int)n[1], MODE_COL, MODE_COL, 0, f, 2, n[2], n[2], 0, 0, 0, lab);
+        if (b.status != DFT3D_OK) break;
+        passes.back().src = passes.back().dst = BUF_OUT;
+        passes.back().in_off = passes.back().out_off = g0 * plane;
+      }
     }
     if (b.status == DFT3D_OK) {
-      passes[0].src = BUF_IN;
-      passes[0].dst = BUF_OUT;
-      for (size_t i = 1; i < passes.size(); ++i) passes[i].src = passes[i].dst = BUF_OUT;
+      Field f[1] = {{plane, 1, 1}};
+      std::snprintf(lab, sizeof lab, "slab.depth DFT%lld", (long long)n[0]);
+      b.add((int)n[0], MODE_COL, MODE_COL, 0, f, 1, plane, plane, 0, 0, 0, lab);
+      if (b.status == DFT3D_OK) passes.back().src = passes.back().dst = BUF_OUT;
     }
   } else {  // VOLUMETRIC
     for (int axis = 2; axis >= 0; --axis) {
@@ -331,6 +345,7 @@ std::string describe_passes(const int64_t n[3], int schedule,
        << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""
+       << ",\"in_off\":" << p.in_off << ",\"out_off\":" << p.out_off
        << ",\"args\":{\"B\":" << p.args.B << ",\"m0\":" << p.args.m0
        << ",\"m1\":" << p.args.m1 << ",\"s0\":" << p.args.s0 << ",\"s1\":" << p.args.s1
        << ",\"is\":[" << p.args.is0 << "," << p.args.is1 << "," << p.args.is2 << "]"

@@ -18,7 +18,7 @@ LAYOUTS = {"natural": 0, "shuffled": 1}
 PRECISIONS = {"fp32": 0, "bf16x1": 1, "fp16x1": 2, "bf16x6": 3, "bf16x9": 4,
               "fp16x3": 5}
 OPT_PRECISION, OPT_TILE, OPT_XCD_REMAP, OPT_SPLIT_MAX, OPT_NONTEMPORAL = 1, 2, 3, 4, 5
-OPT_PERSISTENT = 6
+OPT_PERSISTENT, OPT_SLAB_GROUP = 6, 7
 OPT_NUM_PASSES = 100
 
 OK = 0
@@ -63,7 +63,8 @@ def lib():
     L.dft3d_status_string.argtypes = [ci]
     L.dft3d_status_string.restype = ctypes.c_char_p
     L.dft3d_plan.argtypes = [i64, i64, i64, ci, ci, ctypes.POINTER(vp)]
-    L.dft3d_plan_describe.argtypes = [i64, i64, i64, ci, ci, ctypes.c_char_p, sz,
+    L.dft3d_plan_describe.argtypes = [i64, i64, i64, ci, ci, ctypes.POINTER(ci),
+                                      ctypes.POINTER(i64), ci, ctypes.c_char_p, sz,
                                       ctypes.POINTER(sz)]
     L.dft3d_plan_set_option.argtypes = [vp, ci, i64]
     L.dft3d_plan_get_option.argtypes = [vp, ci, ctypes.POINTER(i64)]
@@ -84,17 +85,26 @@ def _check(st: int, what: str) -> None:
         raise Dft3dError(st, what)
 
 
+OPTION_KEYS = {"precision": OPT_PRECISION, "tile": OPT_TILE,
+               "xcd_remap": OPT_XCD_REMAP, "split_max": OPT_SPLIT_MAX,
+               "nontemporal": OPT_NONTEMPORAL, "persistent": OPT_PERSISTENT,
+               "slab_group": OPT_SLAB_GROUP}
+
+
 def describe(shape: Sequence[int], schedule: str = "auto",
-             layout: str = "natural") -> dict:
+             layout: str = "natural", **opts) -> dict:
     """Pass list the library would run for `shape` (no device needed)."""
     n0, n1, n2 = (int(s) for s in shape)
+    items = [(OPTION_KEYS[k], PRECISIONS[v] if k == "precision" else int(v))
+             for k, v in opts.items()]
+    keys = (ctypes.c_int * max(1, len(items)))(*[k for k, _ in items])
+    vals = (ctypes.c_int64 * max(1, len(items)))(*[v for _, v in items])
     need = ctypes.c_size_t(0)
     L = lib()
-    _check(L.dft3d_plan_describe(n0, n1, n2, SCHEDULES[schedule], LAYOUTS[layout],
-                                 None, 0, ctypes.byref(need)), "describe")
+    args = (n0, n1, n2, SCHEDULES[schedule], LAYOUTS[layout], keys, vals, len(items))
+    _check(L.dft3d_plan_describe(*args, None, 0, ctypes.byref(need)), "describe")
     buf = ctypes.create_string_buffer(need.value)
-    _check(L.dft3d_plan_describe(n0, n1, n2, SCHEDULES[schedule], LAYOUTS[layout],
-                                 buf, need.value, None), "describe")
+    _check(L.dft3d_plan_describe(*args, buf, need.value, None), "describe")
     return json.loads(buf.value.decode())
 
 
@@ -105,7 +115,8 @@ class Plan:
     def __init__(self, shape: Sequence[int], schedule: str = "auto",
                  layout: str = "natural", precision: str = "fp32",
                  tile: int = 0, split_max: int = 0, xcd_remap: int = 1,
-                 nontemporal: int = -1, persistent: int = -1):
+                 nontemporal: int = -1, persistent: int = -1,
+                 slab_group: int = -2):
         self.shape = tuple(int(s) for s in shape)
         self.schedule = schedule
         h = ctypes.c_void_p()
@@ -127,6 +138,8 @@ class Plan:
                 self.set_option(OPT_NONTEMPORAL, nontemporal)
             if persistent >= 0:
                 self.set_option(OPT_PERSISTENT, persistent)
+            if slab_group >= -1:
+                self.set_option(OPT_SLAB_GROUP, slab_group)
         except Exception:
             self.close()
             raise

@@ -52,8 +52,10 @@ def test_bad_enums_rejected():
     assert L.dft3d_plan(8, 8, 8, 0, 5, ctypes.byref(h)) == dft3d.ERR_INVALID_ARG
     assert L.dft3d_plan(8, 8, 8, 0, 0, None) == dft3d.ERR_INVALID_ARG
     # shuffled output is not offered by these schedules
-    assert L.dft3d_plan_describe(8, 8, 8, 2, 1, None, 0, None) == \
+    assert L.dft3d_plan_describe(8, 8, 8, 2, 1, None, None, 0, None, 0, None) == \
         dft3d.ERR_UNSUPPORTED_SCHEDULE
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((8, 8, 8), "slab", tile=3)
 
 
 def test_null_handles_rejected():

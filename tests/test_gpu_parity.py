@@ -218,3 +218,14 @@ def test_full_1024_cubed(schedule):
 
 def test_full_2048x1024x512():
     full_size_check((2048, 1024, 512), "auto", 5)
+
+
+@pytest.mark.parametrize("group", [1, 4, 16])
+def test_slab_plane_groups(group):
+    """Slab with the planes processed in groups (rows then columns per
+    group): forward and inverse against the oracle."""
+    shape = (64, 128, 64)
+    x = inputs.uniform_c64(shape, 27)
+    for sign, inv in ((-1, False), (1, True)):
+        y = gpu_fftn(x, "slab", inverse=inv, slab_group=group)
+        assert oracle.rel_l2(y, ref_fftn(x, sign)) <= oracle.tol(x.size), (group, sign)

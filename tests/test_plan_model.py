@@ -40,8 +40,8 @@ def run_model(x, d, sign):
         a = p["args"]
         ia = addresses(a, p["n"], True)
         oa = addresses(a, p["n"], False)
-        v = bufs[p["src"]][ia]
-        if sign == 1 and i == 0:
+        v = bufs[p["src"]][ia + p["in_off"]]
+        if sign == 1 and p["src"] == "in":
             v = np.conj(v)
         y = np.fft.fft(v, axis=1)
         if p["post_twiddle"]:
@@ -51,15 +51,18 @@ def run_model(x, d, sign):
             y = y * np.exp(-2j * np.pi * ((res[:, None] * k[None, :]) % L) / L)
         if sign == 1 and i == len(passes) - 1:
             y = np.conj(y)
-        bufs[p["dst"]][oa] = y
+        bufs[p["dst"]][oa + p["out_off"]] = y
     return bufs["out"].reshape(x.shape)
 
 
 @pytest.mark.parametrize("shape", SHAPES + [(1024, 1024, 1024), (2048, 1024, 512),
                                             (4096, 4096, 4)])
-@pytest.mark.parametrize("schedule", SCHEDULES)
-def test_pass_maps_are_bijections(shape, schedule):
-    d = dft3d.describe(shape, schedule)
+@pytest.mark.parametrize("schedule", SCHEDULES + ["slab-grouped"])
+def test_pass_maps_are_injective_and_in_bounds(shape, schedule):
+    if schedule == "slab-grouped":
+        d = dft3d.describe(shape, "slab", slab_group=max(1, shape[0] // 4))
+    else:
+        d = dft3d.describe(shape, schedule)
     N = shape[0] * shape[1] * shape[2]
     for p in d["passes"]:
         a = p["args"]
@@ -67,20 +70,21 @@ def test_pass_maps_are_bijections(shape, schedule):
             # sampled: the first, last and a middle block of pencils
             B = a["B"]
             for lo in (0, B // 2, B - 64):
-                sub = dict(a, B=B)
                 b = np.arange(lo, lo + 64, dtype=np.int64)
                 for inp in (True, False):
                     st = a["is"] if inp else a["os"]
                     js = a["ijs"] if inp else a["oks"]
                     base = ((b >> a["s1"]) * st[2] + ((b >> a["s0"]) & a["m1"]) * st[1]
                             + (b & a["m0"]) * st[0])
-                    hi = base.max() + (p["n"] - 1) * js
-                    assert base.min() >= 0 and hi < N, (p["label"], inp)
+                    off = p["in_off"] if inp else p["out_off"]
+                    hi = base.max() + (p["n"] - 1) * js + off
+                    assert base.min() + off >= 0 and hi < N, (p["label"], inp)
             continue
         for inp in (True, False):
-            addr = addresses(a, p["n"], inp).reshape(-1)
+            off = p["in_off"] if inp else p["out_off"]
+            addr = addresses(a, p["n"], inp).reshape(-1) + off
             assert addr.min() >= 0 and addr.max() < N, (p["label"], inp)
-            assert np.unique(addr).size == N, (p["label"], inp)
+            assert np.unique(addr).size == addr.size, (p["label"], inp)
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -93,3 +97,20 @@ def test_pass_list_computes_the_dft(shape, schedule):
         got = run_model(x, d, sign)
         ref = oracle.dft3d(x, sign, "fft")
         assert oracle.rel_l2(got, ref) < 1e-13, (shape, schedule, sign)
+
+
+OPTION_SETS = [dict(slab_group=1), dict(slab_group=2), dict(tile=8), dict(tile=64),
+               dict(split_max=4), dict(persistent=0), dict(nontemporal=1),
+               dict(xcd_remap=0)]
+
+
+@pytest.mark.parametrize("opts", OPTION_SETS)
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_pass_list_with_options(opts, schedule):
+    shape = (8, 16, 32)
+    g = np.random.default_rng(7)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    d = dft3d.describe(shape, schedule, **opts)
+    for sign in (-1, 1):
+        got = run_model(x, d, sign)
+        assert oracle.rel_l2(got, oracle.dft3d(x, sign, "fft")) < 1e-13, (opts, sign)
