@@ -54,7 +54,9 @@ int rebuild(dft3d_plan_s* p) {
   int st = build_passes(p->n, p->schedule, p->layout, p->opt, passes, ws, resolved);
   if (st != DFT3D_OK) return st;
 
-  std::map<int64_t, int64_t> offsets;  // length -> element offset
+  // one table per distinct root length (key n > 0) and per MFMA leaf
+  // precision (key -precision, kLeafTableFloat2 slots of 16-bit values)
+  std::map<int64_t, int64_t> offsets;
   int64_t total = 0;
   for (const Pass& ps : passes) {
     for (int64_t len : {ps.tw_len, ps.twp_len}) {
@@ -63,9 +65,18 @@ int rebuild(dft3d_plan_s* p) {
         total += len;
       }
     }
+    if (ps.leaf && !offsets.count(-ps.leaf)) {
+      offsets[-ps.leaf] = total;
+      total += kLeafTableFloat2;
+    }
   }
   std::vector<float2> host((size_t)total);
-  for (auto& kv : offsets) make_roots(kv.first, host.data() + kv.second);
+  for (auto& kv : offsets) {
+    if (kv.first > 0)
+      make_roots(kv.first, host.data() + kv.second);
+    else
+      make_leaf_table((int)-kv.first, reinterpret_cast<unsigned short*>(host.data() + kv.second));
+  }
 
   float2* dev = nullptr;
   if (fault("alloc") || hipMalloc(&dev, sizeof(float2) * (size_t)total) != hipSuccess) {
@@ -85,7 +96,9 @@ int rebuild(dft3d_plan_s* p) {
   p->twp_off.clear();
   for (const Pass& ps : p->passes) {
     p->tw_off.push_back(offsets[ps.tw_len]);
-    p->twp_off.push_back(ps.twp_len > 0 ? offsets[ps.twp_len] : 0);
+    // post-twiddle table, or the leaf operand table for MFMA passes
+    p->twp_off.push_back(ps.leaf ? offsets[-ps.leaf]
+                                 : (ps.twp_len > 0 ? offsets[ps.twp_len] : 0));
   }
   p->resolved = resolved;
   p->uid = next_plan_uid();

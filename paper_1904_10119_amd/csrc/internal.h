@@ -51,16 +51,24 @@ struct KernelInfo {
   LaunchFn launch;
   int persistent;    // 1: grid of resident workgroups walking all tiles
   int nontemporal;   // 1: streaming (non-temporal) loads and stores
+  int precision = 0; // DFT3D_PREC_*: FP32 butterflies or split MFMA leaves
 };
 
 // All compiled pass kernels.
 const std::vector<KernelInfo>& kernel_registry();
 const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle,
                               int persistent, int nontemporal);
+// The split-precision MFMA pass kernel for a length and layout, if any.
+const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision);
 
 // Roots w_n^m = exp(-2 pi i m / n), m < n, computed in FP64 with exact
 // octant reduction and rounded once to FP32 (eq. (4) entries).
 void make_roots(int64_t n, float2* out);
+// The same root in FP64: (cos, sin) of 2 pi m / n (before the sign).
+void root_fp64(int64_t m, int64_t n, double& c, double& s);
+// MFMA leaf operand table for a precision (kLeafTableHalves 16-bit values).
+constexpr int kLeafTableFloat2 = 3 * 2 * 64 * 8 / 4;  // as float2 slots
+void make_leaf_table(int precision, unsigned short* out);
 
 enum BufId { BUF_IN = 0, BUF_OUT = 1, BUF_WS = 2 };
 
@@ -71,6 +79,7 @@ struct Pass {
   int64_t in_off = 0, out_off = 0;  // element offsets into src / dst
   int64_t tw_len = 0;   // root table of the transform length (== k->n)
   int64_t twp_len = 0;  // post-twiddle table length, 0 if none
+  int leaf = 0;         // precision of the MFMA leaf table the pass reads, 0: none
   std::string label;
 };
 

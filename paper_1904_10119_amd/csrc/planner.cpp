@@ -122,13 +122,21 @@ struct Builder {
   void add(int n, int lmode, int smode, int tw, const Field* f, int nf, int64_t ijs,
            int64_t oks, int64_t twp_len, int res_shift, int64_t res_mask,
            const std::string& label) {
-    const KernelInfo* k = pick_kernel(n, lmode, smode, tw, opt, total_points);
+    const KernelInfo* k = nullptr;
+    int leaf = 0;
+    if (opt.precision != DFT3D_PREC_FP32 && !tw) {
+      // split-precision leaves on the matrix cores where a kernel exists
+      k = find_mfma_kernel(n, lmode, smode, opt.precision);
+      if (k) leaf = opt.precision;
+    }
+    if (!k) k = pick_kernel(n, lmode, smode, tw, opt, total_points);
     if (!k) {
       status = DFT3D_ERR_UNSUPPORTED_SIZE;
       return;
     }
     Pass p;
     p.k = k;
+    p.leaf = leaf;
     set_fields(p.args, f, nf);
     p.args.ijs = ijs;
     p.args.oks = oks;
@@ -238,7 +246,6 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
   if (layout != DFT3D_LAYOUT_NATURAL && layout != DFT3D_LAYOUT_SHUFFLED)
     return DFT3D_ERR_INVALID_ARG;
   if (layout != DFT3D_LAYOUT_NATURAL) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
-  if (opt.precision != DFT3D_PREC_FP32) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
 
   const int64_t total = n[0] * n[1] * n[2];
   Builder b{opt, passes, total};
@@ -341,7 +348,7 @@ std::string describe_passes(const int64_t n[3], int schedule,
        << ",\"load\":\"" << (p.k->lmode == MODE_ROW ? "row" : "col") << "\",\"store\":\""
        << (p.k->smode == MODE_ROW ? "row" : "col") << "\",\"post_twiddle\":"
        << p.k->post_twiddle << ",\"persistent\":" << p.k->persistent
-       << ",\"nontemporal\":" << p.k->nontemporal
+       << ",\"nontemporal\":" << p.k->nontemporal << ",\"precision\":" << p.k->precision
        << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""

@@ -7,6 +7,9 @@ void register_kernels_small(std::vector<KernelInfo>& v);
 void register_kernels_mid(std::vector<KernelInfo>& v);
 void register_kernels_1k(std::vector<KernelInfo>& v);
 void register_kernels_big(std::vector<KernelInfo>& v);
+void register_kernels_mfma_a(std::vector<KernelInfo>& v);
+void register_kernels_mfma_b(std::vector<KernelInfo>& v);
+void register_kernels_mfma_c(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -15,6 +18,9 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_mid(v);
     register_kernels_1k(v);
     register_kernels_big(v);
+    register_kernels_mfma_a(v);
+    register_kernels_mfma_b(v);
+    register_kernels_mfma_c(v);
     return v;
   }();
   return table;
@@ -25,7 +31,14 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
-        k.nontemporal == nontemporal)
+        k.nontemporal == nontemporal && k.precision == 0)
+      return &k;
+  return nullptr;
+}
+
+const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision) {
+  for (const KernelInfo& k : kernel_registry())
+    if (k.n == n && k.lmode == lmode && k.smode == smode && k.precision == precision)
       return &k;
   return nullptr;
 }

@@ -6,35 +6,99 @@
 // library's cos and sin are called only on small arguments, and 0, +-1 and
 // +-sqrt(1/2) are exact.  Each entry is rounded once to FP32.
 #include <cmath>
+#include <cstring>
 
+#include "../../include/dft3d.h"
 #include "internal.h"
 
 namespace dft3d {
 
-void make_roots(int64_t n, float2* out) {
+void root_fp64(int64_t m, int64_t n, double& c, double& s) {
   const double half_pi = 1.57079632679489661923132169163975144;
+  m %= n;
+  if (m < 0) m += n;
+  const int64_t q = (4 * m) / n;      // quarter turns
+  const int64_t rem = 4 * m - q * n;  // (pi/2) * rem / n left over
+  if (rem == 0) {
+    c = 1.0; s = 0.0;
+  } else if (2 * rem == n) {
+    c = std::sqrt(0.5); s = c;
+  } else if (2 * rem < n) {
+    const double x = half_pi * (double)rem / (double)n;
+    c = std::cos(x); s = std::sin(x);
+  } else {
+    const double x = half_pi * (double)(n - rem) / (double)n;
+    c = std::sin(x); s = std::cos(x);
+  }
+  for (int64_t k = 0; k < q; ++k) {  // times i per quarter turn
+    const double t = c;
+    c = -s;
+    s = t;
+  }
+}
+
+void make_roots(int64_t n, float2* out) {
   for (int64_t m = 0; m < n; ++m) {
-    const int64_t q = (4 * m) / n;      // quarter turns
-    const int64_t rem = 4 * m - q * n;  // (pi/2) * rem / n left over
     double c, s;
-    if (rem == 0) {
-      c = 1.0; s = 0.0;
-    } else if (2 * rem == n) {
-      c = std::sqrt(0.5); s = c;
-    } else if (2 * rem < n) {
-      const double x = half_pi * (double)rem / (double)n;
-      c = std::cos(x); s = std::sin(x);
-    } else {
-      const double x = half_pi * (double)(n - rem) / (double)n;
-      c = std::sin(x); s = std::cos(x);
-    }
-    for (int64_t k = 0; k < q; ++k) {  // times i per quarter turn
-      const double t = c;
-      c = -s;
-      s = t;
-    }
+    root_fp64(m, n, c, s);
     out[m] = make_float2((float)c, (float)(-s));
   }
+}
+
+namespace {
+
+// Round to the nearest value with `bits` significand bits (ties to even),
+// with the smallest quantum `minq` (subnormal spacing); exact in FP64.
+double round_sig(double v, int bits, double minq) {
+  if (v == 0.0) return 0.0;
+  int e;
+  std::frexp(v, &e);                      // |v| in [2^(e-1), 2^e)
+  double q = std::ldexp(1.0, e - bits);   // spacing of the format at v
+  if (q < minq) q = minq;
+  return std::nearbyint(v / q) * q;       // default rounding: ties to even
+}
+
+unsigned short bf16_bits(double v) {  // v exactly representable in bf16
+  const float f = (float)v;
+  unsigned int u;
+  std::memcpy(&u, &f, 4);
+  return (unsigned short)(u >> 16);
+}
+
+unsigned short f16_bits(double v) {  // v exactly representable in fp16
+  const _Float16 h = (_Float16)v;
+  unsigned short u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+
+}  // namespace
+
+// Lane l of the 16x16x32 MFMA holds A[l % 16][8 (l / 16) + i]; matrix 0 is
+// [Fr | -Fi], matrix 1 is [Fi | Fr] with F[m][k] = w_16^{m k} (forward).
+// Each entry is split from FP64: bf16 terms unscaled, fp16 terms scaled by
+// 2^(11 t) so that the small terms stay normal.
+void make_leaf_table(int precision, unsigned short* out) {
+  const bool fp16 = precision == DFT3D_PREC_FP16X1 || precision == DFT3D_PREC_FP16X3;
+  for (int t = 0; t < 3; ++t)
+    for (int c = 0; c < 2; ++c)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int i = 0; i < 8; ++i) {
+          const int m = lane % 16, k = 8 * (lane / 16) + i, col = k % 16;
+          double cs, sn;
+          root_fp64((int64_t)m * col, 16, cs, sn);
+          const double fr = cs, fi = -sn;  // w_16^{m col} = cos - i sin
+          double v;
+          if (c == 0) v = k < 16 ? fr : -fi;
+          else v = k < 16 ? fi : fr;
+          // peel terms 0 .. t
+          double r = v, h = 0.0;
+          for (int j = 0; j <= t; ++j) {
+            h = fp16 ? round_sig(r, 11, std::ldexp(1.0, -24)) : round_sig(r, 8, 0.0);
+            r = fp16 ? (r - h) * 2048.0 : r - h;
+          }
+          out[((t * 2 + c) * 64 + lane) * 8 + i] = fp16 ? f16_bits(h) : bf16_bits(h);
+        }
 }
 
 }  // namespace dft3d

@@ -132,3 +132,14 @@ def test_volumetric_splits_every_axis():
 def test_auto_splits_long_axes():
     d = dft3d.describe((2048, 1024, 512), "auto")
     assert [p["n"] for p in d["passes"]] == [512, 1024, 32, 64]
+
+
+def test_split_precision_uses_mfma_leaves_where_available():
+    d = dft3d.describe((256, 256, 256), "pencil", precision="bf16x6")
+    assert all(p["precision"] == dft3d.PRECISIONS["bf16x6"] for p in d["passes"])
+    # lengths below 16 have no MFMA leaf and stay on FP32 butterflies
+    d = dft3d.describe((8, 256, 4), "pencil", precision="bf16x9")
+    assert [p["precision"] for p in d["passes"]] == [0, dft3d.PRECISIONS["bf16x9"], 0]
+    # four-step first halves (post twiddle) stay FP32
+    d = dft3d.describe((2048, 1024, 512), "auto", precision="fp16x3")
+    assert [p["precision"] > 0 for p in d["passes"]] == [True, True, False, True]

@@ -101,7 +101,7 @@ def test_pass_list_computes_the_dft(shape, schedule):
 
 OPTION_SETS = [dict(slab_group=1), dict(slab_group=2), dict(tile=8), dict(tile=64),
                dict(split_max=4), dict(persistent=0), dict(nontemporal=1),
-               dict(xcd_remap=0)]
+               dict(xcd_remap=0), dict(precision="bf16x6"), dict(precision="fp16x3")]
 
 
 @pytest.mark.parametrize("opts", OPTION_SETS)
