@@ -15,8 +15,11 @@ The JSON line also carries:
                 source differs from the one profiled);
   cpu_baseline  the FP64 oracle (recursive radix-2 FFT, all host threads)
                 timed on a bounded sample of the same pencils;
-  schedules     (with --breakdown) forward and inverse time of every
-                schedule.
+  configs       (unless --no-extras) the other workloads: 64^3 forward and
+                inverse (latency), every schedule at 1024^3, every leaf
+                precision at 256^3 and 1024^3, 96 uneven problems batched
+                per pass level against one plan at a time, and
+                2048 x 1024 x 512 auto vs pencil, FP32 vs bf16x6 leaves.
 """
 import argparse
 import json
@@ -99,6 +102,138 @@ def traffic_from_profile(path):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def timed(fn, reps, warm=2):
+    """Average ms of fn() over reps runs (HIP events on the current stream)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extras(x1024_host, args):
+    """The other workloads, each timed on the GPU (no accuracy checks here:
+    the tests carry those)."""
+    import torch
+    from paper_1904_10119_amd import dft3d, inputs
+    out = {}
+
+    def plan_ms(shape, x, y, reps, inverse=False, **kw):
+        p = dft3d.Plan(shape, **kw)
+        ms = timed(lambda: p.execute(x, y, inverse=inverse), reps)
+        n = p.num_passes
+        p.close()
+        return ms, n
+
+    # 64^3, pencil, forward and inverse: latency-bound (2 MiB)
+    shape = (64, 64, 64)
+    x = torch.from_numpy(inputs.uniform_c64(shape, 1)).cuda()
+    y = torch.empty_like(x)
+    f, _ = plan_ms(shape, x, y, 200, schedule="pencil")
+    i, _ = plan_ms(shape, x, y, 200, inverse=True, schedule="pencil")
+    out["64^3 pencil"] = {"fwd_us": round(f * 1e3, 2), "inv_us": round(i * 1e3, 2)}
+    log(f"bench: 64^3 {out['64^3 pencil']}")
+
+    # 1024^3 under every schedule
+    N = 1 << 30
+    fl = 5.0 * N * 30
+    x = torch.from_numpy(x1024_host).cuda()
+    y = torch.empty_like(x)
+    sched = {}
+    for s in ("pencil", "slab", "volumetric"):
+        f, n = plan_ms((1024,) * 3, x, y, 5, schedule=s)
+        i, _ = plan_ms((1024,) * 3, x, y, 5, inverse=True, schedule=s)
+        sched[s] = {"passes": n, "fwd_ms": round(f, 3), "inv_ms": round(i, 3),
+                    "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1),
+                    "hbm_gbs_per_pass": round(16.0 * N / (f / n * 1e-3) / 1e9, 1)}
+        log(f"bench: 1024^3 {s} {sched[s]}")
+    out["1024^3 schedules"] = sched
+    prec = {}
+    for pr in ("fp32", "bf16x6", "bf16x9", "fp16x3"):
+        f, _ = plan_ms((1024,) * 3, x, y, 3, schedule="pencil", precision=pr)
+        prec[pr] = {"fwd_ms": round(f, 3), "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1)}
+    out["1024^3 pencil leaf precision"] = prec
+    log(f"bench: 1024^3 precisions {prec}")
+    del x, y
+    torch.cuda.empty_cache()
+
+    # 256^3, Gaussian + 8 plane waves, every leaf precision
+    shape = (256, 256, 256)
+    N = 1 << 24
+    xh, _, _ = inputs.gaussian_waves_c64(shape, 3)
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty_like(x)
+    prec = {}
+    for pr in ("fp32", "bf16x1", "fp16x1", "bf16x6", "bf16x9", "fp16x3"):
+        f, _ = plan_ms(shape, x, y, 20, schedule="pencil", precision=pr)
+        prec[pr] = {"fwd_ms": round(f, 4),
+                    "fwd_gflops": round(5.0 * N * 24 / (f * 1e-3) / 1e9, 1)}
+    out["256^3 pencil leaf precision"] = prec
+    log(f"bench: 256^3 precisions {prec}")
+    del x, y
+    torch.cuda.empty_cache()
+
+    # 96 uneven problems: batched per pass level vs one plan at a time
+    shapes = inputs.batch_shapes(96, 104)
+    xs = [torch.from_numpy(inputs.uniform_c64(sh, 400 + k)).cuda()
+          for k, sh in enumerate(shapes)]
+    ys = [torch.empty_like(v) for v in xs]
+    pts = sum(v.numel() for v in xs)
+    flops = sum(5.0 * v.numel() * math.log2(v.numel()) for v in xs)
+    b_ms = timed(lambda: dft3d.fftn_batched(xs, outs=ys), 20)
+    plans = [dft3d.get_plan(v.shape, "auto") for v in xs]
+    for p, v in zip(plans, xs):
+        p.bind_workspace(v.device)
+    l_ms = timed(lambda: [p.execute(v, w) for p, v, w in zip(plans, xs, ys)], 20)
+    loop_launches = sum(p.num_passes for p in plans)
+    del plans
+    # autotune every distinct shape, then the batch again with tuned plans
+    tuned = {}
+    for sh in sorted(set(shapes)):
+        tuned["x".join(map(str, sh))] = dft3d.autotune(sh)["schedule"]
+    t_ms = timed(lambda: dft3d.fftn_batched(xs, outs=ys), 20)
+    out["batched 96 {32,64,128}^3"] = {
+        "points": pts, "batched_ms": round(b_ms, 4), "plan_loop_ms": round(l_ms, 4),
+        "batched_gflops": round(flops / (b_ms * 1e-3) / 1e9, 1),
+        "autotuned_batched_ms": round(t_ms, 4),
+        "autotuned_schedules": sorted(set(tuned.values())),
+        "launches_batched": 3, "launches_loop": loop_launches}
+    log(f"bench: batched {out['batched 96 {32,64,128}^3']}")
+    del xs, ys
+    torch.cuda.empty_cache()
+
+    # 2048 x 1024 x 512: auto vs fixed pencil, FP32 vs bf16x6 leaves
+    shape = (2048, 1024, 512)
+    N = 1 << 30
+    x = torch.from_numpy(inputs.uniform_c64(shape, 5)).cuda()
+    y = torch.empty_like(x)
+    r = {}
+    runs = [("auto untuned", dict(schedule="auto")), ("pencil", dict(schedule="pencil")),
+            ("auto bf16x6", dict(schedule="auto", precision="bf16x6"))]
+    for name, kw in runs:
+        f, n = plan_ms(shape, x, y, 3, **kw)
+        i, _ = plan_ms(shape, x, y, 3, inverse=True, **kw)
+        r[name] = {"passes": n, "fwd_ms": round(f, 3), "inv_ms": round(i, 3),
+                   "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1)}
+    r["autotune"] = dft3d.autotune(shape)
+    f, n = plan_ms(shape, x, y, 3, schedule="auto")
+    r["auto tuned"] = {"passes": n, "fwd_ms": round(f, 3),
+                       "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1)}
+    out["2048x1024x512"] = r
+    log(f"bench: 2048x1024x512 {r}")
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +242,9 @@ def main():
     ap.add_argument("--shape", default="1024,1024,1024")
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--breakdown", action="store_true",
-                    help="also time every schedule forward and inverse")
+                    help="(kept for compatibility; the extras include it)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the 1024^3 headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of the array (the "
@@ -167,20 +304,6 @@ def main():
                      "bytes_per_launch": 16 * N,
                      "avg_launch_ms": round(per_launch_ms, 4)},
     }
-    if args.breakdown:
-        sched = {}
-        for s in ("pencil", "slab", "volumetric", "auto"):
-            p = dft3d.Plan(shape, s)
-            f_ms, _ = time_plan(p, x, out, max(3, args.steps // 2), 2)
-            i_ms, _ = time_plan(p, x, out, max(3, args.steps // 2), 2, inverse=True)
-            sched[s] = {"passes": p.num_passes, "fwd_ms": round(f_ms, 4),
-                        "inv_ms": round(i_ms, 4),
-                        "fwd_gflops": round(flops / (f_ms * 1e-3) / 1e9, 1),
-                        "fwd_gbs_per_pass": round(
-                            16.0 * N / (f_ms / p.num_passes * 1e-3) / 1e9, 1)}
-            log(f"bench: {s}: {sched[s]}")
-            p.close()
-        result["schedules"] = sched
     if args.copy_calibration:
         for _ in range(2):
             out.copy_(x)
@@ -200,6 +323,8 @@ def main():
         log(f"bench: device copy {result['copy_calibration']}")
     del x, out
     torch.cuda.empty_cache()
+    if not args.no_extras and shape == (1024, 1024, 1024):
+        result["configs"] = extras(x_host, args)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         result["cpu_baseline"] = cpu_baseline(x_host)

@@ -160,6 +160,21 @@ int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
 int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
                           void* const* out, int count, int sign, void* stream);
 
+/* Autotuner: time candidate schedules and kernel options (pencil with and
+ * without the persistent kernels, split long axes, other tiles; slab;
+ * volumetric) for a (n0, n1, n2) transform on the current device, on `in`
+ * and `out` (device buffers of n0 n1 n2 complex64; out is overwritten), in
+ * stream order on `stream`, and record the fastest: DFT3D_SCHED_AUTO plans
+ * of that shape created afterwards use it (their precision is kept).  The
+ * choice is kept for the process and, when the environment variable
+ * DFT3D_TUNE_CACHE names a file, written there and read back by later
+ * processes on the same GPU architecture.  Candidates allocate their own
+ * workspace.  best_schedule and best_ms (may be NULL) receive the choice and
+ * its forward time.  Blocks until the timing is done. */
+int dft3d_autotune(int64_t n0, int64_t n1, int64_t n2, const void* in,
+                   void* out, void* stream, int* best_schedule,
+                   double* best_ms);
+
 /* Release the plan, its device tables and any plan-owned workspace.
  * NULL is accepted. */
 int dft3d_destroy(dft3d_plan_t plan);

@@ -51,7 +51,8 @@ int rebuild(dft3d_plan_s* p) {
   std::vector<Pass> passes;
   size_t ws = 0;
   int resolved = 0;
-  int st = build_passes(p->n, p->schedule, p->layout, p->opt, passes, ws, resolved);
+  const int sched = (p->schedule == DFT3D_SCHED_AUTO && p->tuned >= 0) ? p->tuned : p->schedule;
+  int st = build_passes(p->n, sched, p->layout, p->opt, passes, ws, resolved);
   if (st != DFT3D_OK) return st;
 
   // one table per distinct root length (key n > 0) and per MFMA leaf
@@ -235,6 +236,7 @@ int dft3d_plan(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
     delete p;
     return DFT3D_ERR_HIP;
   }
+  if (schedule == DFT3D_SCHED_AUTO) tune_lookup(p);
   st = rebuild(p);
   if (st != DFT3D_OK) {
     free_tables(p);

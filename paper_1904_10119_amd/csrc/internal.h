@@ -121,6 +121,7 @@ struct dft3d_plan_s {
   size_t ws_bytes = 0;
   bool ws_owned = false;
   uint64_t uid = 0;  // changes whenever the pass list is rebuilt
+  int tuned = -1;    // AUTO plans: schedule chosen by the autotuner, -1 none
 };
 
 namespace dft3d {
@@ -130,4 +131,6 @@ int ensure_workspace(dft3d_plan_s* p);
 int batch_execute(dft3d_plan_s* const* plans, const void* const* in,
                   void* const* out, int count, int sign, hipStream_t stream);
 void batch_forget_plan(const dft3d_plan_s* p);
+// AUTO plans: apply the autotuner's recorded choice for the shape, if any.
+void tune_lookup(dft3d_plan_s* p);
 }  // namespace dft3d

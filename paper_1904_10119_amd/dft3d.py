@@ -34,7 +34,7 @@ ERR_WORKSPACE_TOO_SMALL = -7
 EXPORTS = ("dft3d_status_string", "dft3d_plan", "dft3d_plan_describe",
            "dft3d_plan_set_option", "dft3d_plan_get_option",
            "dft3d_workspace_size", "dft3d_set_workspace", "dft3d_execute",
-           "dft3d_execute_batched", "dft3d_destroy")
+           "dft3d_execute_batched", "dft3d_autotune", "dft3d_destroy")
 
 _lib = None
 
@@ -73,6 +73,8 @@ def lib():
     L.dft3d_execute.argtypes = [vp, vp, vp, ci, vp]
     L.dft3d_execute_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp),
                                         ctypes.POINTER(vp), ci, ci, vp]
+    L.dft3d_autotune.argtypes = [i64, i64, i64, vp, vp, vp, ctypes.POINTER(ci),
+                                 ctypes.POINTER(ctypes.c_double)]
     L.dft3d_destroy.argtypes = [vp]
     for f in EXPORTS[1:]:
         getattr(L, f).restype = ci
@@ -213,6 +215,27 @@ def get_plan(shape, schedule="auto", precision="fp32", device_index=0, **opts) -
         p = Plan(shape, schedule, precision=precision, **opts)
         _plans[key] = p
     return p
+
+
+SCHEDULE_NAMES = {v: k for k, v in SCHEDULES.items()}
+
+
+def autotune(shape, device="cuda") -> dict:
+    """Time candidate schedules for `shape` on the GPU and make the fastest
+    the choice of later "auto" plans of that shape."""
+    import torch
+    from . import inputs
+    shape = tuple(int(v) for v in shape)
+    x = torch.from_numpy(inputs.uniform_c64(shape, 77)).to(device)
+    out = torch.empty_like(x)
+    best = ctypes.c_int(-1)
+    ms = ctypes.c_double(0.0)
+    _check(lib().dft3d_autotune(*shape, x.data_ptr(), out.data_ptr(),
+                                torch.cuda.current_stream(x.device).cuda_stream,
+                                ctypes.byref(best), ctypes.byref(ms)), "dft3d_autotune")
+    for key in [k for k in _plans if k[0] == shape and k[1] == "auto"]:
+        _plans.pop(key).close()
+    return {"schedule": SCHEDULE_NAMES.get(best.value, str(best.value)), "ms": ms.value}
 
 
 def fftn(x, schedule: str = "auto", precision: str = "fp32", inverse: bool = False,

@@ -130,7 +130,12 @@ def test_volumetric_splits_every_axis():
 
 
 def test_auto_splits_long_axes():
+    # untuned auto splits only 4096-long axes; split_max lowers the bar
     d = dft3d.describe((2048, 1024, 512), "auto")
+    assert [p["n"] for p in d["passes"]] == [512, 1024, 2048]
+    d = dft3d.describe((4096, 8, 16), "auto")
+    assert [p["n"] for p in d["passes"]] == [16, 8, 64, 64]
+    d = dft3d.describe((2048, 1024, 512), "auto", split_max=1024)
     assert [p["n"] for p in d["passes"]] == [512, 1024, 32, 64]
 
 
@@ -141,5 +146,5 @@ def test_split_precision_uses_mfma_leaves_where_available():
     d = dft3d.describe((8, 256, 4), "pencil", precision="bf16x9")
     assert [p["precision"] for p in d["passes"]] == [0, dft3d.PRECISIONS["bf16x9"], 0]
     # four-step first halves (post twiddle) stay FP32
-    d = dft3d.describe((2048, 1024, 512), "auto", precision="fp16x3")
+    d = dft3d.describe((2048, 1024, 512), "auto", precision="fp16x3", split_max=1024)
     assert [p["precision"] > 0 for p in d["passes"]] == [True, True, False, True]

@@ -229,3 +229,23 @@ def test_slab_plane_groups(group):
     for sign, inv in ((-1, False), (1, True)):
         y = gpu_fftn(x, "slab", inverse=inv, slab_group=group)
         assert oracle.rel_l2(y, ref_fftn(x, sign)) <= oracle.tol(x.size), (group, sign)
+
+
+def test_autotune_records_choice_for_auto_plans(tmp_path, monkeypatch):
+    """The autotuner times the candidates, records the fastest, and later
+    auto plans of that shape use it (and still match the oracle); the
+    choice is written to and read back from the cache file."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("DFT3D_TUNE_CACHE", str(cache))
+    shape = (128, 32, 64)
+    r = dft3d.autotune(shape)
+    say("autotune", shape, r)
+    assert r["schedule"] in ("pencil", "slab", "volumetric") and r["ms"] > 0
+    assert cache.exists() and f"{shape[0]} {shape[1]} {shape[2]}" in cache.read_text()
+    x = inputs.uniform_c64(shape, 28)
+    p = dft3d.Plan(shape, "auto")
+    y = torch.empty(shape, dtype=torch.complex64, device="cuda")
+    p.execute(torch.from_numpy(x).cuda(), y)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(y.cpu().numpy(), ref_fftn(x, -1)) <= oracle.tol(x.size)
+    p.close()
