@@ -155,6 +155,16 @@ def extras(x1024_host, args):
                     "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1),
                     "hbm_gbs_per_pass": round(16.0 * N / (f / n * 1e-3) / 1e9, 1)}
         log(f"bench: 1024^3 {s} {sched[s]}")
+    # volumetric leaving the shuffled (digit-exchanged) order, and its inverse
+    # from that order
+    f, n = plan_ms((1024,) * 3, x, y, 5, schedule="volumetric", layout="shuffled")
+    i, _ = plan_ms((1024,) * 3, x, y, 5, inverse=True, schedule="volumetric",
+                   layout="shuffled")
+    sched["volumetric shuffled"] = {
+        "passes": n, "fwd_ms": round(f, 3), "inv_ms": round(i, 3),
+        "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1),
+        "hbm_gbs_per_pass": round(16.0 * N / (f / n * 1e-3) / 1e9, 1)}
+    log(f"bench: 1024^3 volumetric shuffled {sched['volumetric shuffled']}")
     out["1024^3 schedules"] = sched
     prec = {}
     for pr in ("fp32", "bf16x6", "bf16x9", "fp16x3"):

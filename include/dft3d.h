@@ -51,11 +51,17 @@ enum dft3d_schedule {
   DFT3D_SCHED_VOLUMETRIC = 3
 };
 
-/* Output layouts.  NATURAL is C order (n0, n1, n2).  SHUFFLED leaves the
- * digit-transposed order of a four-step transform (Section 2.4: the last
- * redistribution may be dropped when the consumer does not need natural
- * order); it is accepted only where documented and otherwise rejected with
- * DFT3D_ERR_UNSUPPORTED_SCHEDULE. */
+/* Layouts of the transformed data.  NATURAL is C order (n0, n1, n2) on both
+ * sides.  SHUFFLED (VOLUMETRIC and AUTO schedules only, which then resolves
+ * to VOLUMETRIC; others return DFT3D_ERR_UNSUPPORTED_SCHEDULE) drops the
+ * final digit exchange of every split axis (Section 2.4, Section 3.2): along
+ * an axis of length n >= 4 split n = a b with a = 2^ceil(log2(n) / 2),
+ * the transformed entry of natural index k' + b l' (k' < b, l' < a) is kept
+ * at position l' + a k'; axes shorter than 4 stay in natural order.  The
+ * forward transform (sign -1) takes natural input and writes this order;
+ * the inverse (sign +1) takes input in this order and writes natural order,
+ * so a pointwise product between the two (a convolution) needs neither
+ * exchange.  Batched execution accepts NATURAL plans only. */
 enum dft3d_layout { DFT3D_LAYOUT_NATURAL = 0, DFT3D_LAYOUT_SHUFFLED = 1 };
 
 /* Leaf arithmetic.  FP32 runs every butterfly in binary32 with twiddles
@@ -143,7 +149,12 @@ int dft3d_set_workspace(dft3d_plan_t plan, void* dev_ptr, size_t bytes);
  * non-overlapping (in == out is INVALID_ARG); in is never written.
  * sign = -1 forward, +1 inverse, anything else INVALID_ARG.  Launch errors
  * are returned (HIP_ERROR); faults inside kernels surface at the caller's
- * next synchronisation. */
+ * next synchronisation.  Once the plan has a workspace (bound with
+ * dft3d_set_workspace or allocated by an earlier execute) and has executed
+ * once on the device, a call only launches kernels on `stream`: no
+ * allocation, synchronisation or memset, so it may be captured into a HIP
+ * graph and replayed (the graph keeps the buffer pointers it was captured
+ * with). */
 int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
                   void* stream);
 
@@ -156,7 +167,10 @@ int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
  * for repeated plans); later calls with the same sequence only refresh the
  * buffer pointers.  Plans whose passes exceed length 256 run one after
  * another.  count == 0 is a no-op.  Plans must use the NATURAL layout and
- * FP32.  Not thread-safe for concurrent calls with overlapping plans. */
+ * FP32.  Not thread-safe for concurrent calls with overlapping plans.  The
+ * call waits for its previous descriptor upload, so it cannot be captured
+ * into a HIP graph: on a capturing stream it returns
+ * DFT3D_ERR_UNSUPPORTED_SCHEDULE before enqueueing anything. */
 int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
                           void* const* out, int count, int sign, void* stream);
 

@@ -166,6 +166,40 @@ def fft_pencils(x_c64: np.ndarray, axis: int, first: int, count: int,
     return out
 
 
+def shuffled_positions(n: int, a: int) -> np.ndarray:
+    """Natural index held at each position of the shuffled order of a
+    length-n axis split n = a * b (Section 2.4; eq. (3) without its final
+    transposition, as in Section 3.2): natural entry y[k' + b l'] (k' < b,
+    l' < a) sits at position l' + a k'.  a = 1 or a = n is natural order."""
+    if n % a:
+        raise ValueError("a must divide n")
+    b = n // a
+    pos = np.arange(n, dtype=np.int64)
+    lp, kp = pos % a, pos // a
+    return kp + b * lp
+
+
+def to_shuffled(y, factors) -> np.ndarray:
+    """Rearrange a natural-order 3D array into the shuffled order with the
+    per-axis split factors ``factors`` = (a0, a1, a2)."""
+    y = np.asarray(y)
+    for axis, a in enumerate(factors):
+        idx = shuffled_positions(y.shape[axis], int(a))
+        y = np.take(y, idx, axis=axis)
+    return y
+
+
+def from_shuffled(s, factors) -> np.ndarray:
+    """Inverse of ``to_shuffled``."""
+    s = np.asarray(s)
+    for axis, a in enumerate(factors):
+        idx = shuffled_positions(s.shape[axis], int(a))
+        inv = np.empty_like(idx)
+        inv[idx] = np.arange(idx.size)
+        s = np.take(s, inv, axis=axis)
+    return s
+
+
 def rel_l2(a, ref) -> float:
     """||a - ref||_2 / ||ref||_2 over all complex entries, in FP64."""
     a = np.asarray(a).astype(np.complex128, copy=False).reshape(-1)

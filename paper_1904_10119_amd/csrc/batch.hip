@@ -166,6 +166,14 @@ BatchGraph* find_cached(dft3d_plan_s* const* plans, int count, int device) {
 
 int batch_execute(dft3d_plan_s* const* plans, const void* const* in, void* const* out,
                   int count, int sign, hipStream_t stream) {
+  {  // the descriptor upload synchronises with the previous call: not capturable
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+      (void)hipGetLastError();
+      return DFT3D_ERR_HIP;
+    }
+    if (cs != hipStreamCaptureStatusNone) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+  }
   bool all = true;
   for (int i = 0; i < count; ++i) {
     const int st = ensure_workspace(plans[i]);

@@ -54,12 +54,25 @@ int rebuild(dft3d_plan_s* p) {
   const int sched = (p->schedule == DFT3D_SCHED_AUTO && p->tuned >= 0) ? p->tuned : p->schedule;
   int st = build_passes(p->n, sched, p->layout, p->opt, passes, ws, resolved);
   if (st != DFT3D_OK) return st;
+  // shuffled plans: the inverse runs its own list (shuffled in, natural out)
+  std::vector<Pass> ipasses;
+  if (p->layout == DFT3D_LAYOUT_SHUFFLED) {
+    size_t iws = 0;
+    int ires = 0;
+    st = build_passes(p->n, sched, p->layout, p->opt, ipasses, iws, ires, true);
+    if (st != DFT3D_OK) return st;
+    if (iws > ws) ws = iws;
+  }
 
   // one table per distinct root length (key n > 0) and per MFMA leaf
   // precision (key -precision, kLeafTableFloat2 slots of 16-bit values)
   std::map<int64_t, int64_t> offsets;
   int64_t total = 0;
-  for (const Pass& ps : passes) {
+  std::vector<const Pass*> all;
+  for (const Pass& ps : passes) all.push_back(&ps);
+  for (const Pass& ps : ipasses) all.push_back(&ps);
+  for (const Pass* pp : all) {
+    const Pass& ps = *pp;
     for (int64_t len : {ps.tw_len, ps.twp_len}) {
       if (len > 0 && !offsets.count(len)) {
         offsets[len] = total;
@@ -93,14 +106,19 @@ int rebuild(dft3d_plan_s* p) {
   free_tables(p);
   p->tables = dev;
   p->passes.swap(passes);
-  p->tw_off.clear();
-  p->twp_off.clear();
-  for (const Pass& ps : p->passes) {
-    p->tw_off.push_back(offsets[ps.tw_len]);
-    // post-twiddle table, or the leaf operand table for MFMA passes
-    p->twp_off.push_back(ps.leaf ? offsets[-ps.leaf]
-                                 : (ps.twp_len > 0 ? offsets[ps.twp_len] : 0));
-  }
+  p->ipasses.swap(ipasses);
+  auto table_offsets = [&offsets](const std::vector<Pass>& list, std::vector<int64_t>& tw,
+                                  std::vector<int64_t>& twp) {
+    tw.clear();
+    twp.clear();
+    for (const Pass& ps : list) {
+      tw.push_back(offsets[ps.tw_len]);
+      // post-twiddle table, or the leaf operand table for MFMA passes
+      twp.push_back(ps.leaf ? offsets[-ps.leaf] : (ps.twp_len > 0 ? offsets[ps.twp_len] : 0));
+    }
+  };
+  table_offsets(p->passes, p->tw_off, p->twp_off);
+  table_offsets(p->ipasses, p->itw_off, p->itwp_off);
   p->resolved = resolved;
   p->uid = next_plan_uid();
   if (ws > p->ws_need && p->ws_owned) free_workspace(p);  // regrown lazily
@@ -203,7 +221,16 @@ int dft3d_plan_describe(int64_t n0, int64_t n1, int64_t n2, int schedule, int la
   int resolved = 0;
   st = build_passes(n, schedule, layout, opt, passes, ws, resolved);
   if (st != DFT3D_OK) return st;
-  const std::string s = describe_passes(n, resolved, passes, ws);
+  std::vector<Pass> ipasses;
+  if (layout == DFT3D_LAYOUT_SHUFFLED) {
+    size_t iws = 0;
+    int ires = 0;
+    st = build_passes(n, schedule, layout, opt, ipasses, iws, ires, true);
+    if (st != DFT3D_OK) return st;
+    if (iws > ws) ws = iws;
+  }
+  const std::string s = describe_passes(n, resolved, layout, passes,
+                                        layout == DFT3D_LAYOUT_SHUFFLED ? &ipasses : nullptr, ws);
   if (needed) *needed = s.size() + 1;
   if (buf && len > 0) {
     const size_t m = s.size() < len - 1 ? s.size() : len - 1;
@@ -236,7 +263,7 @@ int dft3d_plan(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
     delete p;
     return DFT3D_ERR_HIP;
   }
-  if (schedule == DFT3D_SCHED_AUTO) tune_lookup(p);
+  if (schedule == DFT3D_SCHED_AUTO && layout == DFT3D_LAYOUT_NATURAL) tune_lookup(p);
   st = rebuild(p);
   if (st != DFT3D_OK) {
     free_tables(p);
@@ -311,16 +338,21 @@ int dft3d_execute(dft3d_plan_t p, const void* in, void* out, int sign, void* str
   hipStream_t s = static_cast<hipStream_t>(stream);
   float2* bufs[3] = {const_cast<float2*>(static_cast<const float2*>(in)),
                      static_cast<float2*>(out), static_cast<float2*>(p->ws)};
-  const size_t np = p->passes.size();
+  // a shuffled plan's inverse takes shuffled input through its own list
+  const bool inv_list = sign == 1 && !p->ipasses.empty();
+  const std::vector<Pass>& list = inv_list ? p->ipasses : p->passes;
+  const std::vector<int64_t>& tw_off = inv_list ? p->itw_off : p->tw_off;
+  const std::vector<int64_t>& twp_off = inv_list ? p->itwp_off : p->twp_off;
+  const size_t np = list.size();
   for (size_t i = 0; i < np; ++i) {
-    const Pass& ps = p->passes[i];
+    const Pass& ps = list[i];
     PassArgs a = ps.args;
     // inverse as conj(DFT(conj(x))): every pass reading the input conjugates
     // it; the last pass writes every output element and conjugates them
     a.conj_in = (sign == 1 && ps.src == BUF_IN) ? 1 : 0;
     a.conj_out = (sign == 1 && i + 1 == np) ? 1 : 0;
-    const float2* tw = p->tables + p->tw_off[i];
-    const float2* twp = p->tables + p->twp_off[i];
+    const float2* tw = p->tables + tw_off[i];
+    const float2* twp = p->tables + twp_off[i];
     hipError_t e =
         ps.k->launch(a, bufs[ps.src] + ps.in_off, bufs[ps.dst] + ps.out_off, tw, twp, s);
     if (e != hipSuccess) return DFT3D_ERR_HIP;

@@ -94,12 +94,19 @@ struct Options {
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success
-// fills passes and the workspace size in bytes.
+// fills passes and the workspace size in bytes.  from_layout = false gives
+// the forward list (natural input, output in `layout` order); true gives
+// the list that takes input in `layout` order to natural output, which the
+// inverse of a shuffled plan runs (for the natural layout both coincide).
 int build_passes(const int64_t n[3], int schedule, int layout, const Options& opt,
-                 std::vector<Pass>& passes, size_t& ws_bytes, int& resolved_schedule);
+                 std::vector<Pass>& passes, size_t& ws_bytes, int& resolved_schedule,
+                 bool from_layout = false);
 
-std::string describe_passes(const int64_t n[3], int schedule,
-                            const std::vector<Pass>& passes, size_t ws_bytes);
+// JSON description of a plan; inverse_passes (may be null) is listed as
+// "inverse_passes" when given.
+std::string describe_passes(const int64_t n[3], int schedule, int layout,
+                            const std::vector<Pass>& passes,
+                            const std::vector<Pass>* inverse_passes, size_t ws_bytes);
 
 uint64_t next_plan_uid();
 
@@ -114,6 +121,10 @@ struct dft3d_plan_s {
   dft3d::Options opt;
   std::vector<dft3d::Pass> passes;
   std::vector<int64_t> tw_off, twp_off;  // per pass, element offsets in tables
+  // Shuffled layout only: the passes the inverse runs (input in shuffled
+  // order, natural output) and their table offsets; empty otherwise.
+  std::vector<dft3d::Pass> ipasses;
+  std::vector<int64_t> itw_off, itwp_off;
   int device = -1;
   float2* tables = nullptr;
   size_t ws_need = 0;

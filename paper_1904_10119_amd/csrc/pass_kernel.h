@@ -388,6 +388,14 @@ void add_kernels(std::vector<KernelInfo>& v) {
   add_kernels_nt<N, T, 1>(v);
 }
 
+// ROW->ROW with the four-step twiddle: the first half of a split axis whose
+// input is in the shuffled (digit-exchanged) order, contiguous case.
+template <int N, int T>
+void add_row_twiddle_kernels(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info<N, T, MODE_ROW, MODE_ROW, 1, 0>());
+  v.push_back(kernel_info<N, T, MODE_ROW, MODE_ROW, 1, 1>());
+}
+
 template <int N, int T, int NT, class BL>
 void add_persistent_kernels_nt(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_COL, 0, NT, BL>());

@@ -15,6 +15,12 @@
 //     y[k' + Bf l'].
 //   AUTO: the pencil rotation, with axes longer than a threshold split into
 //     V1 + V2 as in the volumetric schedule.
+//   SHUFFLED layout (volumetric only; Section 2.4, Section 3.2): the forward
+//     transform leaves out the final digit exchange of every split axis, so
+//     natural entry y[k' + Bf l'] stays at position l' + A k' (V2 writes in
+//     the layout it reads).  The inverse takes that order and returns
+//     natural order: W1 = DFT_A over l' (contiguous in the shuffled order)
+//     times w_n^{k' a}, then W2 = DFT_Bf over k' stored at a + A b.
 #include <algorithm>
 #include <cstdio>
 #include <sstream>
@@ -162,7 +168,9 @@ void split_axis(int64_t n, int64_t& A, int64_t& Bf) {
 }
 
 // V1 + V2 of one axis in natural layout: the array is [outer][n][inner].
-void volumetric_axis(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis) {
+// With shuffled, V2 stores y[k' + Bf l'] at position l' + A k'.
+void volumetric_axis(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis,
+                     bool shuffled) {
   int64_t A, Bf;
   split_axis(n, A, Bf);
   const int64_t slab = n * inner;
@@ -175,15 +183,50 @@ void volumetric_axis(Builder& b, int64_t outer, int64_t n, int64_t inner, int ax
           ilog2(inner), A - 1, lab);
   }
   {  // V2: pencils (o, k', c); elements l at stride inner
-    std::snprintf(lab, sizeof lab, "vol%d.V2 DFT%lld x%lld", axis, (long long)A,
-                  (long long)(outer * Bf * inner));
-    if (inner == 1) {
+    std::snprintf(lab, sizeof lab, "vol%d.V2%s DFT%lld x%lld", axis, shuffled ? " shuf" : "",
+                  (long long)A, (long long)(outer * Bf * inner));
+    if (shuffled && inner == 1) {  // output element l' at A k' + l'
+      Field f[2] = {{Bf, A, A}, {outer, slab, slab}};
+      b.add((int)A, MODE_ROW, MODE_ROW, 0, f, 2, 1, 1, 0, 0, 0, lab);
+    } else if (shuffled) {
+      Field f[3] = {{inner, 1, 1}, {Bf, A * inner, A * inner}, {outer, slab, slab}};
+      b.add((int)A, MODE_COL, MODE_COL, 0, f, 3, inner, inner, 0, 0, 0, lab);
+    } else if (inner == 1) {
       Field f[2] = {{Bf, A, 1}, {outer, slab, slab}};
       b.add((int)A, MODE_ROW, MODE_COL, 0, f, 2, 1, Bf, 0, 0, 0, lab);
     } else {
       Field f[3] = {{inner, 1, 1}, {Bf, A * inner, inner}, {outer, slab, slab}};
       b.add((int)A, MODE_COL, MODE_COL, 0, f, 3, inner, Bf * inner, 0, 0, 0, lab);
     }
+  }
+}
+
+// One axis of the inverse of a shuffled plan: input entry y[k' + Bf l'] at
+// position l' + A k', natural output x[a + A b] at position a + A b:
+//   x[a + A b] = sum_k' w_Bf^{k' b} w_n^{k' a} sum_l' w_A^{l' a} y[k' + Bf l']
+// (forward roots; the inverse conjugates around the whole list).
+void volumetric_axis_from_shuffled(Builder& b, int64_t outer, int64_t n, int64_t inner,
+                                   int axis) {
+  int64_t A, Bf;
+  split_axis(n, A, Bf);
+  const int64_t slab = n * inner;
+  char lab[64];
+  {  // W1: pencils (o, k', c), elements l' at A k' + l', outputs a there too
+    std::snprintf(lab, sizeof lab, "vol%d.W1 DFT%lld x%lld", axis, (long long)A,
+                  (long long)(outer * Bf * inner));
+    if (inner == 1) {
+      Field f[2] = {{Bf, A, A}, {outer, slab, slab}};
+      b.add((int)A, MODE_ROW, MODE_ROW, 1, f, 2, 1, 1, n, 0, Bf - 1, lab);
+    } else {
+      Field f[3] = {{inner, 1, 1}, {Bf, A * inner, A * inner}, {outer, slab, slab}};
+      b.add((int)A, MODE_COL, MODE_COL, 1, f, 3, inner, inner, n, ilog2(inner), Bf - 1, lab);
+    }
+  }
+  {  // W2: pencils (o, a, c), elements k' at a + A k', outputs b at a + A b
+    Field f[2] = {{A * inner, 1, 1}, {outer, slab, slab}};
+    std::snprintf(lab, sizeof lab, "vol%d.W2 DFT%lld x%lld", axis, (long long)Bf,
+                  (long long)(outer * A * inner));
+    b.add((int)Bf, MODE_COL, MODE_COL, 0, f, 2, A * inner, A * inner, 0, 0, 0, lab);
   }
 }
 
@@ -236,7 +279,8 @@ void assign_chain(std::vector<Pass>& passes, size_t first, size_t& ws_needed_fla
 }  // namespace
 
 int build_passes(const int64_t n[3], int schedule, int layout, const Options& opt,
-                 std::vector<Pass>& passes, size_t& ws_bytes, int& resolved) {
+                 std::vector<Pass>& passes, size_t& ws_bytes, int& resolved,
+                 bool from_layout) {
   passes.clear();
   ws_bytes = 0;
   for (int d = 0; d < 3; ++d)
@@ -245,12 +289,16 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
     return DFT3D_ERR_INVALID_ARG;
   if (layout != DFT3D_LAYOUT_NATURAL && layout != DFT3D_LAYOUT_SHUFFLED)
     return DFT3D_ERR_INVALID_ARG;
-  if (layout != DFT3D_LAYOUT_NATURAL) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+  const bool shuffled = layout == DFT3D_LAYOUT_SHUFFLED;
+  // only the volumetric schedule has a digit exchange to leave out
+  if (shuffled && schedule != DFT3D_SCHED_VOLUMETRIC && schedule != DFT3D_SCHED_AUTO)
+    return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
 
   const int64_t total = n[0] * n[1] * n[2];
   Builder b{opt, passes, total};
   resolved = schedule;
-  if (schedule == DFT3D_SCHED_AUTO) resolved = DFT3D_SCHED_PENCIL;
+  if (schedule == DFT3D_SCHED_AUTO)
+    resolved = shuffled ? DFT3D_SCHED_VOLUMETRIC : DFT3D_SCHED_PENCIL;
   // Untuned AUTO splits only 4096-long axes (a 4096 pencil leaves tiles of
   // four pencils); measured at 2048x1024x512, the 2048 pass beats its split.
   const int64_t split_max =
@@ -312,9 +360,11 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
       int64_t outer = 1, inner = 1;
       for (int d = 0; d < axis; ++d) outer *= n[d];
       for (int d = axis + 1; d < 3; ++d) inner *= n[d];
-      if (n[axis] >= 4) {
-        volumetric_axis(b, outer, n[axis], inner, axis);
-      } else {  // too short to split: one in-layout pass
+      if (n[axis] >= 4 && shuffled && from_layout) {
+        volumetric_axis_from_shuffled(b, outer, n[axis], inner, axis);
+      } else if (n[axis] >= 4) {
+        volumetric_axis(b, outer, n[axis], inner, axis, shuffled);
+      } else {  // too short to split (its shuffled order is natural): one pass
         char lab[64];
         std::snprintf(lab, sizeof lab, "vol%d DFT%lld", axis, (long long)n[axis]);
         if (inner == 1) {
@@ -336,13 +386,10 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
   return DFT3D_OK;
 }
 
-std::string describe_passes(const int64_t n[3], int schedule,
-                            const std::vector<Pass>& passes, size_t ws_bytes) {
-  static const char* kSched[] = {"auto", "slab", "pencil", "volumetric"};
+namespace {
+void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
   static const char* kBuf[] = {"in", "out", "ws"};
-  std::ostringstream os;
-  os << "{\"shape\":[" << n[0] << "," << n[1] << "," << n[2] << "],\"schedule\":\""
-     << kSched[schedule] << "\",\"workspace_bytes\":" << ws_bytes << ",\"passes\":[";
+  os << "[";
   for (size_t i = 0; i < passes.size(); ++i) {
     const Pass& p = passes[i];
     if (i) os << ",";
@@ -363,7 +410,25 @@ std::string describe_passes(const int64_t n[3], int schedule,
        << ",\"res_shift\":" << p.args.res_shift << ",\"res_mask\":" << p.args.res_mask
        << ",\"twp_len\":" << p.twp_len << "}}";
   }
-  os << "]}";
+  os << "]";
+}
+}  // namespace
+
+std::string describe_passes(const int64_t n[3], int schedule, int layout,
+                            const std::vector<Pass>& passes,
+                            const std::vector<Pass>* inverse_passes, size_t ws_bytes) {
+  static const char* kSched[] = {"auto", "slab", "pencil", "volumetric"};
+  std::ostringstream os;
+  os << "{\"shape\":[" << n[0] << "," << n[1] << "," << n[2] << "],\"schedule\":\""
+     << kSched[schedule] << "\",\"layout\":\""
+     << (layout == DFT3D_LAYOUT_SHUFFLED ? "shuffled" : "natural")
+     << "\",\"workspace_bytes\":" << ws_bytes << ",\"passes\":";
+  describe_list(os, passes);
+  if (inverse_passes) {
+    os << ",\"inverse_passes\":";
+    describe_list(os, *inverse_passes);
+  }
+  os << "}";
   return os.str();
 }
 

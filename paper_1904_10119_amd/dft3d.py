@@ -220,6 +220,22 @@ def get_plan(shape, schedule="auto", precision="fp32", device_index=0, **opts) -
 SCHEDULE_NAMES = {v: k for k, v in SCHEDULES.items()}
 
 
+def shuffle_factors(shape) -> Tuple[int, int, int]:
+    """Split factor a of every axis in the SHUFFLED layout: along an axis of
+    length n = a * b, the transformed entry of natural index k' + b l' sits
+    at position l' + a k'; a = 2^ceil(log2(n) / 2) for n >= 4, and axes
+    shorter than 4 stay natural (a = 1)."""
+    out = []
+    for n in shape:
+        n = int(n)
+        if n < 4:
+            out.append(1)
+        else:
+            lg = n.bit_length() - 1
+            out.append(1 << ((lg + 1) // 2))
+    return tuple(out)
+
+
 def autotune(shape, device="cuda") -> dict:
     """Time candidate schedules for `shape` on the GPU and make the fastest
     the choice of later "auto" plans of that shape."""
@@ -240,7 +256,9 @@ def autotune(shape, device="cuda") -> dict:
 
 def fftn(x, schedule: str = "auto", precision: str = "fp32", inverse: bool = False,
          out=None, **opts):
-    """3D DFT of a complex64 CUDA tensor of shape (n0, n1, n2); unnormalised."""
+    """3D DFT of a complex64 CUDA tensor of shape (n0, n1, n2); unnormalised.
+    Extra keyword options go to the plan (e.g. layout="shuffled" with the
+    volumetric schedule, tile=, persistent=)."""
     import torch
     if x.dim() != 3:
         raise ValueError("expected a 3D tensor")

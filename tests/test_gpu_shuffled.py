@@ -1,0 +1,154 @@
+"""GPU parity of the SHUFFLED layout (volumetric schedule without the final
+digit exchange of each split axis; Section 2.4, Section 3.2).
+
+The forward transform writes the natural result permuted into the shuffled
+order; the oracle applies the same documented permutation
+(oracle.to_shuffled with the per-axis split factors) before comparing.  The
+inverse takes shuffled input and returns natural order.  Tolerances as in
+the natural-layout tests: tol(N) forward and inverse, 2 tol(N) round trip."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_10119_amd import dft3d, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dft3d.lib()
+    assert "libdft3d.so" in open("/proc/self/maps").read()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(x_np, inverse=False, schedule="volumetric", **opts):
+    x = torch.from_numpy(np.ascontiguousarray(x_np, dtype=np.complex64)).cuda()
+    y = dft3d.fftn(x, schedule=schedule, inverse=inverse, layout="shuffled", **opts)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def ref(x_np, sign):
+    method = "direct" if x_np.size <= (1 << 15) else "fft"
+    return oracle.dft3d(x_np.astype(np.complex128), sign, method)
+
+
+SHAPES = [(1, 1, 1), (2, 4, 8), (8, 2, 4), (4, 8, 2), (64, 64, 64), (32, 64, 128),
+          (128, 16, 32), (4, 2048, 2), (2, 4, 4096), (1024, 8, 4), (16, 1, 512)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("schedule", ["volumetric", "auto"])
+def test_shuffled_forward_inverse_roundtrip(shape, schedule):
+    say("case shuffled", shape, schedule)
+    f = dft3d.shuffle_factors(shape)
+    x = inputs.uniform_c64(shape, 31)
+    N = x.size
+    y = run(x, schedule=schedule)
+    err = oracle.rel_l2(y, oracle.to_shuffled(ref(x, -1), f))
+    say("  fwd rel_l2", err)
+    assert err <= oracle.tol(N)
+    # inverse of arbitrary shuffled-order input z: natural inverse DFT
+    z = inputs.uniform_c64(shape, 32)
+    yi = run(oracle.to_shuffled(z, f).astype(np.complex64), inverse=True, schedule=schedule)
+    assert oracle.rel_l2(yi, ref(z, +1)) <= oracle.tol(N)
+    back = run(y, inverse=True, schedule=schedule) / N
+    assert oracle.rel_l2(back, x) <= 2 * oracle.tol(N)
+
+
+def test_shuffled_is_the_natural_result_permuted():
+    shape = (64, 32, 128)
+    f = dft3d.shuffle_factors(shape)
+    x = inputs.uniform_c64(shape, 33)
+    xt = torch.from_numpy(x).cuda()
+    nat = dft3d.fftn(xt, schedule="volumetric").cpu().numpy()
+    shf = run(x)
+    assert oracle.rel_l2(shf, oracle.to_shuffled(nat, f)) <= oracle.tol(x.size)
+
+
+def test_convolution_through_shuffled_order():
+    """Circular convolution as inverse(forward(x) * forward(h)) with both
+    spectra left in the shuffled order, against the oracle's FP64 spectra
+    (the identity itself is pinned by brute force in the CPU tests)."""
+    shape = (32, 64, 16)
+    x = inputs.uniform_c64(shape, 34)
+    h = inputs.uniform_c64(shape, 35)
+    N = x.size
+    X = dft3d.fftn(torch.from_numpy(x).cuda(), schedule="volumetric", layout="shuffled")
+    H = dft3d.fftn(torch.from_numpy(h).cuda(), schedule="volumetric", layout="shuffled")
+    Y = dft3d.fftn(X * H, schedule="volumetric", layout="shuffled", inverse=True)
+    torch.cuda.synchronize()
+    want = oracle.dft3d(ref(x, -1) * ref(h, -1), +1, "fft")
+    err = oracle.rel_l2(Y.cpu().numpy(), want)
+    say("  convolution rel_l2", err)
+    assert err <= 3 * oracle.tol(N)
+
+
+@pytest.mark.parametrize("precision", ["bf16x6", "fp16x3"])
+def test_shuffled_with_split_precision_leaves(precision):
+    shape = (64, 256, 32)
+    f = dft3d.shuffle_factors(shape)
+    x = inputs.uniform_c64(shape, 36)
+    y = run(x, precision=precision)
+    assert oracle.rel_l2(y, oracle.to_shuffled(ref(x, -1), f)) <= oracle.tol(x.size)
+    back = run(y, inverse=True, precision=precision) / x.size
+    assert oracle.rel_l2(back, x) <= 2 * oracle.tol(x.size)
+
+
+def test_shuffled_full_1024_cubed():
+    """1024^3 in the launch configuration the benchmark times: sampled output
+    pencils against the oracle's direct sums, then the round trip."""
+    shape = (1024, 1024, 1024)
+    say("case shuffled full size", shape)
+    f = dft3d.shuffle_factors(shape)
+    x = inputs.uniform_c64(shape, 2)
+    xt = torch.from_numpy(x).cuda()
+    y = dft3d.fftn(xt, schedule="volumetric", layout="shuffled")
+    torch.cuda.synchronize()
+    g = np.random.default_rng(2)
+    k0 = np.concatenate([[0, 1023], g.integers(0, 1024, 10)])
+    k1 = np.concatenate([[0, 512], g.integers(0, 1024, 10)])
+    sig = [oracle.shuffled_positions(1024, a) for a in f]
+    pos = []
+    for s in sig:
+        inv = np.empty_like(s)
+        inv[s] = np.arange(s.size)
+        pos.append(inv)
+    p0 = torch.from_numpy(pos[0][k0]).cuda()
+    p1 = torch.from_numpy(pos[1][k1]).cuda()
+    got = y[p0, p1, :].cpu().numpy()
+    want = oracle.sample_pencils(x, k0, k1, -1)[:, sig[2]]
+    err = oracle.rel_l2(got, want)
+    say("  sampled pencils rel_l2", err)
+    assert err <= oracle.tol(x.size)
+    back = dft3d.fftn(y, schedule="volumetric", layout="shuffled", inverse=True)
+    d = torch.view_as_real(back).double() / x.size - torch.view_as_real(xt).double()
+    rt = (torch.linalg.vector_norm(d) /
+          torch.linalg.vector_norm(torch.view_as_real(xt).double())).item()
+    say("  round trip rel_l2", rt)
+    assert rt <= 2 * oracle.tol(x.size)
+    del xt, y, back, d
+    torch.cuda.empty_cache()
+
+
+def test_batched_rejects_shuffled_plans():
+    import ctypes
+    p = dft3d.Plan((8, 8, 8), "volumetric", layout="shuffled")
+    x = torch.zeros((8, 8, 8), dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    arr = ctypes.c_void_p * 1
+    st = dft3d.lib().dft3d_execute_batched(arr(p.handle.value), arr(x.data_ptr()),
+                                           arr(y.data_ptr()), 1, -1, None)
+    assert st == dft3d.ERR_UNSUPPORTED_SCHEDULE
+    p.close()

@@ -138,3 +138,39 @@ def test_shuffled_order_is_digit_transpose(a, b):
     kp, lp = np.meshgrid(np.arange(b), np.arange(a), indexing="ij")
     assert np.allclose(shuffled[(lp + a * kp).ravel()], y[(kp + b * lp).ravel()],
                        rtol=0, atol=1e-12)
+    # the oracle's shuffled order is exactly this four-step output order
+    assert np.allclose(shuffled, y[oracle.shuffled_positions(n, a)], rtol=0, atol=1e-12)
+
+
+def test_shuffle_helpers_are_inverse_permutations():
+    g = np.random.default_rng(3)
+    y = g.standard_normal((8, 16, 4)) + 1j * g.standard_normal((8, 16, 4))
+    for factors in [(4, 4, 2), (1, 16, 4), (2, 8, 1)]:
+        s = oracle.to_shuffled(y, factors)
+        assert sorted(s.reshape(-1).tolist(), key=lambda c: (c.real, c.imag)) == \
+            sorted(y.reshape(-1).tolist(), key=lambda c: (c.real, c.imag))
+        assert np.array_equal(oracle.from_shuffled(s, factors), y)
+    # a = 1 and a = n leave the order natural
+    assert np.array_equal(oracle.shuffled_positions(16, 1), np.arange(16))
+    assert np.array_equal(oracle.shuffled_positions(16, 16), np.arange(16))
+    # n = 8 = 4 * 2: positions 0..7 hold 0, 2, 4, 6, 1, 3, 5, 7
+    assert oracle.shuffled_positions(8, 4).tolist() == [0, 2, 4, 6, 1, 3, 5, 7]
+
+
+def test_circular_convolution_by_transforms():
+    """The use of the shuffled order: a pointwise product between a forward
+    and an inverse transform is a circular convolution whatever the order
+    of the transformed entries, as long as both factors share it."""
+    g = np.random.default_rng(4)
+    shape = (2, 4, 4)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    h = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    brute = np.zeros(shape, complex)
+    for i in np.ndindex(shape):
+        for j in np.ndindex(shape):
+            brute[i] += x[j] * h[tuple((i[d] - j[d]) % shape[d] for d in range(3))]
+    f = (2, 2, 2)
+    X = oracle.to_shuffled(oracle.dft3d(x, -1), f)
+    H = oracle.to_shuffled(oracle.dft3d(h, -1), f)
+    got = oracle.dft3d(oracle.from_shuffled(X * H, f), +1) / x.size
+    assert np.allclose(got, brute, rtol=0, atol=1e-12)

@@ -30,12 +30,16 @@ def addresses(args, n, inp):
     return base[:, None] + j[None, :] * js        # (B, n)
 
 
-def run_model(x, d, sign):
+def run_model(x, d, sign, key=None):
+    """Run a pass list; by default the one execute uses for `sign` (a
+    shuffled plan's inverse runs its "inverse_passes")."""
     n_total = x.size
     bufs = {"in": x.reshape(-1).astype(np.complex128),
             "out": np.full(n_total, np.nan, np.complex128),
             "ws": np.full(n_total, np.nan, np.complex128)}
-    passes = d["passes"]
+    if key is None:
+        key = "inverse_passes" if (sign == 1 and "inverse_passes" in d) else "passes"
+    passes = d[key]
     for i, p in enumerate(passes):
         a = p["args"]
         ia = addresses(a, p["n"], True)
@@ -114,3 +118,57 @@ def test_pass_list_with_options(opts, schedule):
     for sign in (-1, 1):
         got = run_model(x, d, sign)
         assert oracle.rel_l2(got, oracle.dft3d(x, sign, "fft")) < 1e-13, (opts, sign)
+
+
+SHUFFLED_SHAPES = [(1, 1, 1), (2, 4, 8), (8, 2, 4), (16, 16, 16), (32, 4, 64), (4, 64, 2),
+                   (2, 256, 8), (64, 1, 32), (4096, 2, 1), (1, 2, 2048), (8, 16, 32)]
+
+
+@pytest.mark.parametrize("shape", SHUFFLED_SHAPES)
+@pytest.mark.parametrize("schedule", ["volumetric", "auto"])
+def test_shuffled_pass_lists(shape, schedule):
+    """Forward list: natural input to the documented shuffled order; inverse
+    list: shuffled input to natural output (both within FP64 rounding)."""
+    g = np.random.default_rng(sum(shape) + 1)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    d = dft3d.describe(shape, schedule, "shuffled")
+    assert d["schedule"] == "volumetric" and d["layout"] == "shuffled"
+    f = dft3d.shuffle_factors(shape)
+    fwd = run_model(x, d, -1)
+    assert oracle.rel_l2(fwd, oracle.to_shuffled(oracle.dft3d(x, -1, "fft"), f)) < 1e-13
+    s = oracle.to_shuffled(x, f)                 # any data in shuffled order
+    inv = run_model(s, d, +1)
+    assert oracle.rel_l2(inv, oracle.dft3d(x, +1, "fft")) < 1e-13
+    # round trip through both lists
+    back = run_model(fwd, d, +1)
+    assert oracle.rel_l2(back, x.size * x) < 1e-13
+
+
+@pytest.mark.parametrize("shape", SHUFFLED_SHAPES + [(1024, 1024, 1024), (4096, 4096, 4)])
+def test_shuffled_pass_maps_in_bounds(shape):
+    d = dft3d.describe(shape, "volumetric", "shuffled")
+    N = shape[0] * shape[1] * shape[2]
+    for key in ("passes", "inverse_passes"):
+        for p in d[key]:
+            a = p["args"]
+            if a["B"] * p["n"] > (1 << 22):
+                B = a["B"]
+                for lo in (0, B // 2, B - 64):
+                    b = np.arange(lo, lo + 64, dtype=np.int64)
+                    for inp in (True, False):
+                        st = a["is"] if inp else a["os"]
+                        js = a["ijs"] if inp else a["oks"]
+                        base = ((b >> a["s1"]) * st[2] + ((b >> a["s0"]) & a["m1"]) * st[1]
+                                + (b & a["m0"]) * st[0])
+                        assert base.min() >= 0 and base.max() + (p["n"] - 1) * js < N
+                continue
+            for inp in (True, False):
+                addr = addresses(a, p["n"], inp).reshape(-1)
+                assert addr.min() >= 0 and addr.max() < N, (key, p["label"], inp)
+                assert np.unique(addr).size == addr.size, (key, p["label"], inp)
+
+
+@pytest.mark.parametrize("schedule", ["pencil", "slab"])
+def test_shuffled_rejected_by_other_schedules(schedule):
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((8, 8, 8), schedule, "shuffled")
