@@ -58,8 +58,10 @@ struct KernelInfo {
 const std::vector<KernelInfo>& kernel_registry();
 const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle,
                               int persistent, int nontemporal);
-// The split-precision MFMA pass kernel for a length and layout, if any.
-const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision);
+// The split-precision MFMA pass kernel for a length and layout, if any
+// (the persistent form when asked for and compiled, else the other form).
+const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
+                                   int persistent);
 
 // Roots w_n^m = exp(-2 pi i m / n), m < n, computed in FP64 with exact
 // octant reduction and rounded once to FP32 (eq. (4) entries).

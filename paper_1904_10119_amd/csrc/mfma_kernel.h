@@ -10,7 +10,8 @@
 // and the products of low combined order are accumulated, smallest first,
 // which recovers FP32-level accuracy from 8- or 11-bit significands.  A
 // leftover radix-2/4/8 stage and every twiddle run in FP32 on the vector
-// ALUs.  The tile lives in LDS between stages (ping-pong buffers).
+// ALUs.  The tile lives in LDS between stages (ping-pong buffers); the
+// persistent form loads the next tile into registers meanwhile.
 //
 // Operand lane layout of the 16x16x32 MFMA (checked on gfx950): lane l
 // holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i < 8, and
@@ -172,42 +173,70 @@ template <int N> constexpr int mfma_rest() {
 }
 // Elements per tile: T = tile / N pencils.
 template <int N> constexpr int mfma_tile_elems() { return N >= 2048 ? 4096 : 8192; }
+// LDS row stride of a pencil: one pad element so that consecutive pencils
+// (the COL-mode staging writes and reads) start in different banks.
+template <int N> constexpr int mfma_row() { return N + 1; }
+template <int N> constexpr int mfma_buf_elems() {
+  return (mfma_tile_elems<N>() / N) * mfma_row<N>();
+}
+constexpr int kMfmaThreads = 256;
 
-template <int N, int LM, int SM, int PREC>
-__global__ void __launch_bounds__(256)
-fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
-              const unsigned short* __restrict__ leaf, const PassArgs a) {
-  constexpr int TE = mfma_tile_elems<N>();
-  constexpr int T = TE / N;
-  constexpr int S16 = mfma_stages<N>();
-  constexpr int REST = mfma_rest<N>();
-  constexpr int NTHR = 256;
-  constexpr int ROUNDS = TE / 16 / 256;  // 16-vector groups: 4 per wave per round
-  __shared__ float2 buf[2][TE];
-  __shared__ float2 ltw[N];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
-
-  for (int i = tid; i < N; i += NTHR) ltw[i] = tw[i];
-  LeafA<PREC> A;
-  A.load(leaf, lane);
-
-  // load the tile: buf[0][q * N + j] = element j of pencil tile*T + q
-#pragma unroll 4
-  for (int idx = tid; idx < TE; idx += NTHR) {
+// Global -> registers: thread tid gets tile elements idx = tid + 256 e, as
+// (pencil q, element j) in the load mode's order (ROW: j fastest, COL: q
+// fastest), so a wavefront reads contiguous runs.  Pencils past the end of
+// a ragged last tile re-read the last pencil (in bounds, never stored).
+template <int N, int LM>
+__device__ __forceinline__ void mfma_load(float2 (&v)[mfma_tile_elems<N>() / kMfmaThreads],
+                                          const float2* src, const PassArgs& a, int64_t tile,
+                                          int tid) {
+  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = tid + kMfmaThreads * e;
     int q, j;
     if constexpr (LM == MODE_ROW) { q = idx / N; j = idx % N; }
     else { q = idx % T; j = idx / T; }
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
-    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
-    float2 v = s[(int64_t)j * a.ijs];
-    if (a.conj_in) v.y = -v.y;
-    buf[0][q * N + j] = v;
+    v[e] = src[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2) +
+               (int64_t)j * a.ijs];
   }
-  __syncthreads();
+}
 
+// Registers -> LDS tile (pencil q at q * mfma_row<N>()), conjugating for
+// the inverse.
+template <int N, int LM>
+__device__ __forceinline__ void mfma_to_lds(const float2 (&v)[mfma_tile_elems<N>() / kMfmaThreads],
+                                            float2* buf, int conj, int tid) {
+  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = tid + kMfmaThreads * e;
+    int q, j;
+    if constexpr (LM == MODE_ROW) { q = idx / N; j = idx % N; }
+    else { q = idx % T; j = idx / T; }
+    float2 x = v[e];
+    if (conj) x.y = -x.y;
+    buf[q * mfma_row<N>() + j] = x;
+  }
+}
+
+// All stages of the tile held in buf[0]; returns the buffer index holding
+// the result.  Radix-16 stages on the matrix cores, a leftover radix on the
+// vector ALUs; Stockham order as in the register kernels.
+template <int N, int PREC>
+__device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()],
+                                              const float2* ltw, const LeafA<PREC>& A,
+                                              int tid) {
+  constexpr int TE = mfma_tile_elems<N>();
+  constexpr int T = TE / N;
+  constexpr int RW = mfma_row<N>();
+  constexpr int S16 = mfma_stages<N>();
+  constexpr int REST = mfma_rest<N>();
+  constexpr int ROUNDS = TE / 16 / 256;  // 16-vector groups: 4 per wave per round
+  const int lane = tid & 63, wave = tid >> 6;
   int cur = 0;
   int NS = 1;
 #pragma unroll
@@ -217,7 +246,7 @@ fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
     const int h = lane >> 4, n = lane & 15;
     const int r0 = 8 * (h & 1);
     const bool imag = h >= 2;
-    const int stride = N / 16;              // butterflies per pencil
+    constexpr int stride = N / 16;  // butterflies per pencil
     const int twstep = N / (NS * 16);
 #pragma unroll
     for (int ro = 0; ro < ROUNDS; ++ro) {
@@ -230,7 +259,7 @@ fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int r = r0 + k;
-          float2 v = in[q * N + t + r * stride];
+          float2 v = in[q * RW + t + r * stride];
           if (NS > 1) v = cmul(v, ltw[tm * r * twstep]);
           xs[k] = imag ? v.y : v.x;
         }
@@ -240,7 +269,7 @@ fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int rp = 4 * h + i;
-          out[q * N + base + rp * NS] = make_float2(yr[i], yi[i]);
+          out[q * RW + base + rp * NS] = make_float2(yr[i], yi[i]);
         }
       }
     }
@@ -248,44 +277,108 @@ fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
     cur ^= 1;
     NS *= 16;
   }
-
   if constexpr (REST > 1) {  // last stage on the vector ALUs
     const float2* in = buf[cur];
     float2* out = buf[cur ^ 1];
     constexpr int BF = N / REST;  // butterflies per pencil
     const int twstep = N / (NS * REST);
-    for (int idx = tid; idx < T * BF; idx += NTHR) {
+    for (int idx = tid; idx < T * BF; idx += kMfmaThreads) {
       const int q = idx / BF, t = idx % BF;
       const int tm = t & (NS - 1);
       float2 v[REST];
 #pragma unroll
       for (int r = 0; r < REST; ++r) {
-        v[r] = in[q * N + t + r * BF];
+        v[r] = in[q * RW + t + r * BF];
         if (r > 0 && NS > 1) v[r] = cmul(v[r], ltw[tm * r * twstep]);
       }
       dft<REST>(v);
       const int base = (t / NS) * NS * REST + tm;
 #pragma unroll
-      for (int r = 0; r < REST; ++r) out[q * N + base + r * NS] = v[r];
+      for (int r = 0; r < REST; ++r) out[q * RW + base + r * NS] = v[r];
     }
     __syncthreads();
     cur ^= 1;
   }
+  return cur;
+}
 
-  // store the tile
-  const float2* res = buf[cur];
-#pragma unroll 4
-  for (int idx = tid; idx < TE; idx += NTHR) {
+// LDS result -> global, in the store mode's order.
+template <int N, int SM>
+__device__ __forceinline__ void mfma_store(const float2* res, float2* dst, const PassArgs& a,
+                                           int64_t tile, int tid) {
+  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = tid + kMfmaThreads * e;
     int q, k;
     if constexpr (SM == MODE_ROW) { q = idx / N; k = idx % N; }
     else { q = idx % T; k = idx / T; }
     const int64_t b = tile * T + q;
-    if (b < a.B) {
-      float2 v = res[q * N + k];
-      if (a.conj_out) v.y = -v.y;
-      float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
-      d[(int64_t)k * a.oks] = v;
-    }
+    float2 v = res[q * mfma_row<N>() + k];
+    if (a.conj_out) v.y = -v.y;
+    if (b < a.B)
+      dst[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2) + (int64_t)k * a.oks] =
+          v;
+  }
+}
+
+// One tile per workgroup: all loads of the tile are issued before any is
+// written to LDS, so a workgroup keeps 32 loads per thread in flight.
+template <int N, int LM, int SM, int PREC>
+__global__ void __launch_bounds__(kMfmaThreads)
+fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
+              const unsigned short* __restrict__ leaf, const PassArgs a) {
+  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+  __shared__ float2 buf[2][mfma_buf_elems<N>()];
+  __shared__ float2 ltw[N];
+  const int tid = threadIdx.x;
+  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
+  float2 v[EPT];
+  mfma_load<N, LM>(v, src, a, tile, tid);
+  for (int i = tid; i < N; i += kMfmaThreads) ltw[i] = tw[i];
+  LeafA<PREC> A;
+  A.load(leaf, tid & 63);
+  mfma_to_lds<N, LM>(v, buf[0], a.conj_in, tid);
+  __syncthreads();
+  const int cur = mfma_transform<N, PREC>(buf, ltw, A, tid);
+  mfma_store<N, SM>(buf[cur], dst, a, tile, tid);
+}
+
+// Persistent form: about one resident workgroup per CU walks the tiles
+// (w, w + G, ...; remapped per XCD).  The next tile's loads go out as soon
+// as the current tile is in LDS, so they are in flight during its matrix-
+// core stages and its stores.
+template <int N, int LM, int SM, int PREC>
+__global__ void __launch_bounds__(kMfmaThreads)
+fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restrict__ tw,
+                         const unsigned short* __restrict__ leaf, const PassArgs a) {
+  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+  __shared__ float2 buf[2][mfma_buf_elems<N>()];
+  __shared__ float2 ltw[N];
+  const int tid = threadIdx.x;
+  const int64_t ntiles = (a.B + T - 1) / T;
+  const int64_t G = gridDim.x;
+  int64_t w = blockIdx.x;
+  if (w >= ntiles) return;
+  const int64_t last = ntiles - 1;
+  float2 v[EPT];
+  mfma_load<N, LM>(v, src, a, tile_index(w, ntiles, a.xcd_remap), tid);
+  for (int i = tid; i < N; i += kMfmaThreads) ltw[i] = tw[i];
+  LeafA<PREC> A;
+  A.load(leaf, tid & 63);
+  while (true) {
+    mfma_to_lds<N, LM>(v, buf[0], a.conj_in, tid);
+    __syncthreads();
+    const int64_t wn = w + G;
+    // prefetch the next tile (past the end: the last tile again, in bounds)
+    mfma_load<N, LM>(v, src, a, tile_index(wn < last ? wn : last, ntiles, a.xcd_remap), tid);
+    const int cur = mfma_transform<N, PREC>(buf, ltw, A, tid);
+    mfma_store<N, SM>(buf[cur], dst, a, tile_index(w, ntiles, a.xcd_remap), tid);
+    __syncthreads();  // every read of the result buffer is done
+    w = wn;
+    if (w >= ntiles) break;
   }
 }
 
@@ -296,25 +389,53 @@ hipError_t launch_mfma(const PassArgs& a, const float2* src, float2* dst, const 
   const int64_t blocks = (a.B + T - 1) / T;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((fft_pass_mfma<N, LM, SM, PREC>), dim3((unsigned)blocks), dim3(256), 0,
-                     stream, src, dst, tw, reinterpret_cast<const unsigned short*>(leaf), a);
+  hipLaunchKernelGGL((fft_pass_mfma<N, LM, SM, PREC>), dim3((unsigned)blocks),
+                     dim3(kMfmaThreads), 0, stream, src, dst, tw,
+                     reinterpret_cast<const unsigned short*>(leaf), a);
   return hipGetLastError();
 }
 
 template <int N, int LM, int SM, int PREC>
+hipError_t launch_mfma_persistent(const PassArgs& a, const float2* src, float2* dst,
+                                  const float2* tw, const float2* leaf, hipStream_t stream) {
+  constexpr int T = mfma_tile_elems<N>() / N;
+  const int64_t tiles = (a.B + T - 1) / T;
+  if (tiles <= 0) return hipSuccess;
+  static int per_cu = -1;  // resident workgroups per CU for this kernel
+  if (per_cu < 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, fft_pass_mfma_persistent<N, LM, SM, PREC>, kMfmaThreads, 0) != hipSuccess)
+      return hipGetLastError();
+    per_cu = nb > 0 ? nb : 1;
+  }
+  int64_t grid = (int64_t)device_cu_count() * per_cu;
+  if (grid > tiles) grid = tiles;
+  hipLaunchKernelGGL((fft_pass_mfma_persistent<N, LM, SM, PREC>), dim3((unsigned)grid),
+                     dim3(kMfmaThreads), 0, stream, src, dst, tw,
+                     reinterpret_cast<const unsigned short*>(leaf), a);
+  return hipGetLastError();
+}
+
+template <int N, int LM, int SM, int PREC, int PERS>
 KernelInfo kernel_info_mfma() {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int LDS = (2 * mfma_tile_elems<N>() + N) * 8;
+  constexpr int LDS = (2 * mfma_buf_elems<N>() + N) * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(mfma_tile_elems<N>() % 4096 == 0, "rounds of 256 vectors");
-  return KernelInfo{N, T, LM, SM, 0, 256, LDS, &launch_mfma<N, LM, SM, PREC>, 0, 0, PREC};
+  return KernelInfo{N, T, LM, SM, 0, kMfmaThreads, LDS,
+                    PERS ? &launch_mfma_persistent<N, LM, SM, PREC> : &launch_mfma<N, LM, SM, PREC>,
+                    PERS, 0, PREC};
 }
 
 template <int N, int PREC>
 void add_mfma_kernels_prec(std::vector<KernelInfo>& v) {
-  v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_COL, PREC>());
-  v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_ROW, PREC>());
-  v.push_back(kernel_info_mfma<N, MODE_COL, MODE_COL, PREC>());
+  v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_COL, PREC, 0>());
+  v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_ROW, PREC, 0>());
+  v.push_back(kernel_info_mfma<N, MODE_COL, MODE_COL, PREC, 0>());
+  v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_COL, PREC, 1>());
+  v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_ROW, PREC, 1>());
+  v.push_back(kernel_info_mfma<N, MODE_COL, MODE_COL, PREC, 1>());
 }
 
 template <int N>

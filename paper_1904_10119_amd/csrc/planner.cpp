@@ -132,7 +132,7 @@ struct Builder {
     int leaf = 0;
     if (opt.precision != DFT3D_PREC_FP32 && !tw) {
       // split-precision leaves on the matrix cores where a kernel exists
-      k = find_mfma_kernel(n, lmode, smode, opt.precision);
+      k = find_mfma_kernel(n, lmode, smode, opt.precision, opt.persistent);
       if (k) leaf = opt.precision;
     }
     if (!k) k = pick_kernel(n, lmode, smode, tw, opt, total_points);

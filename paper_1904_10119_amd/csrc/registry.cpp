@@ -36,11 +36,15 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   return nullptr;
 }
 
-const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision) {
+const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
+                                   int persistent) {
+  const KernelInfo* other = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.n == n && k.lmode == lmode && k.smode == smode && k.precision == precision)
-      return &k;
-  return nullptr;
+    if (k.n == n && k.lmode == lmode && k.smode == smode && k.precision == precision) {
+      if (k.persistent == persistent) return &k;
+      other = &k;
+    }
+  return other;
 }
 
 int device_cu_count() {

@@ -97,3 +97,27 @@ def test_split_on_other_schedules(schedule):
     y = run(x, "bf16x6", schedule=schedule)
     ref = oracle.dft3d(x.astype(np.complex128), -1, "fft")
     assert oracle.rel_l2(y, ref) <= oracle.tol(x.size)
+
+
+@pytest.mark.parametrize("precision", ["bf16x6", "fp16x3"])
+@pytest.mark.parametrize("shape", [(16, 32, 64), (128, 2, 256), (4, 1024, 2),
+                                   (2, 2, 2048), (4096, 2, 2), (16, 2, 16), (8, 512, 8)])
+def test_one_tile_and_persistent_forms(precision, shape):
+    """The one-tile-per-workgroup and the persistent (prefetching) MFMA
+    kernels both meet the tolerance, also with ragged last tiles (shapes
+    with fewer pencils than a tile), forward and inverse."""
+    say("case mfma forms", precision, shape)
+    x = inputs.uniform_c64(shape, 34)
+    xt = torch.from_numpy(x).cuda()
+    for sign, inv in ((-1, False), (1, True)):
+        ref = oracle.dft3d(x.astype(np.complex128), sign, "fft")
+        outs = []
+        for pers in (0, 1):
+            p = dft3d.Plan(shape, "pencil", precision=precision, persistent=pers)
+            y = torch.empty_like(xt)
+            p.execute(xt, y, inverse=inv)
+            torch.cuda.synchronize()
+            outs.append(y.cpu().numpy())
+            p.close()
+            assert oracle.rel_l2(outs[-1], ref) <= oracle.tol(x.size), (pers, sign)
+        assert oracle.rel_l2(outs[0], outs[1]) <= oracle.tol(x.size)
