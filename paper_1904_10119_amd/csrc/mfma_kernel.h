@@ -179,21 +179,23 @@ template <int N> constexpr int mfma_row() { return N + 1; }
 template <int N> constexpr int mfma_buf_elems() {
   return (mfma_tile_elems<N>() / N) * mfma_row<N>();
 }
-constexpr int kMfmaThreads = 256;
+// Workgroup size: one 16-vector group per lane group and round; two waves
+// per SIMD for the 8192-element tiles.
+template <int N> constexpr int mfma_threads() { return mfma_tile_elems<N>() >= 8192 ? 512 : 256; }
 
 // Global -> registers: thread tid gets tile elements idx = tid + 256 e, as
 // (pencil q, element j) in the load mode's order (ROW: j fastest, COL: q
 // fastest), so a wavefront reads contiguous runs.  Pencils past the end of
 // a ragged last tile re-read the last pencil (in bounds, never stored).
 template <int N, int LM>
-__device__ __forceinline__ void mfma_load(float2 (&v)[mfma_tile_elems<N>() / kMfmaThreads],
+__device__ __forceinline__ void mfma_load(float2 (&v)[mfma_tile_elems<N>() / mfma_threads<N>()],
                                           const float2* src, const PassArgs& a, int64_t tile,
                                           int tid) {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + kMfmaThreads * e;
+    const int idx = tid + mfma_threads<N>() * e;
     int q, j;
     if constexpr (LM == MODE_ROW) { q = idx / N; j = idx % N; }
     else { q = idx % T; j = idx / T; }
@@ -207,13 +209,13 @@ __device__ __forceinline__ void mfma_load(float2 (&v)[mfma_tile_elems<N>() / kMf
 // Registers -> LDS tile (pencil q at q * mfma_row<N>()), conjugating for
 // the inverse.
 template <int N, int LM>
-__device__ __forceinline__ void mfma_to_lds(const float2 (&v)[mfma_tile_elems<N>() / kMfmaThreads],
+__device__ __forceinline__ void mfma_to_lds(const float2 (&v)[mfma_tile_elems<N>() / mfma_threads<N>()],
                                             float2* buf, int conj, int tid) {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + kMfmaThreads * e;
+    const int idx = tid + mfma_threads<N>() * e;
     int q, j;
     if constexpr (LM == MODE_ROW) { q = idx / N; j = idx % N; }
     else { q = idx % T; j = idx / T; }
@@ -235,7 +237,8 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
   constexpr int RW = mfma_row<N>();
   constexpr int S16 = mfma_stages<N>();
   constexpr int REST = mfma_rest<N>();
-  constexpr int ROUNDS = TE / 16 / 256;  // 16-vector groups: 4 per wave per round
+  constexpr int NTHR = mfma_threads<N>();
+  constexpr int ROUNDS = TE / 16 / NTHR;  // 16-vector groups: 4 per wave per round
   const int lane = tid & 63, wave = tid >> 6;
   int cur = 0;
   int NS = 1;
@@ -252,7 +255,7 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
     for (int ro = 0; ro < ROUNDS; ++ro) {
 #pragma unroll
       for (int g4 = 0; g4 < 4; ++g4) {
-        const int g = ro * 256 + wave * 64 + g4 * 16 + n;  // vector index
+        const int g = ro * NTHR + wave * 64 + g4 * 16 + n;  // vector index
         const int q = g / stride, t = g % stride;
         const int tm = t & (NS - 1);
         float xs[8];
@@ -282,7 +285,7 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
     float2* out = buf[cur ^ 1];
     constexpr int BF = N / REST;  // butterflies per pencil
     const int twstep = N / (NS * REST);
-    for (int idx = tid; idx < T * BF; idx += kMfmaThreads) {
+    for (int idx = tid; idx < T * BF; idx += NTHR) {
       const int q = idx / BF, t = idx % BF;
       const int tm = t & (NS - 1);
       float2 v[REST];
@@ -307,10 +310,10 @@ template <int N, int SM>
 __device__ __forceinline__ void mfma_store(const float2* res, float2* dst, const PassArgs& a,
                                            int64_t tile, int tid) {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + kMfmaThreads * e;
+    const int idx = tid + mfma_threads<N>() * e;
     int q, k;
     if constexpr (SM == MODE_ROW) { q = idx / N; k = idx % N; }
     else { q = idx % T; k = idx / T; }
@@ -326,17 +329,17 @@ __device__ __forceinline__ void mfma_store(const float2* res, float2* dst, const
 // One tile per workgroup: all loads of the tile are issued before any is
 // written to LDS, so a workgroup keeps 32 loads per thread in flight.
 template <int N, int LM, int SM, int PREC>
-__global__ void __launch_bounds__(kMfmaThreads)
+__global__ void __launch_bounds__(mfma_threads<N>())
 fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
               const unsigned short* __restrict__ leaf, const PassArgs a) {
-  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
   __shared__ float2 buf[2][mfma_buf_elems<N>()];
   __shared__ float2 ltw[N];
   const int tid = threadIdx.x;
   const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
   float2 v[EPT];
   mfma_load<N, LM>(v, src, a, tile, tid);
-  for (int i = tid; i < N; i += kMfmaThreads) ltw[i] = tw[i];
+  for (int i = tid; i < N; i += mfma_threads<N>()) ltw[i] = tw[i];
   LeafA<PREC> A;
   A.load(leaf, tid & 63);
   mfma_to_lds<N, LM>(v, buf[0], a.conj_in, tid);
@@ -350,11 +353,11 @@ fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
 // as the current tile is in LDS, so they are in flight during its matrix-
 // core stages and its stores.
 template <int N, int LM, int SM, int PREC>
-__global__ void __launch_bounds__(kMfmaThreads)
+__global__ void __launch_bounds__(mfma_threads<N>())
 fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restrict__ tw,
                          const unsigned short* __restrict__ leaf, const PassArgs a) {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / kMfmaThreads;
+  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
   __shared__ float2 buf[2][mfma_buf_elems<N>()];
   __shared__ float2 ltw[N];
   const int tid = threadIdx.x;
@@ -365,7 +368,7 @@ fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restric
   const int64_t last = ntiles - 1;
   float2 v[EPT];
   mfma_load<N, LM>(v, src, a, tile_index(w, ntiles, a.xcd_remap), tid);
-  for (int i = tid; i < N; i += kMfmaThreads) ltw[i] = tw[i];
+  for (int i = tid; i < N; i += mfma_threads<N>()) ltw[i] = tw[i];
   LeafA<PREC> A;
   A.load(leaf, tid & 63);
   while (true) {
@@ -390,7 +393,7 @@ hipError_t launch_mfma(const PassArgs& a, const float2* src, float2* dst, const 
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((fft_pass_mfma<N, LM, SM, PREC>), dim3((unsigned)blocks),
-                     dim3(kMfmaThreads), 0, stream, src, dst, tw,
+                     dim3(mfma_threads<N>()), 0, stream, src, dst, tw,
                      reinterpret_cast<const unsigned short*>(leaf), a);
   return hipGetLastError();
 }
@@ -405,14 +408,14 @@ hipError_t launch_mfma_persistent(const PassArgs& a, const float2* src, float2* 
   if (per_cu < 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, fft_pass_mfma_persistent<N, LM, SM, PREC>, kMfmaThreads, 0) != hipSuccess)
+            &nb, fft_pass_mfma_persistent<N, LM, SM, PREC>, mfma_threads<N>(), 0) != hipSuccess)
       return hipGetLastError();
     per_cu = nb > 0 ? nb : 1;
   }
   int64_t grid = (int64_t)device_cu_count() * per_cu;
   if (grid > tiles) grid = tiles;
   hipLaunchKernelGGL((fft_pass_mfma_persistent<N, LM, SM, PREC>), dim3((unsigned)grid),
-                     dim3(kMfmaThreads), 0, stream, src, dst, tw,
+                     dim3(mfma_threads<N>()), 0, stream, src, dst, tw,
                      reinterpret_cast<const unsigned short*>(leaf), a);
   return hipGetLastError();
 }
@@ -422,8 +425,8 @@ KernelInfo kernel_info_mfma() {
   constexpr int T = mfma_tile_elems<N>() / N;
   constexpr int LDS = (2 * mfma_buf_elems<N>() + N) * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
-  static_assert(mfma_tile_elems<N>() % 4096 == 0, "rounds of 256 vectors");
-  return KernelInfo{N, T, LM, SM, 0, kMfmaThreads, LDS,
+  static_assert(mfma_tile_elems<N>() % (16 * mfma_threads<N>()) == 0, "whole rounds");
+  return KernelInfo{N, T, LM, SM, 0, mfma_threads<N>(), LDS,
                     PERS ? &launch_mfma_persistent<N, LM, SM, PREC> : &launch_mfma<N, LM, SM, PREC>,
                     PERS, 0, PREC};
 }
