@@ -247,8 +247,10 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
     const float2* in = buf[cur];
     float2* out = buf[cur ^ 1];
     const int h = lane >> 4, n = lane & 15;
-    const int r0 = 8 * (h & 1);
-    const bool imag = h >= 2;
+    // lanes l and l + 32 feed the same eight rows of vector n (real parts
+    // in lane l, imaginary parts in lane l + 32); each reads and twiddles
+    // four of them and the halves are exchanged across the 32-lane boundary
+    const int rb = 8 * (h & 1) + 4 * (lane >> 5);
     constexpr int stride = N / 16;  // butterflies per pencil
     const int twstep = N / (NS * 16);
 #pragma unroll
@@ -260,11 +262,17 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
         const int tm = t & (NS - 1);
         float xs[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int r = r0 + k;
+        for (int k = 0; k < 4; ++k) {
+          const int r = rb + k;
           float2 v = in[q * RW + t + r * stride];
           if (NS > 1) v = cmul(v, ltw[tm * r * twstep]);
-          xs[k] = imag ? v.y : v.x;
+          // lane < 32 keeps its real part and gets the partner's; lane >= 32
+          // gets the partner's imaginary part and keeps its own
+          const auto sw = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v.x),
+                                                           __builtin_bit_cast(unsigned, v.y),
+                                                           false, false);
+          xs[k] = __builtin_bit_cast(float, (unsigned)sw[0]);
+          xs[4 + k] = __builtin_bit_cast(float, (unsigned)sw[1]);
         }
         f32x4_t yr, yi;
         leaf16<PREC>(A, xs, yr, yi);
