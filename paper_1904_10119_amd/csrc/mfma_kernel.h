@@ -173,9 +173,15 @@ template <int N> constexpr int mfma_rest() {
 }
 // Elements per tile: T = tile / N pencils.
 template <int N> constexpr int mfma_tile_elems() { return N >= 2048 ? 4096 : 8192; }
-// LDS row stride of a pencil: one pad element so that consecutive pencils
-// (the COL-mode staging writes and reads) start in different banks.
-template <int N> constexpr int mfma_row() { return N + 1; }
+// LDS layout of a tile: element x of pencil q at q * mfma_row + x + x / 32
+// (one pad element per 32, so the stride-16 Stockham writes and the
+// stride-N/16 row reads spread over the banks), with one more pad element
+// per pencil so that consecutive pencils (COL-mode staging) start in
+// different banks.
+template <int N> constexpr int mfma_row() { return N + N / 32 + 1; }
+template <int N> __device__ __forceinline__ int mfma_lds(int q, int x) {
+  return q * mfma_row<N>() + x + (x >> 5);
+}
 template <int N> constexpr int mfma_buf_elems() {
   return (mfma_tile_elems<N>() / N) * mfma_row<N>();
 }
@@ -221,7 +227,7 @@ __device__ __forceinline__ void mfma_to_lds(const float2 (&v)[mfma_tile_elems<N>
     else { q = idx % T; j = idx / T; }
     float2 x = v[e];
     if (conj) x.y = -x.y;
-    buf[q * mfma_row<N>() + j] = x;
+    buf[mfma_lds<N>(q, j)] = x;
   }
 }
 
@@ -234,7 +240,6 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
                                               int tid) {
   constexpr int TE = mfma_tile_elems<N>();
   constexpr int T = TE / N;
-  constexpr int RW = mfma_row<N>();
   constexpr int S16 = mfma_stages<N>();
   constexpr int REST = mfma_rest<N>();
   constexpr int NTHR = mfma_threads<N>();
@@ -264,7 +269,7 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int r = rb + k;
-          float2 v = in[q * RW + t + r * stride];
+          float2 v = in[mfma_lds<N>(q, t + r * stride)];
           if (NS > 1) v = cmul(v, ltw[tm * r * twstep]);
           // lane < 32 keeps its real part and gets the partner's; lane >= 32
           // gets the partner's imaginary part and keeps its own
@@ -280,7 +285,7 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int rp = 4 * h + i;
-          out[q * RW + base + rp * NS] = make_float2(yr[i], yi[i]);
+          out[mfma_lds<N>(q, base + rp * NS)] = make_float2(yr[i], yi[i]);
         }
       }
     }
@@ -299,13 +304,13 @@ __device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()]
       float2 v[REST];
 #pragma unroll
       for (int r = 0; r < REST; ++r) {
-        v[r] = in[q * RW + t + r * BF];
+        v[r] = in[mfma_lds<N>(q, t + r * BF)];
         if (r > 0 && NS > 1) v[r] = cmul(v[r], ltw[tm * r * twstep]);
       }
       dft<REST>(v);
       const int base = (t / NS) * NS * REST + tm;
 #pragma unroll
-      for (int r = 0; r < REST; ++r) out[q * RW + base + r * NS] = v[r];
+      for (int r = 0; r < REST; ++r) out[mfma_lds<N>(q, base + r * NS)] = v[r];
     }
     __syncthreads();
     cur ^= 1;
@@ -326,7 +331,7 @@ __device__ __forceinline__ void mfma_store(const float2* res, float2* dst, const
     if constexpr (SM == MODE_ROW) { q = idx / N; k = idx % N; }
     else { q = idx % T; k = idx / T; }
     const int64_t b = tile * T + q;
-    float2 v = res[q * mfma_row<N>() + k];
+    float2 v = res[mfma_lds<N>(q, k)];
     if (a.conj_out) v.y = -v.y;
     if (b < a.B)
       dst[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2) + (int64_t)k * a.oks] =

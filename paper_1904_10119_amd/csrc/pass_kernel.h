@@ -63,6 +63,14 @@ DFT3D_BLOCKING_LOW(2048, 16, 16, 16, 8)
 DFT3D_BLOCKING_LOW(4096, 16, 16, 16, 16)
 #undef DFT3D_BLOCKING_LOW
 
+// Blocking with 64 elements per thread for the persistent 2048 kernel: a
+// tile of 8 pencils runs on 256 threads (one wave per SIMD), whose register
+// budget holds the current and the prefetched tile without scratch.
+template <int N> struct BlockingWide;
+template <> struct BlockingWide<2048> {
+  static constexpr int E = 64, R0 = 64, R1 = 32, R2 = 1;
+};
+
 template <class BL> constexpr int num_stages() {
   return BL::R1 == 1 ? 1 : (BL::R2 == 1 ? 2 : 3);
 }

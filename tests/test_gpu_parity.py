@@ -155,18 +155,23 @@ def test_execute_rejects_aliasing_and_bad_sign():
     p.close()
 
 
-@pytest.mark.parametrize("shape", [(1024, 16, 512), (512, 1024, 8), (64, 1024, 64)])
+@pytest.mark.parametrize("shape", [(1024, 16, 512), (512, 1024, 8), (64, 1024, 64),
+                                   (2048, 8, 16), (16, 2048, 8), (4, 4, 2048)])
 @pytest.mark.parametrize("schedule", ["pencil", "slab"])
 def test_persistent_matches_one_tile_per_workgroup(shape, schedule):
     """The persistent prefetching kernels and the one-tile-per-workgroup
     kernels both meet the oracle tolerance and agree with each other (the
     compiler may contract the same butterflies differently, so they are not
-    compared bit for bit)."""
+    compared bit for bit).  Streaming accesses are forced on so that the
+    persistent kernels run at these sizes too."""
     x = inputs.uniform_c64(shape, 26)
     xt = torch.from_numpy(x).cuda()
     outs = []
     for pers in (0, 1):
-        p = dft3d.Plan(shape, schedule, persistent=pers)
+        d = dft3d.describe(shape, schedule, persistent=pers, nontemporal=1)
+        used = [q["persistent"] for q in d["passes"] if q["n"] in (512, 1024, 2048)]
+        assert used and all(u == pers for u in used), (pers, used)
+        p = dft3d.Plan(shape, schedule, persistent=pers, nontemporal=1)
         y = torch.empty_like(xt)
         p.execute(xt, y)
         torch.cuda.synchronize()
