@@ -10,8 +10,10 @@
 // and the products of low combined order are accumulated, smallest first,
 // which recovers FP32-level accuracy from 8- or 11-bit significands.  A
 // leftover radix-2/4/8 stage and every twiddle run in FP32 on the vector
-// ALUs.  The tile lives in LDS between stages (ping-pong buffers); the
-// persistent form loads the next tile into registers meanwhile.
+// ALUs.  The first stage takes its operands straight from the registers
+// the tile was loaded into, later stages ping-pong through LDS, and a
+// leftover radix writes straight to global memory; the persistent form
+// loads the next tile into registers meanwhile.
 //
 // Operand lane layout of the 16x16x32 MFMA (checked on gfx950): lane l
 // holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i < 8, and
@@ -185,192 +187,216 @@ template <int N> __device__ __forceinline__ int mfma_lds(int q, int x) {
 template <int N> constexpr int mfma_buf_elems() {
   return (mfma_tile_elems<N>() / N) * mfma_row<N>();
 }
-// Workgroup size: one 16-vector group per lane group and round; two waves
-// per SIMD for the 8192-element tiles.
-template <int N> constexpr int mfma_threads() { return mfma_tile_elems<N>() >= 8192 ? 512 : 256; }
+// Workgroup size: one 16-vector group per lane group, so one round of
+// 16-vector groups covers the tile (two waves per SIMD for 8192 points).
+template <int N> constexpr int mfma_threads() { return mfma_tile_elems<N>() / 16; }
+// Tile elements each lane holds for the first stage (4 groups x 4 rows).
+constexpr int kMfmaRegs = 16;
 
-// Global -> registers: thread tid gets tile elements idx = tid + 256 e, as
-// (pencil q, element j) in the load mode's order (ROW: j fastest, COL: q
-// fastest), so a wavefront reads contiguous runs.  Pencils past the end of
-// a ragged last tile re-read the last pencil (in bounds, never stored).
-template <int N, int LM>
-__device__ __forceinline__ void mfma_load(float2 (&v)[mfma_tile_elems<N>() / mfma_threads<N>()],
-                                          const float2* src, const PassArgs& a, int64_t tile,
-                                          int tid) {
+// Vector (pencil q, butterfly t) of a 16-vector group index g.  For the
+// first stage the load mode's contiguous index runs fastest across lanes
+// (ROW: t, COL: q), so the operands come straight from global memory in
+// 128-byte runs; later stages use the ROW order.
+template <int N, int MODE>
+__device__ __forceinline__ void mfma_vec(int g, int& q, int& t) {
+  constexpr int stride = N / 16;
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
+  if constexpr (MODE == MODE_ROW) { q = g / stride; t = g % stride; }
+  else { q = g % T; t = g / T; }
+}
+
+// Global -> registers, already in first-stage operand order: lane (wave,
+// n, h, half) gets rows rb .. rb + 3 (rb = 8 (h & 1) + 4 half) of vector
+// g = wave * 64 + g4 * 16 + n for g4 < 4.  Pencils past the end of a ragged
+// last tile re-read the last pencil (in bounds, never stored).
+template <int N, int LM>
+__device__ __forceinline__ void mfma_load(float2 (&v)[kMfmaRegs], const float2* src,
+                                          const PassArgs& a, int64_t tile, int tid) {
+  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int stride = N / 16;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rb = 8 * ((lane >> 4) & 1) + 4 * (lane >> 5);
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + mfma_threads<N>() * e;
-    int q, j;
-    if constexpr (LM == MODE_ROW) { q = idx / N; j = idx % N; }
-    else { q = idx % T; j = idx / T; }
+  for (int g4 = 0; g4 < 4; ++g4) {
+    int q, t;
+    mfma_vec<N, LM>(wave * 64 + g4 * 16 + (lane & 15), q, t);
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
-    v[e] = src[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2) +
-               (int64_t)j * a.ijs];
-  }
-}
-
-// Registers -> LDS tile (pencil q at q * mfma_row<N>()), conjugating for
-// the inverse.
-template <int N, int LM>
-__device__ __forceinline__ void mfma_to_lds(const float2 (&v)[mfma_tile_elems<N>() / mfma_threads<N>()],
-                                            float2* buf, int conj, int tid) {
-  constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
+    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + mfma_threads<N>() * e;
-    int q, j;
-    if constexpr (LM == MODE_ROW) { q = idx / N; j = idx % N; }
-    else { q = idx % T; j = idx / T; }
-    float2 x = v[e];
-    if (conj) x.y = -x.y;
-    buf[mfma_lds<N>(q, j)] = x;
+    for (int k = 0; k < 4; ++k) v[g4 * 4 + k] = s[(int64_t)(t + (rb + k) * stride) * a.ijs];
   }
 }
 
-// All stages of the tile held in buf[0]; returns the buffer index holding
-// the result.  Radix-16 stages on the matrix cores, a leftover radix on the
-// vector ALUs; Stockham order as in the register kernels.
+// One radix-16 stage for the lane's four 16-vector groups.  x[g4 * 4 + k]
+// is row rb + k of group g4's vector, already twiddled; lanes l and l + 32
+// hold the same vector's rows 0..3 and 4..7 (of the lane group's eight) and
+// exchange halves across the 32-lane boundary so that lane l feeds real
+// parts and lane l + 32 imaginary parts to the matrix cores.
 template <int N, int PREC>
-__device__ __forceinline__ int mfma_transform(float2 (*buf)[mfma_buf_elems<N>()],
-                                              const float2* ltw, const LeafA<PREC>& A,
-                                              int tid) {
-  constexpr int TE = mfma_tile_elems<N>();
-  constexpr int T = TE / N;
-  constexpr int S16 = mfma_stages<N>();
-  constexpr int REST = mfma_rest<N>();
-  constexpr int NTHR = mfma_threads<N>();
-  constexpr int ROUNDS = TE / 16 / NTHR;  // 16-vector groups: 4 per wave per round
-  const int lane = tid & 63, wave = tid >> 6;
-  int cur = 0;
-  int NS = 1;
+__device__ __forceinline__ void mfma_leaf_store(const float2 (&x)[4], const LeafA<PREC>& A,
+                                                float2* out, int q, int t, int NS, int lane) {
+  float xs[8];
 #pragma unroll
-  for (int st = 0; st < S16; ++st) {
+  for (int k = 0; k < 4; ++k) {
+    // lane < 32 keeps its real part and gets the partner's; lane >= 32
+    // gets the partner's imaginary part and keeps its own
+    const auto sw = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x[k].x),
+                                                     __builtin_bit_cast(unsigned, x[k].y),
+                                                     false, false);
+    xs[k] = __builtin_bit_cast(float, (unsigned)sw[0]);
+    xs[4 + k] = __builtin_bit_cast(float, (unsigned)sw[1]);
+  }
+  f32x4_t yr, yi;
+  leaf16<PREC>(A, xs, yr, yi);
+  const int h = lane >> 4;
+  const int tm = t & (NS - 1);
+  const int base = (t / NS) * NS * 16 + tm;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    out[mfma_lds<N>(q, base + (4 * h + i) * NS)] = make_float2(yr[i], yi[i]);
+}
+
+// First stage from the registers mfma_load filled (conjugated for the
+// inverse), output to LDS buffer out.
+template <int N, int LM, int PREC>
+__device__ __forceinline__ void mfma_first_stage(const float2 (&v)[kMfmaRegs], float2* out,
+                                                 const LeafA<PREC>& A, int conj, int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int g4 = 0; g4 < 4; ++g4) {
+    int q, t;
+    mfma_vec<N, LM>(wave * 64 + g4 * 16 + (lane & 15), q, t);
+    float2 x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[k] = v[g4 * 4 + k];
+      if (conj) x[k].y = -x[k].y;
+    }
+    mfma_leaf_store<N, PREC>(x, A, out, q, t, 1, lane);
+  }
+}
+
+// The remaining radix-16 stages on LDS (ping-pong, starting from buffer 0);
+// returns the buffer index holding the result.
+template <int N, int PREC>
+__device__ __forceinline__ int mfma_later_stages(float2 (*buf)[mfma_buf_elems<N>()],
+                                                 const float2* ltw, const LeafA<PREC>& A,
+                                                 int tid) {
+  constexpr int S16 = mfma_stages<N>();
+  constexpr int stride = N / 16;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rb = 8 * ((lane >> 4) & 1) + 4 * (lane >> 5);
+  int cur = 0;
+  int NS = 16;
+#pragma unroll
+  for (int st = 1; st < S16; ++st) {
     const float2* in = buf[cur];
     float2* out = buf[cur ^ 1];
-    const int h = lane >> 4, n = lane & 15;
-    // lanes l and l + 32 feed the same eight rows of vector n (real parts
-    // in lane l, imaginary parts in lane l + 32); each reads and twiddles
-    // four of them and the halves are exchanged across the 32-lane boundary
-    const int rb = 8 * (h & 1) + 4 * (lane >> 5);
-    constexpr int stride = N / 16;  // butterflies per pencil
     const int twstep = N / (NS * 16);
 #pragma unroll
-    for (int ro = 0; ro < ROUNDS; ++ro) {
+    for (int g4 = 0; g4 < 4; ++g4) {
+      int q, t;
+      mfma_vec<N, MODE_ROW>(wave * 64 + g4 * 16 + (lane & 15), q, t);
+      const int tm = t & (NS - 1);
+      float2 x[4];
 #pragma unroll
-      for (int g4 = 0; g4 < 4; ++g4) {
-        const int g = ro * NTHR + wave * 64 + g4 * 16 + n;  // vector index
-        const int q = g / stride, t = g % stride;
-        const int tm = t & (NS - 1);
-        float xs[8];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int r = rb + k;
-          float2 v = in[mfma_lds<N>(q, t + r * stride)];
-          if (NS > 1) v = cmul(v, ltw[tm * r * twstep]);
-          // lane < 32 keeps its real part and gets the partner's; lane >= 32
-          // gets the partner's imaginary part and keeps its own
-          const auto sw = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v.x),
-                                                           __builtin_bit_cast(unsigned, v.y),
-                                                           false, false);
-          xs[k] = __builtin_bit_cast(float, (unsigned)sw[0]);
-          xs[4 + k] = __builtin_bit_cast(float, (unsigned)sw[1]);
-        }
-        f32x4_t yr, yi;
-        leaf16<PREC>(A, xs, yr, yi);
-        const int base = (t / NS) * NS * 16 + tm;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rp = 4 * h + i;
-          out[mfma_lds<N>(q, base + rp * NS)] = make_float2(yr[i], yi[i]);
-        }
+      for (int k = 0; k < 4; ++k) {
+        const int r = rb + k;
+        x[k] = cmul(in[mfma_lds<N>(q, t + r * stride)], ltw[tm * r * twstep]);
       }
+      mfma_leaf_store<N, PREC>(x, A, out, q, t, NS, lane);
     }
     __syncthreads();
     cur ^= 1;
     NS *= 16;
   }
-  if constexpr (REST > 1) {  // last stage on the vector ALUs
-    const float2* in = buf[cur];
-    float2* out = buf[cur ^ 1];
-    constexpr int BF = N / REST;  // butterflies per pencil
-    const int twstep = N / (NS * REST);
-    for (int idx = tid; idx < T * BF; idx += NTHR) {
-      const int q = idx / BF, t = idx % BF;
-      const int tm = t & (NS - 1);
-      float2 v[REST];
-#pragma unroll
-      for (int r = 0; r < REST; ++r) {
-        v[r] = in[mfma_lds<N>(q, t + r * BF)];
-        if (r > 0 && NS > 1) v[r] = cmul(v[r], ltw[tm * r * twstep]);
-      }
-      dft<REST>(v);
-      const int base = (t / NS) * NS * REST + tm;
-#pragma unroll
-      for (int r = 0; r < REST; ++r) out[mfma_lds<N>(q, base + r * NS)] = v[r];
-    }
-    __syncthreads();
-    cur ^= 1;
-  }
   return cur;
 }
 
-// LDS result -> global, in the store mode's order.
+// Last step: with a leftover radix, its butterflies read LDS and write
+// straight to global memory (lanes ordered by the store mode's contiguous
+// index); otherwise the result is copied out in the store mode's order.
 template <int N, int SM>
-__device__ __forceinline__ void mfma_store(const float2* res, float2* dst, const PassArgs& a,
-                                           int64_t tile, int tid) {
+__device__ __forceinline__ void mfma_finish(const float2* res, float2* dst, const float2* ltw,
+                                            const PassArgs& a, int64_t tile, int tid) {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
+  constexpr int NTHR = mfma_threads<N>();
+  constexpr int REST = mfma_rest<N>();
+  if constexpr (REST > 1) {
+    constexpr int BF = N / REST;  // butterflies per pencil == stride of the outputs
+    static_assert((T * BF) % NTHR == 0, "whole butterflies per thread");
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int idx = tid + mfma_threads<N>() * e;
-    int q, k;
-    if constexpr (SM == MODE_ROW) { q = idx / N; k = idx % N; }
-    else { q = idx % T; k = idx / T; }
-    const int64_t b = tile * T + q;
-    float2 v = res[mfma_lds<N>(q, k)];
-    if (a.conj_out) v.y = -v.y;
-    if (b < a.B)
-      dst[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2) + (int64_t)k * a.oks] =
-          v;
+    for (int c = 0; c < T * BF / NTHR; ++c) {
+      const int idx = tid + NTHR * c;
+      int q, t;
+      if constexpr (SM == MODE_ROW) { q = idx / BF; t = idx % BF; }
+      else { q = idx % T; t = idx / T; }
+      float2 v[REST];
+#pragma unroll
+      for (int r = 0; r < REST; ++r) {
+        v[r] = res[mfma_lds<N>(q, t + r * BF)];
+        if (r > 0) v[r] = cmul(v[r], ltw[t * r]);
+      }
+      dft<REST>(v);
+      const int64_t b = tile * T + q;
+      if (b < a.B) {
+        float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+#pragma unroll
+        for (int r = 0; r < REST; ++r) {
+          float2 o = v[r];
+          if (a.conj_out) o.y = -o.y;
+          d[(int64_t)(t + r * BF) * a.oks] = o;
+        }
+      }
+    }
+  } else {
+    constexpr int EPT = mfma_tile_elems<N>() / NTHR;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = tid + NTHR * e;
+      int q, k;
+      if constexpr (SM == MODE_ROW) { q = idx / N; k = idx % N; }
+      else { q = idx % T; k = idx / T; }
+      const int64_t b = tile * T + q;
+      float2 v = res[mfma_lds<N>(q, k)];
+      if (a.conj_out) v.y = -v.y;
+      if (b < a.B)
+        dst[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2) +
+            (int64_t)k * a.oks] = v;
+    }
   }
 }
 
-// One tile per workgroup: all loads of the tile are issued before any is
-// written to LDS, so a workgroup keeps 32 loads per thread in flight.
+// One tile per workgroup.
 template <int N, int LM, int SM, int PREC>
 __global__ void __launch_bounds__(mfma_threads<N>())
 fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
               const unsigned short* __restrict__ leaf, const PassArgs a) {
-  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
   __shared__ float2 buf[2][mfma_buf_elems<N>()];
   __shared__ float2 ltw[N];
   const int tid = threadIdx.x;
   const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
-  float2 v[EPT];
+  float2 v[kMfmaRegs];
   mfma_load<N, LM>(v, src, a, tile, tid);
   for (int i = tid; i < N; i += mfma_threads<N>()) ltw[i] = tw[i];
   LeafA<PREC> A;
   A.load(leaf, tid & 63);
-  mfma_to_lds<N, LM>(v, buf[0], a.conj_in, tid);
+  mfma_first_stage<N, LM, PREC>(v, buf[0], A, a.conj_in, tid);
   __syncthreads();
-  const int cur = mfma_transform<N, PREC>(buf, ltw, A, tid);
-  mfma_store<N, SM>(buf[cur], dst, a, tile, tid);
+  const int cur = mfma_later_stages<N, PREC>(buf, ltw, A, tid);
+  mfma_finish<N, SM>(buf[cur], dst, ltw, a, tile, tid);
 }
 
 // Persistent form: about one resident workgroup per CU walks the tiles
-// (w, w + G, ...; remapped per XCD).  The next tile's loads go out as soon
-// as the current tile is in LDS, so they are in flight during its matrix-
-// core stages and its stores.
+// (w, w + G, ...; remapped per XCD).  As soon as the first stage has
+// consumed the registers, the next tile's loads go out, so they are in
+// flight during the remaining stages and the stores.
 template <int N, int LM, int SM, int PREC>
 __global__ void __launch_bounds__(mfma_threads<N>())
 fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restrict__ tw,
                          const unsigned short* __restrict__ leaf, const PassArgs a) {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int EPT = mfma_tile_elems<N>() / mfma_threads<N>();
   __shared__ float2 buf[2][mfma_buf_elems<N>()];
   __shared__ float2 ltw[N];
   const int tid = threadIdx.x;
@@ -379,19 +405,20 @@ fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restric
   int64_t w = blockIdx.x;
   if (w >= ntiles) return;
   const int64_t last = ntiles - 1;
-  float2 v[EPT];
+  float2 v[kMfmaRegs];
   mfma_load<N, LM>(v, src, a, tile_index(w, ntiles, a.xcd_remap), tid);
   for (int i = tid; i < N; i += mfma_threads<N>()) ltw[i] = tw[i];
   LeafA<PREC> A;
   A.load(leaf, tid & 63);
+  __syncthreads();  // twiddles in LDS
   while (true) {
-    mfma_to_lds<N, LM>(v, buf[0], a.conj_in, tid);
+    mfma_first_stage<N, LM, PREC>(v, buf[0], A, a.conj_in, tid);
     __syncthreads();
     const int64_t wn = w + G;
     // prefetch the next tile (past the end: the last tile again, in bounds)
     mfma_load<N, LM>(v, src, a, tile_index(wn < last ? wn : last, ntiles, a.xcd_remap), tid);
-    const int cur = mfma_transform<N, PREC>(buf, ltw, A, tid);
-    mfma_store<N, SM>(buf[cur], dst, a, tile_index(w, ntiles, a.xcd_remap), tid);
+    const int cur = mfma_later_stages<N, PREC>(buf, ltw, A, tid);
+    mfma_finish<N, SM>(buf[cur], dst, ltw, a, tile_index(w, ntiles, a.xcd_remap), tid);
     __syncthreads();  // every read of the result buffer is done
     w = wn;
     if (w >= ntiles) break;
