@@ -133,32 +133,37 @@ def extras(x1024_host, args):
         p.close()
         return ms, n
 
-    # 64^3, pencil, forward and inverse: latency-bound (2 MiB)
+    # 64^3, forward and inverse: latency-bound (2 MiB).  Pencil (three
+    # passes) and auto (slab: fused plane pass + depth pass), each also
+    # captured once in a HIP graph (torch's capture) and replayed, which
+    # removes the per-call host overhead of the launches
     shape = (64, 64, 64)
     x = torch.from_numpy(inputs.uniform_c64(shape, 1)).cuda()
     y = torch.empty_like(x)
-    f, _ = plan_ms(shape, x, y, 200, schedule="pencil")
-    i, _ = plan_ms(shape, x, y, 200, inverse=True, schedule="pencil")
-    # the same forward captured once in a HIP graph (torch's capture) and
-    # replayed: the three pass launches without per-call host overhead
-    p = dft3d.Plan(shape, "pencil")
-    p.bind_workspace(x.device)
-    p.execute(x, y)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    cs = torch.cuda.Stream()
-    cs.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(cs):
-        with torch.cuda.graph(g, stream=cs):
-            for _ in range(20):
-                p.execute(x, y)
-    torch.cuda.current_stream().wait_stream(cs)
-    gr = timed(g.replay, 20) / 20
-    del g
-    p.close()
-    out["64^3 pencil"] = {"fwd_us": round(f * 1e3, 2), "inv_us": round(i * 1e3, 2),
-                          "fwd_graph_us": round(gr * 1e3, 2)}
-    log(f"bench: 64^3 {out['64^3 pencil']}")
+    small = {}
+    for sch in ("pencil", "auto"):
+        f, n = plan_ms(shape, x, y, 200, schedule=sch)
+        i, _ = plan_ms(shape, x, y, 200, inverse=True, schedule=sch)
+        p = dft3d.Plan(shape, sch)
+        p.bind_workspace(x.device)
+        p.execute(x, y)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            with torch.cuda.graph(g, stream=cs):
+                for _ in range(20):
+                    p.execute(x, y)
+        torch.cuda.current_stream().wait_stream(cs)
+        gr = timed(g.replay, 20) / 20
+        del g
+        p.close()
+        small[sch] = {"schedule": dft3d.describe(shape, sch)["schedule"], "passes": n,
+                      "fwd_us": round(f * 1e3, 2), "inv_us": round(i * 1e3, 2),
+                      "fwd_graph_us": round(gr * 1e3, 2)}
+    out["64^3"] = small
+    log(f"bench: 64^3 {small}")
 
     # 1024^3 under every schedule
     N = 1 << 30

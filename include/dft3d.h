@@ -18,8 +18,9 @@
  *               eqs. (13)-(17)): batched DFT_b over the stride-a subsequences
  *               with the twiddle of eq. (4) and an exchanging store, then
  *               batched DFT_a (Fig. 9, Section 3.2);
- *   AUTO        a per-shape choice (measured when an autotune cache entry
- *               exists, otherwise a fixed heuristic).
+ *   AUTO        a per-shape choice: the autotuner's measured choice when
+ *               one is recorded, otherwise SLAB below 256 MiB (arrays the
+ *               Infinity Cache can hold) and PENCIL from 256 MiB on.
  *
  * Data: complex64 = two IEEE binary32 (re, im), interleaved, 8 bytes per
  * point; C order (n0, n1, n2), n2 contiguous; device pointers, 16-byte
@@ -106,6 +107,10 @@ enum dft3d_option {
                                 where compiled (default 1) */
   DFT3D_OPT_SLAB_GROUP = 7,  /* slab: planes per row/column group, 0 = all
                                 planes, -1 = automatic (default) */
+  DFT3D_OPT_FUSED_PLANE = 8, /* slab, FP32: 1 = 2D DFT of each (n1, n2)
+                                plane in one pass when n1, n2 are in
+                                [16, 128] (the plane stays in LDS between
+                                rows and columns); default 1 */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

@@ -80,7 +80,7 @@ constexpr size_t kCacheMax = 8;
 
 bool batchable(const dft3d_plan_s* p) {
   for (const Pass& ps : p->passes) {
-    if (ps.k->n > kBatchMaxN || ps.k->post_twiddle) return false;
+    if (ps.k->n > kBatchMaxN || ps.k->post_twiddle || ps.k->plane_rows) return false;
     if (batch_tile_for(ps.k->n) == 0) return false;
   }
   return true;
@@ -164,7 +164,7 @@ BatchGraph* find_cached(dft3d_plan_s* const* plans, int count, int device) {
 
 }  // namespace
 
-int batch_execute(dft3d_plan_s* const* plans, const void* const* in, void* const* out,
+int batch_execute(dft3d_plan_s* const* given, const void* const* in, void* const* out,
                   int count, int sign, hipStream_t stream) {
   {  // the descriptor upload synchronises with the previous call: not capturable
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -174,6 +174,13 @@ int batch_execute(dft3d_plan_s* const* plans, const void* const* in, void* const
     }
     if (cs != hipStreamCaptureStatusNone) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
   }
+  // plans with fused plane passes run as their twins without them
+  std::vector<dft3d_plan_s*> views((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    views[i] = batch_view(given[i]);
+    if (!views[i]) return DFT3D_ERR_OUT_OF_MEMORY;
+  }
+  dft3d_plan_s* const* plans = views.data();
   bool all = true;
   for (int i = 0; i < count; ++i) {
     const int st = ensure_workspace(plans[i]);

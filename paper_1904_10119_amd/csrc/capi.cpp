@@ -163,6 +163,10 @@ int apply_option(Options& o, int key, int64_t value) {
       if (value < -1 || value > 4096) return DFT3D_ERR_INVALID_ARG;
       o.slab_group = (int)value;
       return DFT3D_OK;
+    case DFT3D_OPT_FUSED_PLANE:
+      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
+      o.fused_plane = (int)value;
+      return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
   }
@@ -171,6 +175,38 @@ int apply_option(Options& o, int key, int64_t value) {
 }  // namespace
 
 namespace dft3d {
+void destroy_twin(dft3d_plan_s* p) {
+  if (!p->batch_twin) return;
+  batch_forget_plan(p->batch_twin);
+  free_workspace(p->batch_twin);
+  free_tables(p->batch_twin);
+  delete p->batch_twin;
+  p->batch_twin = nullptr;
+}
+
+dft3d_plan_s* batch_view(dft3d_plan_s* p) {
+  bool plane = false;
+  for (const Pass& ps : p->passes) plane = plane || ps.k->plane_rows > 0;
+  if (!plane) return p;
+  if (p->batch_twin) return p->batch_twin;
+  dft3d_plan_s* t = new (std::nothrow) dft3d_plan_s();
+  if (!t) return nullptr;
+  for (int d = 0; d < 3; ++d) t->n[d] = p->n[d];
+  t->schedule = p->schedule;
+  t->layout = p->layout;
+  t->opt = p->opt;
+  t->opt.fused_plane = 0;
+  t->device = p->device;
+  t->tuned = p->tuned;
+  if (rebuild(t) != DFT3D_OK) {
+    free_tables(t);
+    delete t;
+    return nullptr;
+  }
+  p->batch_twin = t;
+  return t;
+}
+
 int ensure_workspace(dft3d_plan_s* p) {
   if (p->ws_need > 0 && (!p->ws || p->ws_bytes < p->ws_need)) {
     if (!p->ws_owned && p->ws) return DFT3D_ERR_WORKSPACE_TOO_SMALL;
@@ -281,6 +317,7 @@ int dft3d_plan_set_option(dft3d_plan_t p, int key, int64_t value) {
   if (st != DFT3D_OK) return st;
   st = rebuild(p);
   if (st != DFT3D_OK) p->opt = saved;  // previous pass list stays in force
+  else destroy_twin(p);                  // rebuilt from the new options on demand
   return st;
 }
 
@@ -294,6 +331,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_NONTEMPORAL: *value = p->opt.nontemporal; break;
     case DFT3D_OPT_PERSISTENT: *value = p->opt.persistent; break;
     case DFT3D_OPT_SLAB_GROUP: *value = p->opt.slab_group; break;
+    case DFT3D_OPT_FUSED_PLANE: *value = p->opt.fused_plane; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }
@@ -378,6 +416,7 @@ int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
 
 int dft3d_destroy(dft3d_plan_t p) {
   if (!p) return DFT3D_OK;
+  destroy_twin(p);
   batch_forget_plan(p);
   free_workspace(p);
   free_tables(p);

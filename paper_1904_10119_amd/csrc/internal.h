@@ -52,12 +52,15 @@ struct KernelInfo {
   int persistent;    // 1: grid of resident workgroups walking all tiles
   int nontemporal;   // 1: streaming (non-temporal) loads and stores
   int precision = 0; // DFT3D_PREC_*: FP32 butterflies or split MFMA leaves
+  int plane_rows = 0; // > 0: fused 2D DFT of (plane_rows, n) planes, one per workgroup
 };
 
 // All compiled pass kernels.
 const std::vector<KernelInfo>& kernel_registry();
 const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle,
                               int persistent, int nontemporal);
+// The fused plane kernel for (n1, n2) planes, if compiled.
+const KernelInfo* find_plane_kernel(int n1, int n2);
 // The split-precision MFMA pass kernel for a length and layout, if any
 // (the persistent form when asked for and compiled, else the other form).
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
@@ -93,6 +96,7 @@ struct Options {
   int nontemporal = 2; // 0 off, 1 on, 2 on for arrays above kStreamBytes
   int persistent = 1;  // use the persistent form where one exists
   int slab_group = -1; // slab: planes per row/column group (0 = all, -1 = auto)
+  int fused_plane = 1; // slab: one fused 2D pass for planes that fit in LDS
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success
@@ -135,6 +139,9 @@ struct dft3d_plan_s {
   bool ws_owned = false;
   uint64_t uid = 0;  // changes whenever the pass list is rebuilt
   int tuned = -1;    // AUTO plans: schedule chosen by the autotuner, -1 none
+  // Plans with fused plane passes: the same transform without them, built on
+  // first batched use (the batched kernel runs one-dimensional passes only).
+  dft3d_plan_s* batch_twin = nullptr;
 };
 
 namespace dft3d {
@@ -146,4 +153,7 @@ int batch_execute(dft3d_plan_s* const* plans, const void* const* in,
 void batch_forget_plan(const dft3d_plan_s* p);
 // AUTO plans: apply the autotuner's recorded choice for the shape, if any.
 void tune_lookup(dft3d_plan_s* p);
+// The plan whose passes the batched kernel runs for p: p itself, or its
+// twin without fused plane passes (created on first use; null if that fails).
+dft3d_plan_s* batch_view(dft3d_plan_s* p);
 }  // namespace dft3d

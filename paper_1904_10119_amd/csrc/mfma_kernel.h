@@ -174,7 +174,7 @@ template <int N> constexpr int mfma_rest() {
   return n;
 }
 // Elements per tile: T = tile / N pencils.
-template <int N> constexpr int mfma_tile_elems() { return N >= 2048 ? 4096 : 8192; }
+template <int N> constexpr int mfma_tile_elems() { return N >= 4096 ? 4096 : 8192; }
 // LDS layout of a tile: element x of pencil q at q * mfma_row + x + x / 32
 // (one pad element per 32, so the stride-16 Stockham writes and the
 // stride-N/16 row reads spread over the banks), with one more pad element

@@ -13,8 +13,10 @@
 //     stride-A subsequences x[l + A k] of each residue l, times w_n^{l k'},
 //     stored exchanged as T0[k'][l]; V2 = DFT_A over l, stored at
 //     y[k' + Bf l'].
-//   AUTO: the pencil rotation, with axes longer than a threshold split into
-//     V1 + V2 as in the volumetric schedule.
+//   AUTO: below 256 MiB (arrays the Infinity Cache can hold between
+//     passes) SLAB, whose planes of up to 128 x 128 points take one fused
+//     pass; above it the pencil rotation, with axes longer than a threshold
+//     split into V1 + V2 as in the volumetric schedule.
 //   SHUFFLED layout (volumetric only; Section 2.4, Section 3.2): the forward
 //     transform leaves out the final digit exchange of every split axis, so
 //     natural entry y[k' + Bf l'] stays at position l' + A k' (V2 writes in
@@ -91,7 +93,7 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
   const int nt = order[nchoice - 1].nt;
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw &&
-        k.persistent == 0 && k.nontemporal == nt)
+        k.persistent == 0 && k.nontemporal == nt && k.precision == 0 && k.plane_rows == 0)
       return &k;
   return nullptr;
 }
@@ -154,6 +156,22 @@ struct Builder {
       p.args.res_mask = res_mask;
       p.args.twp_mask = twp_len - 1;
     }
+    p.label = label;
+    passes.push_back(p);
+  }
+
+  // Fused 2D DFT of n0 contiguous (n1, n2) planes, in layout.
+  void add_plane(const KernelInfo* k, int64_t n0, int64_t n1, int64_t n2,
+                 const std::string& label) {
+    Pass p;
+    p.k = k;
+    Field f[1] = {{n0, n1 * n2, n1 * n2}};
+    set_fields(p.args, f, 1);
+    p.args.ijs = 1;
+    p.args.oks = 1;
+    p.args.xcd_remap = 0;
+    p.tw_len = n2;   // row roots
+    p.twp_len = n1;  // column roots
     p.label = label;
     passes.push_back(p);
   }
@@ -298,7 +316,8 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
   Builder b{opt, passes, total};
   resolved = schedule;
   if (schedule == DFT3D_SCHED_AUTO)
-    resolved = shuffled ? DFT3D_SCHED_VOLUMETRIC : DFT3D_SCHED_PENCIL;
+    resolved = shuffled ? DFT3D_SCHED_VOLUMETRIC
+                        : (total * 8 < kStreamBytes ? DFT3D_SCHED_SLAB : DFT3D_SCHED_PENCIL);
   // Untuned AUTO splits only 4096-long axes (a 4096 pencil leaves tiles of
   // four pencils); measured at 2048x1024x512, the 2048 pass beats its split.
   const int64_t split_max =
@@ -328,7 +347,19 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
     if (group == 0 || group > n[0]) group = n[0];
     while (n[0] % group) --group;
     char lab[64];
-    for (int64_t g0 = 0; g0 < n[0]; g0 += group) {
+    // planes that fit in one workgroup's LDS: rows and columns in one pass
+    const KernelInfo* pk = (opt.fused_plane && opt.precision == DFT3D_PREC_FP32 &&
+                            group == n[0])
+                               ? find_plane_kernel((int)n[1], (int)n[2])
+                               : nullptr;
+    if (pk) {
+      std::snprintf(lab, sizeof lab, "slab.plane DFT%lldx%lld planes %lld", (long long)n[1],
+                    (long long)n[2], (long long)n[0]);
+      b.add_plane(pk, n[0], n[1], n[2], lab);
+      passes.back().src = BUF_IN;
+      passes.back().dst = BUF_OUT;
+    }
+    for (int64_t g0 = 0; g0 < n[0] && !pk; g0 += group) {
       {
         Field f[1] = {{group * n[1], n[2], n[2]}};
         std::snprintf(lab, sizeof lab, "slab.rows DFT%lld planes %lld+%lld", (long long)n[2],
@@ -398,6 +429,7 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << (p.k->smode == MODE_ROW ? "row" : "col") << "\",\"post_twiddle\":"
        << p.k->post_twiddle << ",\"persistent\":" << p.k->persistent
        << ",\"nontemporal\":" << p.k->nontemporal << ",\"precision\":" << p.k->precision
+       << ",\"plane_rows\":" << p.k->plane_rows
        << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""

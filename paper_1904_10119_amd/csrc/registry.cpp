@@ -10,6 +10,7 @@ void register_kernels_big(std::vector<KernelInfo>& v);
 void register_kernels_mfma_a(std::vector<KernelInfo>& v);
 void register_kernels_mfma_b(std::vector<KernelInfo>& v);
 void register_kernels_mfma_c(std::vector<KernelInfo>& v);
+void register_kernels_plane(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -21,6 +22,7 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_mfma_a(v);
     register_kernels_mfma_b(v);
     register_kernels_mfma_c(v);
+    register_kernels_plane(v);
     return v;
   }();
   return table;
@@ -31,8 +33,14 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
-        k.nontemporal == nontemporal && k.precision == 0)
+        k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0)
       return &k;
+  return nullptr;
+}
+
+const KernelInfo* find_plane_kernel(int n1, int n2) {
+  for (const KernelInfo& k : kernel_registry())
+    if (k.plane_rows == n1 && k.n == n2) return &k;
   return nullptr;
 }
 

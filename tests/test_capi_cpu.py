@@ -99,7 +99,8 @@ def check_chain(d, shape):
             # only layout-preserving passes may run in place
             assert p["load"] == p["store"] and p["post_twiddle"] == 0
         assert p["threads"] <= 1024 and p["lds_bytes"] <= 160 * 1024
-        assert p["pencils"] * p["n"] == n
+        # a fused plane pass covers plane_rows x n points per work item
+        assert p["pencils"] * p["n"] * max(1, p["plane_rows"]) == n
     uses_ws = any("ws" in (p["src"], p["dst"]) for p in passes)
     assert d["workspace_bytes"] == (8 * n if uses_ws else 0)
 
@@ -133,10 +134,23 @@ def test_auto_splits_long_axes():
     # untuned auto splits only 4096-long axes; split_max lowers the bar
     d = dft3d.describe((2048, 1024, 512), "auto")
     assert [p["n"] for p in d["passes"]] == [512, 1024, 2048]
-    d = dft3d.describe((4096, 8, 16), "auto")
-    assert [p["n"] for p in d["passes"]] == [16, 8, 64, 64]
+    d = dft3d.describe((4096, 128, 64), "auto")
+    assert [p["n"] for p in d["passes"]] == [64, 128, 64, 64]
     d = dft3d.describe((2048, 1024, 512), "auto", split_max=1024)
     assert [p["n"] for p in d["passes"]] == [512, 1024, 32, 64]
+
+
+def test_auto_uses_slab_below_the_cache_size():
+    # below 256 MiB: slab (planes up to 128 x 128 fused into one pass)
+    d = dft3d.describe((64, 64, 64), "auto")
+    assert d["schedule"] == "slab" and len(d["passes"]) == 2
+    d = dft3d.describe((256, 256, 256), "auto")
+    assert d["schedule"] == "slab" and len(d["passes"]) == 3
+    d = dft3d.describe((4096, 8, 16), "auto")
+    assert d["schedule"] == "slab"
+    # from 256 MiB on: pencil
+    assert dft3d.describe((512, 512, 128), "auto")["schedule"] == "pencil"
+    assert dft3d.describe((1024, 1024, 1024), "auto")["schedule"] == "pencil"
 
 
 def test_split_precision_uses_mfma_leaves_where_available():

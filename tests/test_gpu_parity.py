@@ -254,3 +254,33 @@ def test_autotune_records_choice_for_auto_plans(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert oracle.rel_l2(y.cpu().numpy(), ref_fftn(x, -1)) <= oracle.tol(x.size)
     p.close()
+
+
+@pytest.mark.parametrize("n1", [16, 32, 64, 128])
+@pytest.mark.parametrize("n2", [16, 32, 64, 128])
+def test_slab_fused_plane_kernel(n1, n2):
+    """Every fused plane shape: forward and inverse against the oracle, and
+    against the unfused row + column passes."""
+    shape = (4, n1, n2)
+    say("case fused plane", shape)
+    x = inputs.uniform_c64(shape, 29)
+    d = dft3d.describe(shape, "slab")
+    assert d["passes"][0]["plane_rows"] == n1 and len(d["passes"]) == 2
+    for sign, inv in ((-1, False), (1, True)):
+        y = gpu_fftn(x, "slab", inverse=inv)
+        assert oracle.rel_l2(y, ref_fftn(x, sign)) <= oracle.tol(x.size), (sign,)
+        y0 = gpu_fftn(x, "slab", inverse=inv, fused_plane=0)
+        assert oracle.rel_l2(y, y0) <= oracle.tol(x.size)
+
+
+def test_batched_runs_fused_plane_plans_as_twins():
+    """Batched execution of slab plans whose planes are fused: the batch
+    runs their one-dimensional twins and matches single execution."""
+    shapes = [(64, 64, 64), (32, 128, 16), (16, 16, 16), (128, 32, 64)]
+    xs = [inputs.uniform_c64(s, 60 + i) for i, s in enumerate(shapes)]
+    xt = [torch.from_numpy(x).cuda() for x in xs]
+    for inv, sign in ((False, -1), (True, 1)):
+        ys = dft3d.fftn_batched(xt, schedule="slab", inverse=inv)
+        torch.cuda.synchronize()
+        for x, y in zip(xs, ys):
+            assert oracle.rel_l2(y.cpu().numpy(), ref_fftn(x, sign)) <= oracle.tol(x.size)

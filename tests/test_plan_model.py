@@ -30,6 +30,11 @@ def addresses(args, n, inp):
     return base[:, None] + j[None, :] * js        # (B, n)
 
 
+def pass_points(p):
+    """Points one work item (pencil, or plane for fused plane passes) covers."""
+    return p["n"] * max(1, p.get("plane_rows", 0))
+
+
 def run_model(x, d, sign, key=None):
     """Run a pass list; by default the one execute uses for `sign` (a
     shuffled plan's inverse runs its "inverse_passes")."""
@@ -42,12 +47,16 @@ def run_model(x, d, sign, key=None):
     passes = d[key]
     for i, p in enumerate(passes):
         a = p["args"]
-        ia = addresses(a, p["n"], True)
-        oa = addresses(a, p["n"], False)
+        ia = addresses(a, pass_points(p), True)
+        oa = addresses(a, pass_points(p), False)
         v = bufs[p["src"]][ia + p["in_off"]]
         if sign == 1 and p["src"] == "in":
             v = np.conj(v)
-        y = np.fft.fft(v, axis=1)
+        if p.get("plane_rows", 0):   # fused 2D DFT of contiguous planes
+            n1 = p["plane_rows"]
+            y = np.fft.fft2(v.reshape(-1, n1, p["n"])).reshape(v.shape)
+        else:
+            y = np.fft.fft(v, axis=1)
         if p["post_twiddle"]:
             L = a["twp_len"]
             res = (np.arange(a["B"]) >> a["res_shift"]) & a["res_mask"]
@@ -70,7 +79,7 @@ def test_pass_maps_are_injective_and_in_bounds(shape, schedule):
     N = shape[0] * shape[1] * shape[2]
     for p in d["passes"]:
         a = p["args"]
-        if a["B"] * p["n"] > (1 << 22):
+        if a["B"] * pass_points(p) > (1 << 22):
             # sampled: the first, last and a middle block of pencils
             B = a["B"]
             for lo in (0, B // 2, B - 64):
@@ -81,12 +90,12 @@ def test_pass_maps_are_injective_and_in_bounds(shape, schedule):
                     base = ((b >> a["s1"]) * st[2] + ((b >> a["s0"]) & a["m1"]) * st[1]
                             + (b & a["m0"]) * st[0])
                     off = p["in_off"] if inp else p["out_off"]
-                    hi = base.max() + (p["n"] - 1) * js + off
+                    hi = base.max() + (pass_points(p) - 1) * js + off
                     assert base.min() + off >= 0 and hi < N, (p["label"], inp)
             continue
         for inp in (True, False):
             off = p["in_off"] if inp else p["out_off"]
-            addr = addresses(a, p["n"], inp).reshape(-1) + off
+            addr = addresses(a, pass_points(p), inp).reshape(-1) + off
             assert addr.min() >= 0 and addr.max() < N, (p["label"], inp)
             assert np.unique(addr).size == addr.size, (p["label"], inp)
 
@@ -103,7 +112,7 @@ def test_pass_list_computes_the_dft(shape, schedule):
         assert oracle.rel_l2(got, ref) < 1e-13, (shape, schedule, sign)
 
 
-OPTION_SETS = [dict(slab_group=1), dict(slab_group=2), dict(tile=8), dict(tile=64),
+OPTION_SETS = [dict(slab_group=1), dict(slab_group=2), dict(fused_plane=0), dict(tile=8), dict(tile=64),
                dict(split_max=4), dict(persistent=0), dict(nontemporal=1),
                dict(xcd_remap=0), dict(precision="bf16x6"), dict(precision="fp16x3")]
 
@@ -172,3 +181,21 @@ def test_shuffled_pass_maps_in_bounds(shape):
 def test_shuffled_rejected_by_other_schedules(schedule):
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((8, 8, 8), schedule, "shuffled")
+
+
+@pytest.mark.parametrize("shape", [(4, 16, 16), (2, 128, 128), (8, 32, 64), (16, 128, 16),
+                                   (1, 64, 128), (32, 16, 8), (8, 256, 16)])
+def test_slab_fused_plane_pass(shape):
+    """Planes of 16..128 x 16..128 points go through one fused 2D pass;
+    other planes keep the row and column passes."""
+    d = dft3d.describe(shape, "slab")
+    fused = 16 <= shape[1] <= 128 and 16 <= shape[2] <= 128
+    planes = [p for p in d["passes"] if p["plane_rows"]]
+    assert len(planes) == (1 if fused else 0)
+    assert len(d["passes"]) == (2 if fused else 3)
+    g = np.random.default_rng(5)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    for sign in (-1, 1):
+        assert oracle.rel_l2(run_model(x, d, sign), oracle.dft3d(x, sign, "fft")) < 1e-13
+    off = dft3d.describe(shape, "slab", fused_plane=0)
+    assert not any(p["plane_rows"] for p in off["passes"])
