@@ -1,7 +1,8 @@
 // Host side of the batched form (dft3d_execute_batched): turns a sequence
-// of plans into the work items of batch_level_kernel once per sequence of
-// plans, and on every call refreshes the buffer pointers, uploads the
-// descriptors and launches one kernel per pass level.
+// of plans into the work items of batch_level_kernel (and, for fused plane
+// passes, batch_plane_level_kernel) once per sequence of plans, and on
+// every call refreshes the buffer pointers, uploads the descriptors and
+// launches one kernel per pass level and item kind.
 #include <atomic>
 #include <cstdlib>
 #include <cstring>
@@ -43,9 +44,10 @@ struct BatchGraph {
   std::vector<uint64_t> uids;
   std::vector<BatchItem> items;       // host copy (pointers refreshed per call)
   std::vector<int> item_plan, item_pass;
-  struct Level {
+  struct Level {  // one launch: the 1D items or the plane items of a pass level
     int item_lo, item_hi;
     int64_t base, ntiles;
+    int planes;  // 1: fused plane items (batch_plane_level_kernel)
   };
   std::vector<Level> levels;
   BatchItem* staging = nullptr;       // pinned host copy of the descriptors
@@ -80,7 +82,11 @@ constexpr size_t kCacheMax = 8;
 
 bool batchable(const dft3d_plan_s* p) {
   for (const Pass& ps : p->passes) {
-    if (ps.k->n > kBatchMaxN || ps.k->post_twiddle || ps.k->plane_rows) return false;
+    if (ps.k->plane_rows) {
+      if (!batch_plane_shape(ps.k->plane_rows, ps.k->n)) return false;
+      continue;
+    }
+    if (ps.k->n > kBatchMaxN || ps.k->post_twiddle) return false;
     if (batch_tile_for(ps.k->n) == 0) return false;
   }
   return true;
@@ -94,33 +100,43 @@ int build_batch(BatchGraph* g, dft3d_plan_s* const* plans, int count) {
   for (int i = 0; i < count; ++i) levels = std::max(levels, plans[i]->passes.size());
   int64_t first = 0;
   for (size_t lv = 0; lv < levels; ++lv) {
-    BatchGraph::Level L;
-    L.item_lo = (int)g->items.size();
-    L.base = first;
-    for (int i = 0; i < count; ++i) {
-      const dft3d_plan_s* p = plans[i];
-      if (lv >= p->passes.size()) continue;
-      const Pass& ps = p->passes[lv];
-      BatchItem it;
-      std::memset(&it, 0, sizeof it);
-      it.a = ps.args;
-      it.tw = p->tables + p->tw_off[lv];
-      it.n = ps.k->n;
-      it.lmode = ps.k->lmode;
-      it.smode = ps.k->smode;
-      const int T = batch_tile_for(it.n);
-      it.ntiles = (ps.args.B + T - 1) / T;
-      it.first = first;
-      it.dep = -1;
-      first += it.ntiles;
-      g->items.push_back(it);
-      g->item_plan.push_back(i);
-      g->item_pass.push_back((int)lv);
+    for (int planes = 1; planes >= 0; --planes) {  // plane items, then 1D items
+      BatchGraph::Level L;
+      L.item_lo = (int)g->items.size();
+      L.base = first;
+      L.planes = planes;
+      for (int i = 0; i < count; ++i) {
+        const dft3d_plan_s* p = plans[i];
+        if (lv >= p->passes.size()) continue;
+        const Pass& ps = p->passes[lv];
+        if ((ps.k->plane_rows > 0) != (planes == 1)) continue;
+        BatchItem it;
+        std::memset(&it, 0, sizeof it);
+        it.a = ps.args;
+        it.tw = p->tables + p->tw_off[lv];
+        it.twp = p->tables + p->twp_off[lv];
+        it.n = ps.k->n;
+        it.n1 = ps.k->plane_rows;
+        it.lmode = ps.k->lmode;
+        it.smode = ps.k->smode;
+        if (planes) {
+          it.ntiles = ps.args.B;
+        } else {
+          const int T = batch_tile_for(it.n);
+          it.ntiles = (ps.args.B + T - 1) / T;
+        }
+        it.first = first;
+        it.dep = -1;
+        first += it.ntiles;
+        g->items.push_back(it);
+        g->item_plan.push_back(i);
+        g->item_pass.push_back((int)lv);
+      }
+      L.item_hi = (int)g->items.size();
+      L.ntiles = first - L.base;
+      if (L.ntiles > 0x7fffffffLL) return DFT3D_ERR_UNSUPPORTED_SIZE;
+      if (L.item_hi > L.item_lo) g->levels.push_back(L);
     }
-    L.item_hi = (int)g->items.size();
-    L.ntiles = first - L.base;
-    if (L.ntiles > 0x7fffffffLL) return DFT3D_ERR_UNSUPPORTED_SIZE;
-    g->levels.push_back(L);
   }
   g->ws.assign(count, nullptr);
   for (int i = 0; i < count; ++i) {
@@ -237,12 +253,19 @@ int batch_execute(dft3d_plan_s* const* given, const void* const* in, void* const
   g->launched = true;
   for (const BatchGraph::Level& L : g->levels) {
     if (L.ntiles <= 0) continue;
-    hipLaunchKernelGGL(batch_level_kernel, dim3((unsigned)L.ntiles), dim3(kBatchThreads), 0,
-                       stream, g->d_items, L.item_lo, L.item_hi, L.base);
+    if (L.planes)
+      hipLaunchKernelGGL(batch_plane_level_kernel, dim3((unsigned)L.ntiles),
+                         dim3(kBatchThreads), 0, stream, g->d_items, L.item_lo, L.item_hi,
+                         L.base);
+    else
+      hipLaunchKernelGGL(batch_level_kernel, dim3((unsigned)L.ntiles), dim3(kBatchThreads), 0,
+                         stream, g->d_items, L.item_lo, L.item_hi, L.base);
     if (hipGetLastError() != hipSuccess) return DFT3D_ERR_HIP;
   }
   return DFT3D_OK;
 }
+
+bool batch_runs_plane(int n1, int n2) { return batch_plane_shape(n1, n2); }
 
 void batch_forget_plan(const dft3d_plan_s* p) {
   std::lock_guard<std::mutex> lock(g_mutex);

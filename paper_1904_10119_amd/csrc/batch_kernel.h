@@ -3,7 +3,9 @@
 // Every (problem, pass) of a batch becomes a work item; the tiles of all
 // items of one pass level are laid out consecutively, and one launch of
 // batch_level_kernel runs a whole level (one workgroup per tile, the tile's
-// item found by binary search).  The kernel boundary between levels orders
+// item found by binary search).  Fused plane passes (slab) are items of
+// their own kind, one workgroup per plane, run by batch_plane_level_kernel
+// in a launch of their own for the level.  The kernel boundary between levels orders
 // each pass of a problem after the previous one, so there are no waits
 // between workgroups: three launches run 96 pencil-schedule problems.
 //
@@ -14,6 +16,7 @@
 #pragma once
 
 #include "pass_kernel.h"
+#include "plane_kernel.h"
 
 namespace dft3d {
 
@@ -31,12 +34,20 @@ struct BatchItem {
   const float2* src;  // refreshed on every call
   float2* dst;
   const float2* tw;   // root table of length n
+  const float2* twp;  // plane items: root table of length n1
   int64_t first;      // queue position of the item's first tile
-  int64_t ntiles;
-  int32_t n;          // transform length
+  int64_t ntiles;     // tiles, or planes for plane items
+  int32_t n;          // transform length (plane items: row length n2)
+  int32_t n1;         // plane items: column length; 0 for 1D passes
   int32_t dep;        // item whose completion this one waits for, -1: none
   int32_t lmode, smode;
 };
+
+// Fused plane passes the batched plane kernel runs: (n1, n2) planes with
+// both sides in {32, 64, 128}, n1 n2 / 256 elements per thread.
+__host__ __device__ constexpr bool batch_plane_shape(int n1, int n2) {
+  return (n1 == 32 || n1 == 64 || n1 == 128) && (n2 == 32 || n2 == 64 || n2 == 128);
+}
 
 struct BatchState {  // zeroed before every launch
   unsigned long long head;  // next ticket
@@ -114,6 +125,39 @@ batch_level_kernel(const BatchItem* __restrict__ items, int item_lo, int item_hi
     case 128: batch_tile_modes<128>(it, tile, lds); break;
     default: batch_tile_modes<256>(it, tile, lds); break;
   }
+}
+
+// One workgroup per plane of the plane items [item_lo, item_hi) of one
+// level (fused 2D DFT of the plane, as fft_plane_kernel, with 256 threads).
+__global__ void __launch_bounds__(kBatchThreads)
+batch_plane_level_kernel(const BatchItem* __restrict__ items, int item_lo, int item_hi,
+                         int64_t base) {
+  __shared__ float2 lds[plane_lds_elems<128, 128>()];
+  const int64_t ticket = base + blockIdx.x;
+  int lo = item_lo, hi = item_hi - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= ticket) lo = mid; else hi = mid - 1;
+  }
+  const BatchItem& it = items[lo];
+  const int64_t plane = ticket - it.first;
+  const int tid = threadIdx.x;
+#define DFT3D_PLANE_CASE(A, B)                                                              \
+  if (it.n1 == A && it.n == B) {                                                            \
+    plane_run<A, B, A * B / kBatchThreads>(it.src, it.dst, it.tw, it.twp, it.a, plane, lds, \
+                                           tid);                                            \
+    return;                                                                                 \
+  }
+  DFT3D_PLANE_CASE(32, 32)
+  DFT3D_PLANE_CASE(32, 64)
+  DFT3D_PLANE_CASE(32, 128)
+  DFT3D_PLANE_CASE(64, 32)
+  DFT3D_PLANE_CASE(64, 64)
+  DFT3D_PLANE_CASE(64, 128)
+  DFT3D_PLANE_CASE(128, 32)
+  DFT3D_PLANE_CASE(128, 64)
+  DFT3D_PLANE_CASE(128, 128)
+#undef DFT3D_PLANE_CASE
 }
 
 __global__ void __launch_bounds__(kBatchThreads)

@@ -186,7 +186,8 @@ void destroy_twin(dft3d_plan_s* p) {
 
 dft3d_plan_s* batch_view(dft3d_plan_s* p) {
   bool plane = false;
-  for (const Pass& ps : p->passes) plane = plane || ps.k->plane_rows > 0;
+  for (const Pass& ps : p->passes)
+    plane = plane || (ps.k->plane_rows > 0 && !batch_runs_plane(ps.k->plane_rows, ps.k->n));
   if (!plane) return p;
   if (p->batch_twin) return p->batch_twin;
   dft3d_plan_s* t = new (std::nothrow) dft3d_plan_s();

@@ -139,8 +139,8 @@ struct dft3d_plan_s {
   bool ws_owned = false;
   uint64_t uid = 0;  // changes whenever the pass list is rebuilt
   int tuned = -1;    // AUTO plans: schedule chosen by the autotuner, -1 none
-  // Plans with fused plane passes: the same transform without them, built on
-  // first batched use (the batched kernel runs one-dimensional passes only).
+  // Plans with fused plane passes the batched plane kernel does not cover:
+  // the same transform without them, built on first batched use.
   dft3d_plan_s* batch_twin = nullptr;
 };
 
@@ -153,7 +153,10 @@ int batch_execute(dft3d_plan_s* const* plans, const void* const* in,
 void batch_forget_plan(const dft3d_plan_s* p);
 // AUTO plans: apply the autotuner's recorded choice for the shape, if any.
 void tune_lookup(dft3d_plan_s* p);
-// The plan whose passes the batched kernel runs for p: p itself, or its
-// twin without fused plane passes (created on first use; null if that fails).
+// The plan whose passes the batched kernels run for p: p itself, or, when
+// p has a fused plane pass the batched plane kernel does not cover, its
+// twin without fused plane passes (created on first use; null on failure).
 dft3d_plan_s* batch_view(dft3d_plan_s* p);
+// Whether the batched plane kernel covers (n1, n2) planes.
+bool batch_runs_plane(int n1, int n2);
 }  // namespace dft3d

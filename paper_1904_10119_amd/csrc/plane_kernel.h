@@ -58,20 +58,18 @@ template <int N1, int N2> constexpr int plane_lds_elems() {
   return a > b ? a : b;
 }
 
+// 2D DFT of plane b with E elements per thread (N1 * N2 / E threads).
 // tw2: roots of length n2 (rows), tw1: roots of length n1 (columns).
-template <int N1, int N2>
-__global__ void __launch_bounds__((N1 * N2 / plane_elems<N1, N2>()))
-fft_plane_kernel(const float2* src, float2* dst, const float2* __restrict__ tw2,
-                 const float2* __restrict__ tw1, const PassArgs a) {
-  constexpr int E = plane_elems<N1, N2>();
+template <int N1, int N2, int E>
+__device__ __forceinline__ void plane_run(const float2* src, float2* dst,
+                                          const float2* __restrict__ tw2,
+                                          const float2* __restrict__ tw1, const PassArgs& a,
+                                          int64_t b, float2* lds, int tid) {
   using BR = PlaneBlocking<N2, E>;
   using BC = PlaneBlocking<N1, E>;
   constexpr int P2 = N2 / E, P1 = N1 / E;
   constexpr int SQR = plane_stride<N2>();  // row pencils; also the plane rows
   constexpr int SQC = plane_stride<N1>();  // column pencils
-  __shared__ float2 lds[plane_lds_elems<N1, N2>()];
-  const int tid = threadIdx.x;
-  const int64_t b = blockIdx.x;
   const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
   float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
 
@@ -103,6 +101,15 @@ fft_plane_kernel(const float2* src, float2* dst, const float2* __restrict__ tw2,
     if (a.conj_out) o.y = -o.y;
     d[(p + P1 * e) * N2 + q] = o;
   }
+}
+
+template <int N1, int N2>
+__global__ void __launch_bounds__((N1 * N2 / plane_elems<N1, N2>()))
+fft_plane_kernel(const float2* src, float2* dst, const float2* __restrict__ tw2,
+                 const float2* __restrict__ tw1, const PassArgs a) {
+  __shared__ float2 lds[plane_lds_elems<N1, N2>()];
+  plane_run<N1, N2, plane_elems<N1, N2>()>(src, dst, tw2, tw1, a, blockIdx.x, lds,
+                                           threadIdx.x);
 }
 
 template <int N1, int N2>

@@ -180,3 +180,17 @@ def test_level_batched_96_problems_repeat_and_inverse():
     for i in range(0, 96, 11):
         ref = oracle.dft3d(xs[i].astype(np.complex128), +1, "fft")
         assert oracle.rel_l2(outs2[i].cpu().numpy(), ref) <= oracle.tol(xs[i].size)
+
+
+def test_level_batched_every_plane_shape():
+    """Slab plans of every plane shape the batched plane kernel covers
+    ({32, 64, 128} squared), with a few planes each, in one batch; forward
+    and inverse against the oracle."""
+    shapes = [(n0, n1, n2) for n1 in (32, 64, 128) for n2 in (32, 64, 128)
+              for n0 in (2,)] + [(4, 16, 64), (2, 128, 16)]
+    say("case plane shapes", shapes)
+    xs, xt = make_batch(shapes, 70)
+    for inv, sign in ((False, -1), (True, 1)):
+        ys = dft3d.fftn_batched(xt, schedule="slab", inverse=inv)
+        torch.cuda.synchronize()
+        check_against_oracle(xs, ys, sign)
