@@ -44,10 +44,10 @@ struct BatchGraph {
   std::vector<uint64_t> uids;
   std::vector<BatchItem> items;       // host copy (pointers refreshed per call)
   std::vector<int> item_plan, item_pass;
-  struct Level {  // one launch: the 1D items or the plane items of a pass level
+  struct Level {  // one launch: the 1D items or one class of plane items of a pass level
     int item_lo, item_hi;
     int64_t base, ntiles;
-    int planes;  // 1: fused plane items (batch_plane_level_kernel)
+    int planes;  // 0: 1D items; 1: small planes; 2: large planes
   };
   std::vector<Level> levels;
   BatchItem* staging = nullptr;       // pinned host copy of the descriptors
@@ -100,7 +100,7 @@ int build_batch(BatchGraph* g, dft3d_plan_s* const* plans, int count) {
   for (int i = 0; i < count; ++i) levels = std::max(levels, plans[i]->passes.size());
   int64_t first = 0;
   for (size_t lv = 0; lv < levels; ++lv) {
-    for (int planes = 1; planes >= 0; --planes) {  // plane items, then 1D items
+    for (int planes = 2; planes >= 0; --planes) {  // large, small planes, then 1D items
       BatchGraph::Level L;
       L.item_lo = (int)g->items.size();
       L.base = first;
@@ -109,7 +109,9 @@ int build_batch(BatchGraph* g, dft3d_plan_s* const* plans, int count) {
         const dft3d_plan_s* p = plans[i];
         if (lv >= p->passes.size()) continue;
         const Pass& ps = p->passes[lv];
-        if ((ps.k->plane_rows > 0) != (planes == 1)) continue;
+        const int64_t pts = (int64_t)ps.k->plane_rows * ps.k->n;
+        const int kind = ps.k->plane_rows == 0 ? 0 : (pts <= kBatchSmallPlane ? 1 : 2);
+        if (kind != planes) continue;
         BatchItem it;
         std::memset(&it, 0, sizeof it);
         it.a = ps.args;
@@ -253,8 +255,12 @@ int batch_execute(dft3d_plan_s* const* given, const void* const* in, void* const
   g->launched = true;
   for (const BatchGraph::Level& L : g->levels) {
     if (L.ntiles <= 0) continue;
-    if (L.planes)
-      hipLaunchKernelGGL(batch_plane_level_kernel, dim3((unsigned)L.ntiles),
+    if (L.planes == 1)
+      hipLaunchKernelGGL(batch_plane_level_kernel<0>, dim3((unsigned)L.ntiles),
+                         dim3(kBatchThreads), 0, stream, g->d_items, L.item_lo, L.item_hi,
+                         L.base);
+    else if (L.planes == 2)
+      hipLaunchKernelGGL(batch_plane_level_kernel<1>, dim3((unsigned)L.ntiles),
                          dim3(kBatchThreads), 0, stream, g->d_items, L.item_lo, L.item_hi,
                          L.base);
     else

@@ -127,12 +127,19 @@ batch_level_kernel(const BatchItem* __restrict__ items, int item_lo, int item_hi
   }
 }
 
+// Planes of at most this many points run in the small-plane launch (about
+// 35 KB of LDS, several workgroups per CU); larger ones in the large-plane
+// launch (136 KB, one workgroup per CU).
+constexpr int kBatchSmallPlane = 4096;
+
 // One workgroup per plane of the plane items [item_lo, item_hi) of one
 // level (fused 2D DFT of the plane, as fft_plane_kernel, with 256 threads).
+// LARGE selects the plane shapes above kBatchSmallPlane points.
+template <int LARGE>
 __global__ void __launch_bounds__(kBatchThreads)
 batch_plane_level_kernel(const BatchItem* __restrict__ items, int item_lo, int item_hi,
                          int64_t base) {
-  __shared__ float2 lds[plane_lds_elems<128, 128>()];
+  __shared__ float2 lds[LARGE ? plane_lds_elems<128, 128>() : plane_lds_elems<128, 32>()];
   const int64_t ticket = base + blockIdx.x;
   int lo = item_lo, hi = item_hi - 1;
   while (lo < hi) {
@@ -148,15 +155,21 @@ batch_plane_level_kernel(const BatchItem* __restrict__ items, int item_lo, int i
                                            tid);                                            \
     return;                                                                                 \
   }
-  DFT3D_PLANE_CASE(32, 32)
-  DFT3D_PLANE_CASE(32, 64)
-  DFT3D_PLANE_CASE(32, 128)
-  DFT3D_PLANE_CASE(64, 32)
-  DFT3D_PLANE_CASE(64, 64)
-  DFT3D_PLANE_CASE(64, 128)
-  DFT3D_PLANE_CASE(128, 32)
-  DFT3D_PLANE_CASE(128, 64)
-  DFT3D_PLANE_CASE(128, 128)
+  if constexpr (!LARGE) {
+    static_assert(plane_lds_elems<128, 32>() >= plane_lds_elems<32, 128>() &&
+                      plane_lds_elems<128, 32>() >= plane_lds_elems<64, 64>(),
+                  "small-plane LDS");
+    DFT3D_PLANE_CASE(32, 32)
+    DFT3D_PLANE_CASE(32, 64)
+    DFT3D_PLANE_CASE(32, 128)
+    DFT3D_PLANE_CASE(64, 32)
+    DFT3D_PLANE_CASE(64, 64)
+    DFT3D_PLANE_CASE(128, 32)
+  } else {
+    DFT3D_PLANE_CASE(64, 128)
+    DFT3D_PLANE_CASE(128, 64)
+    DFT3D_PLANE_CASE(128, 128)
+  }
 #undef DFT3D_PLANE_CASE
 }
 
