@@ -257,12 +257,12 @@ int batch_execute(dft3d_plan_s* const* given, const void* const* in, void* const
     if (L.ntiles <= 0) continue;
     if (L.planes == 1)
       hipLaunchKernelGGL(batch_plane_level_kernel<0>, dim3((unsigned)L.ntiles),
-                         dim3(kBatchThreads), 0, stream, g->d_items, L.item_lo, L.item_hi,
-                         L.base);
+                         dim3(batch_plane_threads<0>()), 0, stream, g->d_items, L.item_lo,
+                         L.item_hi, L.base);
     else if (L.planes == 2)
       hipLaunchKernelGGL(batch_plane_level_kernel<1>, dim3((unsigned)L.ntiles),
-                         dim3(kBatchThreads), 0, stream, g->d_items, L.item_lo, L.item_hi,
-                         L.base);
+                         dim3(batch_plane_threads<1>()), 0, stream, g->d_items, L.item_lo,
+                         L.item_hi, L.base);
     else
       hipLaunchKernelGGL(batch_level_kernel, dim3((unsigned)L.ntiles), dim3(kBatchThreads), 0,
                          stream, g->d_items, L.item_lo, L.item_hi, L.base);

@@ -132,11 +132,14 @@ batch_level_kernel(const BatchItem* __restrict__ items, int item_lo, int item_hi
 // launch (136 KB, one workgroup per CU).
 constexpr int kBatchSmallPlane = 4096;
 
+// Threads of a plane workgroup: 256 for small planes, 1024 for large ones.
+template <int LARGE> constexpr int batch_plane_threads() { return LARGE ? 1024 : 256; }
+
 // One workgroup per plane of the plane items [item_lo, item_hi) of one
-// level (fused 2D DFT of the plane, as fft_plane_kernel, with 256 threads).
-// LARGE selects the plane shapes above kBatchSmallPlane points.
+// level (fused 2D DFT of the plane, as fft_plane_kernel).  LARGE selects
+// the plane shapes above kBatchSmallPlane points.
 template <int LARGE>
-__global__ void __launch_bounds__(kBatchThreads)
+__global__ void __launch_bounds__(batch_plane_threads<LARGE>())
 batch_plane_level_kernel(const BatchItem* __restrict__ items, int item_lo, int item_hi,
                          int64_t base) {
   __shared__ float2 lds[LARGE ? plane_lds_elems<128, 128>() : plane_lds_elems<128, 32>()];
@@ -151,8 +154,8 @@ batch_plane_level_kernel(const BatchItem* __restrict__ items, int item_lo, int i
   const int tid = threadIdx.x;
 #define DFT3D_PLANE_CASE(A, B)                                                              \
   if (it.n1 == A && it.n == B) {                                                            \
-    plane_run<A, B, A * B / kBatchThreads>(it.src, it.dst, it.tw, it.twp, it.a, plane, lds, \
-                                           tid);                                            \
+    plane_run<A, B, A * B / batch_plane_threads<LARGE>()>(it.src, it.dst, it.tw, it.twp,     \
+                                                         it.a, plane, lds, tid);           \
     return;                                                                                 \
   }
   if constexpr (!LARGE) {
