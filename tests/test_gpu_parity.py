@@ -284,3 +284,19 @@ def test_batched_runs_fused_plane_plans_as_twins():
         torch.cuda.synchronize()
         for x, y in zip(xs, ys):
             assert oracle.rel_l2(y.cpu().numpy(), ref_fftn(x, sign)) <= oracle.tol(x.size)
+
+
+def test_error_against_size_sweep():
+    """Accuracy curve from 8^3 to 256^3 (auto schedule, uniform inputs):
+    every size within tol(N); the measured values are printed for the
+    record."""
+    errs = {}
+    for n in (8, 16, 32, 64, 128, 256):
+        shape = (n, n, n)
+        x = inputs.uniform_c64(shape, 11)
+        for sched in ("auto", "pencil"):
+            y = gpu_fftn(x, sched)
+            err = oracle.rel_l2(y, oracle.dft3d(x.astype(np.complex128), -1, "fft"))
+            errs[(n, sched)] = err
+            assert err <= oracle.tol(x.size), (n, sched, err)
+    say("error curve", {f"{k[0]}^3 {k[1]}": "%.3e" % v for k, v in errs.items()})
