@@ -111,6 +111,11 @@ enum dft3d_option {
                                 plane in one pass when n1, n2 are in
                                 [16, 128] (the plane stays in LDS between
                                 rows and columns); default 1 */
+  DFT3D_OPT_FUSED_AXES = 9,  /* volumetric, FP32, natural layout: 1 = the
+                                second half of one axis and the first half
+                                of the next in one pass where the split
+                                factors match (a_d = b_{d-1} = 16 or 32:
+                                256^3, 1024^3); default 1 */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

@@ -1,0 +1,99 @@
+// Volumetric schedule: the second half of one axis and the first half of the
+// next in one pass (Fig. 9, eqs. (13)-(17) applied to two axes at once).
+//
+// Axis d of length n_d = a * b is split four-step style; its first half V1
+// has left T0 at axis position k a + l (k < b, l < a).  The fused pass
+// finishes axis d -- DFT_a over l, natural output k + b l' -- and starts
+// axis d-1 (length n' = A' B', A' = B' = a): for residue r' of axis d-1,
+// DFT_a over m of the rows r' + A' m, times w_{n'}^{r' k2}, stored at row
+// r' + A' k2.  A workgroup owns one residue r', all a rows, and KC
+// consecutive V2 runs (CONTIG: runs contiguous along axis d, the innermost
+// axis) or one run and KC consecutive innermost points (runs strided), so
+// both the loads and the stores move KC * 8-byte segments or longer.
+//
+// Stage 1: thread = one run (c, kk, m) -> DFT_a in registers -> LDS tile
+// [m][j], j = c + C (kk + K l').  Stage 2: thread = one column j -> the a
+// rows from LDS -> DFT_a -> twiddle -> store.
+//
+// PassArgs fields used: tile t splits into f0 = t & m0, f1 = (t >> s0) & m1
+// (the residue r'), f2 = t >> s1; tile bases f0 is0 + f1 is1 + f2 is2 (in)
+// and f0 os0 + f1 os1 + f2 os2 (out); ijs = row step A' * S_{d-1}; oks =
+// S_d (axis d stride); res_mask = b; twp_mask = n' - 1.
+#pragma once
+
+#include "pass_kernel.h"
+
+namespace dft3d {
+
+template <int A, int KC> constexpr int fused_row() { return KC * A + ((KC * A) >> 5) + 1; }
+
+template <int A, int KC, int CONTIG>
+__global__ void __launch_bounds__(A* KC)
+fft_fused_axes_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
+                      const float2* __restrict__ twp, const PassArgs a) {
+  constexpr int K = CONTIG ? KC : 1;
+  constexpr int C = CONTIG ? 1 : KC;
+  constexpr int SJ = fused_row<A, KC>();
+  __shared__ float2 lds[A * SJ];
+  const int tid = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int64_t f0 = t & a.m0, f1 = (t >> a.s0) & a.m1, f2 = t >> a.s1;
+  const int64_t in_base = f0 * a.is0 + f1 * a.is1 + f2 * a.is2;
+  const int64_t out_base = f0 * a.os0 + f1 * a.os1 + f2 * a.os2;
+  const int64_t RM = a.ijs, SD = a.oks, b = a.res_mask;
+
+  // stage 1: run (c, kk, m), elements l along axis d
+  {
+    const int c = tid % C, kk = (tid / C) % K, m = tid / KC;
+    const float2* s = src + in_base + m * RM + (int64_t)(kk * A) * SD + c;
+    float2 v[A];
+#pragma unroll
+    for (int l = 0; l < A; ++l) {
+      v[l] = s[l * SD];
+      if (a.conj_in) v[l].y = -v[l].y;
+    }
+    dft<A>(v);
+    float2* row = lds + m * SJ;
+#pragma unroll
+    for (int lp = 0; lp < A; ++lp) row[lds_pad_index(c + C * (kk + K * lp))] = v[lp];
+  }
+  __syncthreads();
+  // stage 2: column j = tid, the a rows m of residue r' = f1
+  {
+    float2 v[A];
+#pragma unroll
+    for (int m = 0; m < A; ++m) v[m] = lds[m * SJ + lds_pad_index(tid)];
+    dft<A>(v);
+    const int c = tid % C, kk = (tid / C) % K, lp = tid / KC;
+    float2* d = dst + out_base + (kk + b * lp) * SD + c;
+#pragma unroll
+    for (int k2 = 0; k2 < A; ++k2) {
+      float2 w = cmul(v[k2], twp[(f1 * k2) & a.twp_mask]);
+      if (a.conj_out) w.y = -w.y;
+      d[k2 * RM] = w;
+    }
+  }
+}
+
+template <int A, int KC, int CONTIG>
+hipError_t launch_fused_axes(const PassArgs& a, const float2* src, float2* dst,
+                             const float2* tw, const float2* twp, hipStream_t stream) {
+  if (a.B <= 0) return hipSuccess;
+  if (a.B > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((fft_fused_axes_kernel<A, KC, CONTIG>), dim3((unsigned)a.B), dim3(A * KC),
+                     0, stream, src, dst, tw, twp, a);
+  return hipGetLastError();
+}
+
+template <int A, int KC, int CONTIG>
+KernelInfo kernel_info_fused_axes() {
+  constexpr int LDS = A * fused_row<A, KC>() * 8;
+  static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
+  static_assert(A * KC <= 1024, "workgroup too large");
+  const int mode = CONTIG ? MODE_ROW : MODE_COL;
+  KernelInfo k{A, KC, mode, mode, 1, A * KC, LDS, &launch_fused_axes<A, KC, CONTIG>, 0, 0, 0};
+  k.fused_axes = 1;
+  return k;
+}
+
+}  // namespace dft3d

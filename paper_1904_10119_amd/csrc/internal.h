@@ -53,6 +53,7 @@ struct KernelInfo {
   int nontemporal;   // 1: streaming (non-temporal) loads and stores
   int precision = 0; // DFT3D_PREC_*: FP32 butterflies or split MFMA leaves
   int plane_rows = 0; // > 0: fused 2D DFT of (plane_rows, n) planes, one per workgroup
+  int fused_axes = 0; // 1: volumetric V2 of one axis fused with V1 of the next (n = a)
 };
 
 // All compiled pass kernels.
@@ -61,6 +62,9 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
                               int persistent, int nontemporal);
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
+// The fused volumetric two-axis kernel for split factor a, if compiled
+// (contig: V2 runs contiguous in memory).
+const KernelInfo* find_fused_axes_kernel(int a, int contig);
 // The split-precision MFMA pass kernel for a length and layout, if any
 // (the persistent form when asked for and compiled, else the other form).
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
@@ -97,6 +101,7 @@ struct Options {
   int persistent = 1;  // use the persistent form where one exists
   int slab_group = -1; // slab: planes per row/column group (0 = all, -1 = auto)
   int fused_plane = 1; // slab: one fused 2D pass for planes that fit in LDS
+  int fused_axes = 1;  // volumetric: V2 of an axis and V1 of the next in one pass
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

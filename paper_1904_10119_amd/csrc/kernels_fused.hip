@@ -1,0 +1,11 @@
+// Fused volumetric two-axis kernels for split factors 16 and 32.
+#include "fused_axes_kernel.h"
+
+namespace dft3d {
+void register_kernels_fused(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info_fused_axes<32, 16, 1>());
+  v.push_back(kernel_info_fused_axes<32, 16, 0>());
+  v.push_back(kernel_info_fused_axes<16, 16, 1>());
+  v.push_back(kernel_info_fused_axes<16, 32, 0>());
+}
+}  // namespace dft3d

@@ -93,7 +93,8 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
   const int nt = order[nchoice - 1].nt;
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw &&
-        k.persistent == 0 && k.nontemporal == nt && k.precision == 0 && k.plane_rows == 0)
+        k.persistent == 0 && k.nontemporal == nt && k.precision == 0 && k.plane_rows == 0 &&
+        k.fused_axes == 0)
       return &k;
   return nullptr;
 }
@@ -160,6 +161,24 @@ struct Builder {
     passes.push_back(p);
   }
 
+  // Volumetric V2 of axis d fused with V1 of axis d-1 (fused_axes_kernel.h
+  // documents the argument fields).
+  void add_fused(const KernelInfo* k, const Field* f, int64_t row_step, int64_t sd,
+                 int64_t b, int64_t n_prev, int a, const std::string& label) {
+    Pass p;
+    p.k = k;
+    set_fields(p.args, f, 3);
+    p.args.ijs = row_step;
+    p.args.oks = sd;
+    p.args.res_mask = b;
+    p.args.twp_mask = n_prev - 1;
+    p.args.xcd_remap = 0;
+    p.tw_len = a;
+    p.twp_len = n_prev;
+    p.label = label;
+    passes.push_back(p);
+  }
+
   // Fused 2D DFT of n0 contiguous (n1, n2) planes, in layout.
   void add_plane(const KernelInfo* k, int64_t n0, int64_t n1, int64_t n2,
                  const std::string& label) {
@@ -187,8 +206,7 @@ void split_axis(int64_t n, int64_t& A, int64_t& Bf) {
 
 // V1 + V2 of one axis in natural layout: the array is [outer][n][inner].
 // With shuffled, V2 stores y[k' + Bf l'] at position l' + A k'.
-void volumetric_axis(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis,
-                     bool shuffled) {
+void volumetric_v1(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis) {
   int64_t A, Bf;
   split_axis(n, A, Bf);
   const int64_t slab = n * inner;
@@ -200,6 +218,14 @@ void volumetric_axis(Builder& b, int64_t outer, int64_t n, int64_t inner, int ax
     b.add((int)Bf, MODE_COL, MODE_COL, 1, f, 2, A * inner, A * inner, n,
           ilog2(inner), A - 1, lab);
   }
+}
+
+void volumetric_v2(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis,
+                   bool shuffled) {
+  int64_t A, Bf;
+  split_axis(n, A, Bf);
+  const int64_t slab = n * inner;
+  char lab[64];
   {  // V2: pencils (o, k', c); elements l at stride inner
     std::snprintf(lab, sizeof lab, "vol%d.V2%s DFT%lld x%lld", axis, shuffled ? " shuf" : "",
                   (long long)A, (long long)(outer * Bf * inner));
@@ -217,6 +243,36 @@ void volumetric_axis(Builder& b, int64_t outer, int64_t n, int64_t inner, int ax
       b.add((int)A, MODE_COL, MODE_COL, 0, f, 3, inner, Bf * inner, 0, 0, 0, lab);
     }
   }
+}
+
+// V2 of axis d and V1 of axis d - 1 in one pass, when a = A_d equals
+// B_{d-1} and a kernel for it exists; returns false otherwise.  The array
+// is [outer][n_prev][n][inner] with outer == 1 unless the V2 runs are
+// contiguous (inner == 1).
+bool volumetric_fused(Builder& b, int64_t outer, int64_t n_prev, int64_t n, int64_t inner,
+                      int axis) {
+  int64_t A, Bf, Ap, Bp;
+  split_axis(n, A, Bf);
+  split_axis(n_prev, Ap, Bp);
+  if (A != Bp) return false;
+  const int contig = inner == 1;
+  const KernelInfo* k = find_fused_axes_kernel((int)A, contig);
+  if (!k) return false;
+  const int64_t KC = k->tile;
+  const int64_t sd = inner, sprev = n * inner, so = n_prev * sprev;
+  char lab[64];
+  std::snprintf(lab, sizeof lab, "vol%d.V2+vol%d.V1 DFT%lldx%lld", axis, axis - 1,
+                (long long)A, (long long)Bp);
+  if (contig) {
+    if (Bf % KC) return false;
+    Field f[3] = {{Bf / KC, KC * A * sd, KC * sd}, {Ap, sprev, sprev}, {outer, so, so}};
+    b.add_fused(k, f, Ap * sprev, sd, Bf, n_prev, (int)A, lab);
+  } else {
+    if (outer != 1 || inner % KC) return false;
+    Field f[3] = {{inner / KC, KC, KC}, {Ap, sprev, sprev}, {Bf, A * sd, sd}};
+    b.add_fused(k, f, Ap * sprev, sd, Bf, n_prev, (int)A, lab);
+  }
+  return true;
 }
 
 // One axis of the inverse of a shuffled plan: input entry y[k' + Bf l'] at
@@ -387,15 +443,47 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
       if (b.status == DFT3D_OK) passes.back().src = passes.back().dst = BUF_OUT;
     }
   } else {  // VOLUMETRIC
-    for (int axis = 2; axis >= 0; --axis) {
-      int64_t outer = 1, inner = 1;
+    // natural FP32 plans fuse V2 of an axis with V1 of the next where the
+    // split factors match (four passes instead of six for 256^3, 1024^3)
+    const bool fuse = opt.fused_axes && !shuffled && opt.precision == DFT3D_PREC_FP32;
+    int pending = -1;  // axis whose V2 is still to come
+    auto dims = [&n](int axis, int64_t& outer, int64_t& inner) {
+      outer = 1;
+      inner = 1;
       for (int d = 0; d < axis; ++d) outer *= n[d];
       for (int d = axis + 1; d < 3; ++d) inner *= n[d];
+    };
+    auto flush = [&]() {
+      if (pending < 0) return;
+      int64_t o, in;
+      dims(pending, o, in);
+      volumetric_v2(b, o, n[pending], in, pending, shuffled);
+      pending = -1;
+    };
+    for (int axis = 2; axis >= 0; --axis) {
+      int64_t outer = 1, inner = 1;
+      dims(axis, outer, inner);
       if (n[axis] >= 4 && shuffled && from_layout) {
         volumetric_axis_from_shuffled(b, outer, n[axis], inner, axis);
-      } else if (n[axis] >= 4) {
-        volumetric_axis(b, outer, n[axis], inner, axis, shuffled);
-      } else {  // too short to split (its shuffled order is natural): one pass
+        continue;
+      }
+      if (n[axis] >= 4) {
+        if (pending == axis + 1 && fuse && n[pending] >= 4) {
+          int64_t po, pin;
+          dims(pending, po, pin);
+          // the pending axis's outer dimensions are [outer][n[axis]]
+          if (volumetric_fused(b, outer, n[axis], n[pending], pin, pending)) {
+            pending = axis;
+            continue;
+          }
+        }
+        flush();
+        volumetric_v1(b, outer, n[axis], inner, axis);
+        pending = axis;
+        continue;
+      }
+      flush();
+      {  // too short to split (its shuffled order is natural): one pass
         char lab[64];
         std::snprintf(lab, sizeof lab, "vol%d DFT%lld", axis, (long long)n[axis]);
         if (inner == 1) {
@@ -407,6 +495,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
         }
       }
     }
+    flush();
     assign_chain(passes, 0, need_ws);
   }
   if (b.status != DFT3D_OK) {
@@ -429,7 +518,7 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << (p.k->smode == MODE_ROW ? "row" : "col") << "\",\"post_twiddle\":"
        << p.k->post_twiddle << ",\"persistent\":" << p.k->persistent
        << ",\"nontemporal\":" << p.k->nontemporal << ",\"precision\":" << p.k->precision
-       << ",\"plane_rows\":" << p.k->plane_rows
+       << ",\"plane_rows\":" << p.k->plane_rows << ",\"fused_axes\":" << p.k->fused_axes
        << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""

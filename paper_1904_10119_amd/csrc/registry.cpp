@@ -11,6 +11,7 @@ void register_kernels_mfma_a(std::vector<KernelInfo>& v);
 void register_kernels_mfma_b(std::vector<KernelInfo>& v);
 void register_kernels_mfma_c(std::vector<KernelInfo>& v);
 void register_kernels_plane(std::vector<KernelInfo>& v);
+void register_kernels_fused(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -23,6 +24,7 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_mfma_b(v);
     register_kernels_mfma_c(v);
     register_kernels_plane(v);
+    register_kernels_fused(v);
     return v;
   }();
   return table;
@@ -33,8 +35,16 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
-        k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0)
+        k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0 &&
+        k.fused_axes == 0)
       return &k;
+  return nullptr;
+}
+
+const KernelInfo* find_fused_axes_kernel(int a, int contig) {
+  const int mode = contig ? MODE_ROW : MODE_COL;
+  for (const KernelInfo& k : kernel_registry())
+    if (k.fused_axes && k.n == a && k.lmode == mode) return &k;
   return nullptr;
 }
 

@@ -99,8 +99,12 @@ def check_chain(d, shape):
             # only layout-preserving passes may run in place
             assert p["load"] == p["store"] and p["post_twiddle"] == 0
         assert p["threads"] <= 1024 and p["lds_bytes"] <= 160 * 1024
-        # a fused plane pass covers plane_rows x n points per work item
-        assert p["pencils"] * p["n"] * max(1, p["plane_rows"]) == n
+        # a fused plane pass covers plane_rows x n points per work item, a
+        # fused two-axis volumetric pass n x n x tile points per workgroup
+        if p["fused_axes"]:
+            assert p["pencils"] * p["n"] * p["n"] * p["tile"] == n
+        else:
+            assert p["pencils"] * p["n"] * max(1, p["plane_rows"]) == n
     uses_ws = any("ws" in (p["src"], p["dst"]) for p in passes)
     assert d["workspace_bytes"] == (8 * n if uses_ws else 0)
 

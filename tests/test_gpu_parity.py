@@ -300,3 +300,20 @@ def test_error_against_size_sweep():
             errs[(n, sched)] = err
             assert err <= oracle.tol(x.size), (n, sched, err)
     say("error curve", {f"{k[0]}^3 {k[1]}": "%.3e" % v for k, v in errs.items()})
+
+
+@pytest.mark.parametrize("shape", [(2, 256, 256), (256, 256, 32), (2, 1024, 512),
+                                   (1024, 512, 16), (256, 256, 256)])
+def test_volumetric_fused_axes_kernels(shape):
+    """Each fused volumetric two-axis kernel (split factor 16 or 32, runs
+    contiguous or strided): forward and inverse against the oracle and
+    against the unfused six-pass list."""
+    say("case fused axes", shape)
+    d = dft3d.describe(shape, "volumetric")
+    assert any(p["fused_axes"] for p in d["passes"])
+    x = inputs.uniform_c64(shape, 30)
+    for sign, inv in ((-1, False), (1, True)):
+        y = gpu_fftn(x, "volumetric", inverse=inv)
+        assert oracle.rel_l2(y, ref_fftn(x, sign)) <= oracle.tol(x.size), (sign,)
+        y0 = gpu_fftn(x, "volumetric", inverse=inv, fused_axes=0)
+        assert oracle.rel_l2(y, y0) <= oracle.tol(x.size)

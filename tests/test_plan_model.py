@@ -35,6 +35,44 @@ def pass_points(p):
     return p["n"] * max(1, p.get("plane_rows", 0))
 
 
+def fused_tiles(p):
+    """(input, output) element addresses of a fused volumetric two-axis pass,
+    shaped (tile, m, kk, c, l) and (tile, k2, kk, c, l') -- the kernel's
+    documented argument fields read back literally."""
+    a = p["args"]
+    A, KC = p["n"], p["tile"]
+    contig = p["load"] == "row"
+    K, C = (KC, 1) if contig else (1, KC)
+    t = np.arange(a["B"], dtype=np.int64)
+    f0, f1, f2 = t & a["m0"], (t >> a["s0"]) & a["m1"], t >> a["s1"]
+    ib = f0 * a["is"][0] + f1 * a["is"][1] + f2 * a["is"][2]
+    ob = f0 * a["os"][0] + f1 * a["os"][1] + f2 * a["os"][2]
+    RM, SD, b = a["ijs"], a["oks"], a["res_mask"]
+    m = np.arange(A)[None, :, None, None, None]
+    kk = np.arange(K)[None, None, :, None, None]
+    c = np.arange(C)[None, None, None, :, None]
+    l = np.arange(A)[None, None, None, None, :]
+    ia = ib[:, None, None, None, None] + m * RM + (kk * A + l) * SD + c
+    oa = ob[:, None, None, None, None] + m * RM + (kk + b * l) * SD + c
+    return ia, oa, f1
+
+
+def fused_model(bufs, p, sign, last):
+    ia, oa, r = fused_tiles(p)
+    v = bufs[p["src"]][ia]
+    if sign == 1 and p["src"] == "in":
+        v = np.conj(v)
+    v = np.fft.fft(v, axis=4)            # V2 of axis d: DFT_a over l
+    v = np.fft.fft(v, axis=1)            # V1 of axis d-1: DFT over the rows m
+    L = p["args"]["twp_len"]
+    k2 = np.arange(p["n"])
+    tw = np.exp(-2j * np.pi * ((r[:, None] * k2[None, :]) % L) / L)
+    v = v * tw[:, :, None, None, None]
+    if sign == 1 and last:
+        v = np.conj(v)
+    bufs[p["dst"]][oa] = v
+
+
 def run_model(x, d, sign, key=None):
     """Run a pass list; by default the one execute uses for `sign` (a
     shuffled plan's inverse runs its "inverse_passes")."""
@@ -47,6 +85,9 @@ def run_model(x, d, sign, key=None):
     passes = d[key]
     for i, p in enumerate(passes):
         a = p["args"]
+        if p.get("fused_axes"):
+            fused_model(bufs, p, sign, i == len(passes) - 1)
+            continue
         ia = addresses(a, pass_points(p), True)
         oa = addresses(a, pass_points(p), False)
         v = bufs[p["src"]][ia + p["in_off"]]
@@ -79,6 +120,13 @@ def test_pass_maps_are_injective_and_in_bounds(shape, schedule):
     N = shape[0] * shape[1] * shape[2]
     for p in d["passes"]:
         a = p["args"]
+        if p.get("fused_axes"):
+            if a["B"] * p["n"] * p["n"] * p["tile"] <= (1 << 22):
+                ia, oa, _ = fused_tiles(p)
+                for addr in (ia.reshape(-1), oa.reshape(-1)):
+                    assert addr.min() >= 0 and addr.max() < N, p["label"]
+                    assert np.unique(addr).size == addr.size, p["label"]
+            continue
         if a["B"] * pass_points(p) > (1 << 22):
             # sampled: the first, last and a middle block of pencils
             B = a["B"]
@@ -199,3 +247,34 @@ def test_slab_fused_plane_pass(shape):
         assert oracle.rel_l2(run_model(x, d, sign), oracle.dft3d(x, sign, "fft")) < 1e-13
     off = dft3d.describe(shape, "slab", fused_plane=0)
     assert not any(p["plane_rows"] for p in off["passes"])
+
+
+@pytest.mark.parametrize("shape,nfused", [
+    ((2, 256, 256), 1),      # a = 16, V2 runs contiguous
+    ((256, 256, 32), 1),     # a = 16, V2 runs strided
+    ((2, 1024, 512), 1),     # a = 32, contiguous
+    ((1024, 512, 16), 1),    # a = 32, strided
+    ((256, 256, 256), 2),    # both pairs
+    ((16, 256, 16), 0), ((256, 16, 256), 0), ((4, 1024, 1024), 1)])
+def test_volumetric_fused_axes(shape, nfused):
+    """Where the split factors match, V2 of an axis and V1 of the next run as
+    one fused pass; the pass list still computes the DFT, and turning the
+    option off restores the six separate halves."""
+    d = dft3d.describe(shape, "volumetric")
+    fused = [p for p in d["passes"] if p["fused_axes"]]
+    assert len(fused) == nfused
+    off = dft3d.describe(shape, "volumetric", fused_axes=0)
+    assert not any(p["fused_axes"] for p in off["passes"])
+    assert len(d["passes"]) == len(off["passes"]) - len(fused)
+    if shape[0] * shape[1] * shape[2] <= (1 << 23):
+        g = np.random.default_rng(9)
+        x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+        for sign in (-1, 1):
+            ref = oracle.dft3d(x, sign, "fft")
+            assert oracle.rel_l2(run_model(x, d, sign), ref) < 1e-13
+
+
+def test_volumetric_1024_cubed_has_four_passes():
+    d = dft3d.describe((1024, 1024, 1024), "volumetric")
+    assert len(d["passes"]) == 4
+    assert [p["fused_axes"] for p in d["passes"]] == [0, 1, 1, 0]
