@@ -27,51 +27,105 @@ namespace dft3d {
 
 template <int A, int KC> constexpr int fused_row() { return KC * A + ((KC * A) >> 5) + 1; }
 
+struct FusedTile {
+  int64_t in_base, out_base, r;  // tile bases and the residue r' of axis d-1
+};
+
+__device__ __forceinline__ FusedTile fused_tile(int64_t t, const PassArgs& a) {
+  const int64_t f0 = t & a.m0, f1 = (t >> a.s0) & a.m1, f2 = t >> a.s1;
+  return FusedTile{f0 * a.is0 + f1 * a.is1 + f2 * a.is2, f0 * a.os0 + f1 * a.os1 + f2 * a.os2,
+                   f1};
+}
+
+// Stage-1 inputs of this thread's run (c, kk, m): elements l along axis d.
+template <int A, int KC, int CONTIG>
+__device__ __forceinline__ void fused_load(float2 (&v)[A], const float2* src, const PassArgs& a,
+                                           const FusedTile& ft, int tid) {
+  constexpr int K = CONTIG ? KC : 1;
+  constexpr int C = CONTIG ? 1 : KC;
+  const int c = tid % C, kk = (tid / C) % K, m = tid / KC;
+  const float2* s = src + ft.in_base + m * a.ijs + (int64_t)(kk * A) * a.oks + c;
+#pragma unroll
+  for (int l = 0; l < A; ++l) v[l] = s[l * a.oks];
+}
+
+// Stage 1: DFT_a over l in registers, results to the LDS tile [m][j].
+template <int A, int KC, int CONTIG>
+__device__ __forceinline__ void fused_stage1(float2 (&v)[A], float2* lds, int conj, int tid) {
+  constexpr int K = CONTIG ? KC : 1;
+  constexpr int C = CONTIG ? 1 : KC;
+  const int c = tid % C, kk = (tid / C) % K, m = tid / KC;
+  if (conj) {
+#pragma unroll
+    for (int l = 0; l < A; ++l) v[l].y = -v[l].y;
+  }
+  dft<A>(v);
+  float2* row = lds + m * fused_row<A, KC>();
+#pragma unroll
+  for (int lp = 0; lp < A; ++lp) row[lds_pad_index(c + C * (kk + K * lp))] = v[lp];
+}
+
+// Stage 2: column j = tid over the a rows, DFT, twiddle w_{n'}^{r' k2}, store.
+template <int A, int KC, int CONTIG>
+__device__ __forceinline__ void fused_stage2(const float2* lds, float2* dst,
+                                             const float2* __restrict__ twp, const PassArgs& a,
+                                             const FusedTile& ft, int tid) {
+  constexpr int K = CONTIG ? KC : 1;
+  constexpr int C = CONTIG ? 1 : KC;
+  float2 v[A];
+#pragma unroll
+  for (int m = 0; m < A; ++m) v[m] = lds[m * fused_row<A, KC>() + lds_pad_index(tid)];
+  dft<A>(v);
+  const int c = tid % C, kk = (tid / C) % K, lp = tid / KC;
+  float2* d = dst + ft.out_base + (kk + a.res_mask * lp) * a.oks + c;
+#pragma unroll
+  for (int k2 = 0; k2 < A; ++k2) {
+    float2 w = cmul(v[k2], twp[(ft.r * k2) & a.twp_mask]);
+    if (a.conj_out) w.y = -w.y;
+    d[k2 * a.ijs] = w;
+  }
+}
+
+// One tile per workgroup.
 template <int A, int KC, int CONTIG>
 __global__ void __launch_bounds__(A* KC)
 fft_fused_axes_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
                       const float2* __restrict__ twp, const PassArgs a) {
-  constexpr int K = CONTIG ? KC : 1;
-  constexpr int C = CONTIG ? 1 : KC;
-  constexpr int SJ = fused_row<A, KC>();
-  __shared__ float2 lds[A * SJ];
+  __shared__ float2 lds[A * fused_row<A, KC>()];
   const int tid = threadIdx.x;
-  const int64_t t = blockIdx.x;
-  const int64_t f0 = t & a.m0, f1 = (t >> a.s0) & a.m1, f2 = t >> a.s1;
-  const int64_t in_base = f0 * a.is0 + f1 * a.is1 + f2 * a.is2;
-  const int64_t out_base = f0 * a.os0 + f1 * a.os1 + f2 * a.os2;
-  const int64_t RM = a.ijs, SD = a.oks, b = a.res_mask;
-
-  // stage 1: run (c, kk, m), elements l along axis d
-  {
-    const int c = tid % C, kk = (tid / C) % K, m = tid / KC;
-    const float2* s = src + in_base + m * RM + (int64_t)(kk * A) * SD + c;
-    float2 v[A];
-#pragma unroll
-    for (int l = 0; l < A; ++l) {
-      v[l] = s[l * SD];
-      if (a.conj_in) v[l].y = -v[l].y;
-    }
-    dft<A>(v);
-    float2* row = lds + m * SJ;
-#pragma unroll
-    for (int lp = 0; lp < A; ++lp) row[lds_pad_index(c + C * (kk + K * lp))] = v[lp];
-  }
+  const FusedTile ft = fused_tile(blockIdx.x, a);
+  float2 v[A];
+  fused_load<A, KC, CONTIG>(v, src, a, ft, tid);
+  fused_stage1<A, KC, CONTIG>(v, lds, a.conj_in, tid);
   __syncthreads();
-  // stage 2: column j = tid, the a rows m of residue r' = f1
-  {
-    float2 v[A];
-#pragma unroll
-    for (int m = 0; m < A; ++m) v[m] = lds[m * SJ + lds_pad_index(tid)];
-    dft<A>(v);
-    const int c = tid % C, kk = (tid / C) % K, lp = tid / KC;
-    float2* d = dst + out_base + (kk + b * lp) * SD + c;
-#pragma unroll
-    for (int k2 = 0; k2 < A; ++k2) {
-      float2 w = cmul(v[k2], twp[(f1 * k2) & a.twp_mask]);
-      if (a.conj_out) w.y = -w.y;
-      d[k2 * RM] = w;
-    }
+  fused_stage2<A, KC, CONTIG>(lds, dst, twp, a, ft, tid);
+}
+
+// Persistent form: about one workgroup per CU walks the tiles w, w + G, ...
+// and loads the next tile's runs into registers as soon as the current
+// tile's first stage has left them, so the loads are in flight during the
+// second stage and the stores.  Past the last tile the prefetch re-reads
+// the last tile (in bounds).
+template <int A, int KC, int CONTIG>
+__global__ void __launch_bounds__(A* KC)
+fft_fused_axes_persistent(const float2* src, float2* dst, const float2* __restrict__ tw,
+                          const float2* __restrict__ twp, const PassArgs a) {
+  __shared__ float2 lds[A * fused_row<A, KC>()];
+  const int tid = threadIdx.x;
+  const int64_t ntiles = a.B, G = gridDim.x, last = ntiles - 1;
+  int64_t w = blockIdx.x;
+  if (w >= ntiles) return;
+  float2 v[A];
+  fused_load<A, KC, CONTIG>(v, src, a, fused_tile(w, a), tid);
+  while (true) {
+    fused_stage1<A, KC, CONTIG>(v, lds, a.conj_in, tid);
+    __syncthreads();
+    const int64_t wn = w + G;
+    fused_load<A, KC, CONTIG>(v, src, a, fused_tile(wn < last ? wn : last, a), tid);
+    fused_stage2<A, KC, CONTIG>(lds, dst, twp, a, fused_tile(w, a), tid);
+    __syncthreads();  // every read of the tile is done before the next writes
+    w = wn;
+    if (w >= ntiles) break;
   }
 }
 
@@ -85,13 +139,38 @@ hipError_t launch_fused_axes(const PassArgs& a, const float2* src, float2* dst,
   return hipGetLastError();
 }
 
+int device_cu_count();
+
 template <int A, int KC, int CONTIG>
+hipError_t launch_fused_axes_persistent(const PassArgs& a, const float2* src, float2* dst,
+                                        const float2* tw, const float2* twp,
+                                        hipStream_t stream) {
+  if (a.B <= 0) return hipSuccess;
+  static int per_cu = -1;  // resident workgroups per CU for this kernel
+  if (per_cu < 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, fft_fused_axes_persistent<A, KC, CONTIG>, A * KC, 0) != hipSuccess)
+      return hipGetLastError();
+    per_cu = nb > 0 ? nb : 1;
+  }
+  int64_t grid = (int64_t)device_cu_count() * per_cu;
+  if (grid > a.B) grid = a.B;
+  hipLaunchKernelGGL((fft_fused_axes_persistent<A, KC, CONTIG>), dim3((unsigned)grid),
+                     dim3(A * KC), 0, stream, src, dst, tw, twp, a);
+  return hipGetLastError();
+}
+
+template <int A, int KC, int CONTIG, int PERS>
 KernelInfo kernel_info_fused_axes() {
   constexpr int LDS = A * fused_row<A, KC>() * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(A * KC <= 1024, "workgroup too large");
   const int mode = CONTIG ? MODE_ROW : MODE_COL;
-  KernelInfo k{A, KC, mode, mode, 1, A * KC, LDS, &launch_fused_axes<A, KC, CONTIG>, 0, 0, 0};
+  KernelInfo k{A, KC, mode, mode, 1, A * KC, LDS,
+               PERS ? &launch_fused_axes_persistent<A, KC, CONTIG>
+                    : &launch_fused_axes<A, KC, CONTIG>,
+               PERS, 0, 0};
   k.fused_axes = 1;
   return k;
 }

@@ -63,8 +63,8 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
 // The fused volumetric two-axis kernel for split factor a, if compiled
-// (contig: V2 runs contiguous in memory).
-const KernelInfo* find_fused_axes_kernel(int a, int contig);
+// (contig: V2 runs contiguous in memory; the persistent form if asked for).
+const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent);
 // The split-precision MFMA pass kernel for a length and layout, if any
 // (the persistent form when asked for and compiled, else the other form).
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,

@@ -3,9 +3,13 @@
 
 namespace dft3d {
 void register_kernels_fused(std::vector<KernelInfo>& v) {
-  v.push_back(kernel_info_fused_axes<32, 16, 1>());
-  v.push_back(kernel_info_fused_axes<32, 16, 0>());
-  v.push_back(kernel_info_fused_axes<16, 16, 1>());
-  v.push_back(kernel_info_fused_axes<16, 32, 0>());
+  v.push_back(kernel_info_fused_axes<32, 16, 1, 0>());
+  v.push_back(kernel_info_fused_axes<32, 16, 0, 0>());
+  v.push_back(kernel_info_fused_axes<16, 16, 1, 0>());
+  v.push_back(kernel_info_fused_axes<16, 32, 0, 0>());
+  v.push_back(kernel_info_fused_axes<32, 16, 1, 1>());
+  v.push_back(kernel_info_fused_axes<32, 16, 0, 1>());
+  v.push_back(kernel_info_fused_axes<16, 16, 1, 1>());
+  v.push_back(kernel_info_fused_axes<16, 32, 0, 1>());
 }
 }  // namespace dft3d

@@ -41,11 +41,15 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   return nullptr;
 }
 
-const KernelInfo* find_fused_axes_kernel(int a, int contig) {
+const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent) {
   const int mode = contig ? MODE_ROW : MODE_COL;
+  const KernelInfo* other = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.fused_axes && k.n == a && k.lmode == mode) return &k;
-  return nullptr;
+    if (k.fused_axes && k.n == a && k.lmode == mode) {
+      if (k.persistent == persistent) return &k;
+      other = &k;
+    }
+  return other;
 }
 
 const KernelInfo* find_plane_kernel(int n1, int n2) {

@@ -317,3 +317,8 @@ def test_volumetric_fused_axes_kernels(shape):
         assert oracle.rel_l2(y, ref_fftn(x, sign)) <= oracle.tol(x.size), (sign,)
         y0 = gpu_fftn(x, "volumetric", inverse=inv, fused_axes=0)
         assert oracle.rel_l2(y, y0) <= oracle.tol(x.size)
+        # the persistent (prefetching) form of the fused kernels
+        dp = dft3d.describe(shape, "volumetric", nontemporal=1)
+        assert all(p["persistent"] for p in dp["passes"] if p["fused_axes"])
+        yp = gpu_fftn(x, "volumetric", inverse=inv, nontemporal=1)
+        assert oracle.rel_l2(yp, ref_fftn(x, sign)) <= oracle.tol(x.size), (sign, "pers")
