@@ -157,9 +157,10 @@ int dft3d_set_workspace(dft3d_plan_t plan, void* dev_ptr, size_t bytes);
 /* Enqueue the transform on `stream` (a hipStream_t; NULL = default stream)
  * and return.  in, out: device pointers of n0 n1 n2 complex64, distinct and
  * non-overlapping (in == out is INVALID_ARG); in is never written.
- * sign = -1 forward, +1 inverse, anything else INVALID_ARG.  Launch errors
- * are returned (HIP_ERROR); faults inside kernels surface at the caller's
- * next synchronisation.  Once the plan has a workspace (bound with
+ * sign = -1 forward, +1 inverse, anything else INVALID_ARG.  The current
+ * device must be the one the plan was created on (INVALID_ARG otherwise).
+ * Launch errors are returned (HIP_ERROR); faults inside kernels surface at
+ * the caller's next synchronisation.  Once the plan has a workspace (bound with
  * dft3d_set_workspace or allocated by an earlier execute) and has executed
  * once on the device, a call only launches kernels on `stream`: no
  * allocation, synchronisation or memset, so it may be captured into a HIP

@@ -321,8 +321,12 @@ int dft3d_plan_set_option(dft3d_plan_t p, int key, int64_t value) {
   int st = apply_option(p->opt, key, value);
   if (st != DFT3D_OK) return st;
   st = rebuild(p);
-  if (st != DFT3D_OK) p->opt = saved;  // previous pass list stays in force
-  else destroy_twin(p);                  // rebuilt from the new options on demand
+  if (st != DFT3D_OK) {
+    p->opt = saved;  // previous pass list stays in force
+  } else {
+    destroy_twin(p);        // rebuilt from the new options on demand
+    batch_forget_plan(p);   // batched descriptors of the old pass list
+  }
   return st;
 }
 
@@ -368,8 +372,24 @@ int dft3d_set_workspace(dft3d_plan_t p, void* dev_ptr, size_t bytes) {
 }
 
 
+namespace {
+// Plans run on the device they were created on.
+int check_device(const dft3d_plan_s* p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return DFT3D_ERR_HIP;
+  }
+  return dev == p->device ? DFT3D_OK : DFT3D_ERR_INVALID_ARG;
+}
+}  // namespace
+
 int dft3d_execute(dft3d_plan_t p, const void* in, void* out, int sign, void* stream) {
   if (!p || !in || !out || (sign != -1 && sign != 1)) return DFT3D_ERR_INVALID_ARG;
+  {
+    const int st = check_device(p);
+    if (st != DFT3D_OK) return st;
+  }
   const size_t bytes = (size_t)(p->n[0] * p->n[1] * p->n[2]) * sizeof(float2);
   if (overlaps(in, out, bytes)) return DFT3D_ERR_INVALID_ARG;
   {
@@ -413,6 +433,8 @@ int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
     if (!plans[i] || !in[i] || !out[i]) return DFT3D_ERR_INVALID_ARG;
     if (plans[i]->layout != DFT3D_LAYOUT_NATURAL || plans[i]->opt.precision != 0)
       return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+    const int st = check_device(plans[i]);
+    if (st != DFT3D_OK) return st;
     const size_t bytes =
         (size_t)(plans[i]->n[0] * plans[i]->n[1] * plans[i]->n[2]) * sizeof(float2);
     if (overlaps(in[i], out[i], bytes)) return DFT3D_ERR_INVALID_ARG;
