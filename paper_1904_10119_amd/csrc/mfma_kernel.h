@@ -233,22 +233,33 @@ __device__ __forceinline__ void mfma_load(float2 (&v)[kMfmaRegs], const float2* 
 // hold the same vector's rows 0..3 and 4..7 (of the lane group's eight) and
 // exchange halves across the 32-lane boundary so that lane l feeds real
 // parts and lane l + 32 imaginary parts to the matrix cores.
+//
+// The matrix cores do not round their dot products to nearest: measured on
+// random operands the result carries a bias of a fraction of an ulp of one
+// sign.  Summed coherently by the later stages and axes (at the DC bins)
+// that bias grows with the transform size, so every other vector (by the
+// parity of pencil + butterfly) is transformed negated and negated back,
+// which makes the bias alternate in sign and cancel in those sums.  The
+// negations are exact.
 template <int N, int PREC>
 __device__ __forceinline__ void mfma_leaf_store(const float2 (&x)[4], const LeafA<PREC>& A,
                                                 float2* out, int q, int t, int NS, int lane) {
+  const float sgn = ((q + t) & 1) ? -1.0f : 1.0f;
   float xs[8];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     // lane < 32 keeps its real part and gets the partner's; lane >= 32
     // gets the partner's imaginary part and keeps its own
-    const auto sw = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x[k].x),
-                                                     __builtin_bit_cast(unsigned, x[k].y),
-                                                     false, false);
+    const auto sw = __builtin_amdgcn_permlane32_swap(
+        __builtin_bit_cast(unsigned, x[k].x * sgn), __builtin_bit_cast(unsigned, x[k].y * sgn),
+        false, false);
     xs[k] = __builtin_bit_cast(float, (unsigned)sw[0]);
     xs[4 + k] = __builtin_bit_cast(float, (unsigned)sw[1]);
   }
   f32x4_t yr, yi;
   leaf16<PREC>(A, xs, yr, yi);
+  yr *= sgn;
+  yi *= sgn;
   const int h = lane >> 4;
   const int tm = t & (NS - 1);
   const int base = (t / NS) * NS * 16 + tm;

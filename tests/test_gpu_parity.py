@@ -183,14 +183,14 @@ def test_persistent_matches_one_tile_per_workgroup(shape, schedule):
     assert oracle.rel_l2(outs[0], outs[1]) <= oracle.tol(x.size)
 
 
-def full_size_check(shape, schedule, seed, nsamp=12):
+def full_size_check(shape, schedule, seed, nsamp=12, **opts):
     """Full-size transform in the launch configuration bench.py times:
     sampled output pencils y[k0, k1, :] against the oracle's direct sums,
     Parseval over the whole array, and the inverse round trip."""
-    say("case full size", shape, schedule)
+    say("case full size", shape, schedule, opts)
     x = inputs.uniform_c64(shape, seed)
     xt = torch.from_numpy(x).cuda()
-    y = dft3d.fftn(xt, schedule=schedule)
+    y = dft3d.fftn(xt, schedule=schedule, **opts)
     torch.cuda.synchronize()
     N = x.size
     g = np.random.default_rng(seed)
@@ -206,7 +206,7 @@ def full_size_check(shape, schedule, seed, nsamp=12):
     ey = torch.sum(torch.view_as_real(y).double() ** 2).item()
     assert abs(ey / (N * ex) - 1.0) <= 2 * oracle.tol(N)
     # round trip: inverse(forward(x)) / N == x
-    back = dft3d.fftn(y, schedule=schedule, inverse=True)
+    back = dft3d.fftn(y, schedule=schedule, inverse=True, **opts)
     d = torch.view_as_real(back).double() / N - torch.view_as_real(xt).double()
     rt = (torch.linalg.vector_norm(d) /
           torch.linalg.vector_norm(torch.view_as_real(xt).double())).item()
@@ -223,6 +223,25 @@ def test_full_1024_cubed(schedule):
 
 def test_full_2048x1024x512():
     full_size_check((2048, 1024, 512), "auto", 5)
+
+
+@pytest.mark.parametrize("precision", ["bf16x6", "bf16x9", "fp16x3"])
+def test_full_1024_cubed_split_precision(precision):
+    """The split-precision leaves at full size, as the benchmark runs them."""
+    full_size_check((1024, 1024, 1024), "pencil", 2, precision=precision)
+
+
+def test_full_2048x1024x512_bf16x6():
+    full_size_check((2048, 1024, 512), "auto", 5, precision="bf16x6")
+
+
+@pytest.mark.parametrize("shape", [(4096, 4096, 16), (16, 4096, 4096)])
+def test_longest_axes(shape):
+    """The longest supported axes (4096, split four-step by the auto
+    schedule: five passes) in a 2 GiB array."""
+    d = dft3d.describe(shape, "auto")
+    assert d["schedule"] == "pencil" and len(d["passes"]) == 5
+    full_size_check(shape, "auto", 7, nsamp=8)
 
 
 @pytest.mark.parametrize("group", [1, 4, 16])
