@@ -178,10 +178,16 @@ int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
  * for repeated plans); later calls with the same sequence only refresh the
  * buffer pointers.  Plans whose passes exceed length 256 run one after
  * another.  count == 0 is a no-op.  Plans must use the NATURAL layout and
- * FP32.  Not thread-safe for concurrent calls with overlapping plans.  The
- * call waits for its previous descriptor upload, so it cannot be captured
- * into a HIP graph: on a capturing stream it returns
- * DFT3D_ERR_UNSUPPORTED_SCHEDULE before enqueueing anything. */
+ * FP32.  Not thread-safe for concurrent calls with overlapping plans.
+ * A call with the same plans, buffers and sign as the previous one reuses
+ * the descriptors already on the device (no upload).  Capture into a HIP
+ * graph: on a capturing stream the call records only its kernel launches,
+ * so an earlier call outside the capture must have used exactly these
+ * plans, buffers and sign (and bound every workspace); otherwise it returns
+ * DFT3D_ERR_UNSUPPORTED_SCHEDULE before enqueueing anything.  Those
+ * descriptors then stay fixed while the plans live (later calls with other
+ * buffers get descriptor sets of their own); destroying or changing a plan
+ * invalidates graphs that captured it. */
 int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
                           void* const* out, int count, int sign, void* stream);
 

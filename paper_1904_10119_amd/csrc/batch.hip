@@ -1,8 +1,9 @@
 // Host side of the batched form (dft3d_execute_batched): turns a sequence
 // of plans into the work items of batch_level_kernel (and, for fused plane
-// passes, batch_plane_level_kernel) once per sequence of plans, and on
-// every call refreshes the buffer pointers, uploads the descriptors and
-// launches one kernel per pass level and item kind.
+// passes, batch_plane_level_kernel) once per sequence of plans; a call
+// whose buffers differ from what the device descriptors hold refreshes and
+// uploads them, and every call launches one kernel per pass level and item
+// kind.  Under stream capture only the launches are recorded.
 #include <atomic>
 #include <cstdlib>
 #include <cstring>
@@ -59,6 +60,20 @@ struct BatchGraph {
   hipEvent_t copied = nullptr;        // the last upload has read staging
   bool launched = false;
   int device = -1;
+  // What the device descriptors hold now (per item: source, destination,
+  // conjugation flags); a call with the same values needs no upload.
+  struct Ptrs {
+    const float2* src;
+    float2* dst;
+    int conj_in, conj_out;
+    bool operator==(const Ptrs& o) const {
+      return src == o.src && dst == o.dst && conj_in == o.conj_in && conj_out == o.conj_out;
+    }
+  };
+  std::vector<Ptrs> last;
+  // Captured into a HIP graph: the descriptors must not change while the
+  // plans live; calls with other buffers use another descriptor set.
+  bool frozen = false;
 
   void release() {
     if (copied) {
@@ -164,34 +179,71 @@ int build_batch(BatchGraph* g, dft3d_plan_s* const* plans, int count) {
   return DFT3D_OK;
 }
 
-BatchGraph* find_cached(dft3d_plan_s* const* plans, int count, int device) {
+// Per-item pointers and flags of a call.
+void item_ptrs(const BatchGraph* g, dft3d_plan_s* const* plans, const void* const* in,
+               void* const* out, int sign, std::vector<BatchGraph::Ptrs>& cur) {
+  cur.resize(g->items.size());
+  for (size_t k = 0; k < g->items.size(); ++k) {
+    const dft3d_plan_s* p = plans[g->item_plan[k]];
+    const Pass& ps = p->passes[g->item_pass[k]];
+    const int i = g->item_plan[k];
+    void* ws = g->ws[i] ? g->ws[i] : p->ws;
+    float2* bufs[3] = {const_cast<float2*>(static_cast<const float2*>(in[i])),
+                       static_cast<float2*>(out[i]), static_cast<float2*>(ws)};
+    cur[k].src = bufs[ps.src] + ps.in_off;
+    cur[k].dst = bufs[ps.dst] + ps.out_off;
+    cur[k].conj_in = (sign == 1 && ps.src == BUF_IN) ? 1 : 0;
+    cur[k].conj_out = (sign == 1 && g->item_pass[k] + 1 == (int)p->passes.size()) ? 1 : 0;
+  }
+}
+
+// The cached descriptor set for this sequence of plans: one whose device
+// descriptors already match the call if there is one, otherwise one that
+// is not frozen (its descriptors get refreshed); null if neither exists.
+BatchGraph* find_cached(dft3d_plan_s* const* plans, const void* const* in, void* const* out,
+                        int count, int sign, int device, std::vector<BatchGraph::Ptrs>& cur) {
+  BatchGraph* reuse = nullptr;
+  size_t reuse_at = 0;
   for (size_t c = 0; c < g_cache.size(); ++c) {
     BatchGraph* g = g_cache[c];
     if ((int)g->plans.size() != count || g->device != device) continue;
     bool same = true;
     for (int i = 0; i < count && same; ++i)
       same = g->plans[i] == plans[i] && g->uids[i] == plans[i]->uid;
-    if (same) {  // move to most recent
+    if (!same) continue;
+    item_ptrs(g, plans, in, out, sign, cur);
+    if (g->launched && g->last == cur) {  // move to most recent
       g_cache.erase(g_cache.begin() + (long)c);
       g_cache.push_back(g);
       return g;
     }
+    if (!g->frozen && !reuse) {
+      reuse = g;
+      reuse_at = c;
+    }
   }
-  return nullptr;
+  if (reuse) {
+    g_cache.erase(g_cache.begin() + (long)reuse_at);
+    g_cache.push_back(reuse);
+    item_ptrs(reuse, plans, in, out, sign, cur);
+  }
+  return reuse;
 }
 
 }  // namespace
 
 int batch_execute(dft3d_plan_s* const* given, const void* const* in, void* const* out,
                   int count, int sign, hipStream_t stream) {
-  {  // the descriptor upload synchronises with the previous call: not capturable
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
-      (void)hipGetLastError();
-      return DFT3D_ERR_HIP;
-    }
-    if (cs != hipStreamCaptureStatusNone) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+  // Under stream capture only kernel launches may be recorded: the call
+  // must find descriptors already on the device for exactly these plans,
+  // buffers and sign (left there by an earlier call outside the capture).
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return DFT3D_ERR_HIP;
   }
+  if (cs == hipStreamCaptureStatusInvalidated) return DFT3D_ERR_HIP;
+  const bool capturing = cs == hipStreamCaptureStatusActive;
   // plans with fused plane passes run as their twins without them
   std::vector<dft3d_plan_s*> views((size_t)count);
   for (int i = 0; i < count; ++i) {
@@ -201,6 +253,9 @@ int batch_execute(dft3d_plan_s* const* given, const void* const* in, void* const
   dft3d_plan_s* const* plans = views.data();
   bool all = true;
   for (int i = 0; i < count; ++i) {
+    // a capture cannot allocate: workspaces must exist already
+    if (capturing && plans[i]->ws_need > 0 && (!plans[i]->ws || plans[i]->ws_bytes < plans[i]->ws_need))
+      return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
     const int st = ensure_workspace(plans[i]);
     if (st != DFT3D_OK) return st;
     all = all && batchable(plans[i]);
@@ -216,43 +271,51 @@ int batch_execute(dft3d_plan_s* const* given, const void* const* in, void* const
   if (hipGetDevice(&device) != hipSuccess) return DFT3D_ERR_HIP;
 
   std::lock_guard<std::mutex> lock(g_mutex);
-  BatchGraph* g = find_cached(plans, count, device);
-  if (!g) {
-    g = new BatchGraph();
-    const int st = build_batch(g, plans, count);
-    if (st != DFT3D_OK) {
-      g->release();
-      delete g;
-      return st;
+  std::vector<BatchGraph::Ptrs> cur;
+  BatchGraph* g = find_cached(plans, in, out, count, sign, device, cur);
+  const bool ready = g && g->launched && g->last == cur;
+  if (capturing) {
+    if (!ready) return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+    g->frozen = true;
+  } else if (!ready) {
+    if (!g) {
+      g = new BatchGraph();
+      const int st = build_batch(g, plans, count);
+      if (st != DFT3D_OK) {
+        g->release();
+        delete g;
+        return st;
+      }
+      g_cache.push_back(g);
+      item_ptrs(g, plans, in, out, sign, cur);
+      // evict the oldest set that no graph holds
+      if (g_cache.size() > kCacheMax) {
+        for (size_t c = 0; c + 1 < g_cache.size(); ++c) {
+          if (g_cache[c]->frozen) continue;
+          g_cache[c]->release();
+          delete g_cache[c];
+          g_cache.erase(g_cache.begin() + (long)c);
+          break;
+        }
+      }
     }
-    g_cache.push_back(g);
-    if (g_cache.size() > kCacheMax) {
-      g_cache.front()->release();
-      delete g_cache.front();
-      g_cache.erase(g_cache.begin());
+    // the previous upload must have read the staging copy before it changes
+    if (g->launched && hipEventSynchronize(g->copied) != hipSuccess) return DFT3D_ERR_HIP;
+    for (size_t k = 0; k < g->items.size(); ++k) {
+      BatchItem& it = g->staging[k];
+      it.src = cur[k].src;
+      it.dst = cur[k].dst;
+      it.a.conj_in = cur[k].conj_in;
+      it.a.conj_out = cur[k].conj_out;
     }
+    const size_t bytes = sizeof(BatchItem) * g->items.size();
+    if (hipMemcpyAsync(g->d_items, g->staging, bytes, hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipEventRecord(g->copied, stream) != hipSuccess)
+      return DFT3D_ERR_HIP;
+    g->launched = true;
+    g->last = cur;
   }
-  // the previous upload must have read the staging copy before it changes
-  if (g->launched && hipEventSynchronize(g->copied) != hipSuccess) return DFT3D_ERR_HIP;
-  for (size_t k = 0; k < g->items.size(); ++k) {
-    const dft3d_plan_s* p = plans[g->item_plan[k]];
-    const Pass& ps = p->passes[g->item_pass[k]];
-    const int i = g->item_plan[k];
-    void* ws = g->ws[i] ? g->ws[i] : p->ws;
-    float2* bufs[3] = {const_cast<float2*>(static_cast<const float2*>(in[i])),
-                       static_cast<float2*>(out[i]), static_cast<float2*>(ws)};
-    BatchItem& it = g->staging[k];
-    it.src = bufs[ps.src] + ps.in_off;
-    it.dst = bufs[ps.dst] + ps.out_off;
-    it.a.conj_in = (sign == 1 && ps.src == BUF_IN) ? 1 : 0;
-    it.a.conj_out = (sign == 1 && g->item_pass[k] + 1 == (int)p->passes.size()) ? 1 : 0;
-  }
-  const size_t bytes = sizeof(BatchItem) * g->items.size();
-  if (hipMemcpyAsync(g->d_items, g->staging, bytes, hipMemcpyHostToDevice, stream) !=
-          hipSuccess ||
-      hipEventRecord(g->copied, stream) != hipSuccess)
-    return DFT3D_ERR_HIP;
-  g->launched = true;
   for (const BatchGraph::Level& L : g->levels) {
     if (L.ntiles <= 0) continue;
     if (L.planes == 1)

@@ -48,21 +48,6 @@ DFT3D_BLOCKING(2048, 32, 32, 8, 8)
 DFT3D_BLOCKING(4096, 32, 32, 16, 8)
 #undef DFT3D_BLOCKING
 
-// Blocking with 16 elements per thread (three radix stages for the longest
-// lengths): half the registers per pencil element, used by the persistent
-// form, which keeps a second tile in flight in registers.
-template <int N> struct BlockingLow;
-#define DFT3D_BLOCKING_LOW(N_, E_, R0_, R1_, R2_)                           \
-  template <> struct BlockingLow<N_> {                                      \
-    static constexpr int E = E_, R0 = R0_, R1 = R1_, R2 = R2_;              \
-  };
-DFT3D_BLOCKING_LOW(256, 16, 16, 16, 1)
-DFT3D_BLOCKING_LOW(512, 16, 16, 16, 2)
-DFT3D_BLOCKING_LOW(1024, 16, 16, 16, 4)
-DFT3D_BLOCKING_LOW(2048, 16, 16, 16, 8)
-DFT3D_BLOCKING_LOW(4096, 16, 16, 16, 16)
-#undef DFT3D_BLOCKING_LOW
-
 // Blocking with 64 elements per thread for the persistent 2048 kernel: a
 // tile of 8 pencils runs on 256 threads (one wave per SIMD), whose register
 // budget holds the current and the prefetched tile without scratch.

@@ -82,3 +82,69 @@ def test_graph_replay_matches_eager(shape, schedule, layout):
         x.copy_(torch.from_numpy(inputs.uniform_c64(shape, 41)))
         del g
     p.close()
+
+
+def test_batched_graph_replay_matches_eager():
+    """Batched execution captured after an eager call with the same buffers:
+    replays reproduce the eager result bit for bit, also after eager batched
+    calls with other output buffers in between (which must not disturb the
+    captured descriptors), and transform new values put in the inputs."""
+    shapes = [(32, 64, 128), (64, 64, 64), (8, 16, 4), (128, 32, 16), (32, 32, 32)]
+    xs = [torch.from_numpy(inputs.uniform_c64(s, 50 + i)).cuda() for i, s in enumerate(shapes)]
+    outs = [torch.empty_like(x) for x in xs]
+    for inverse in (False, True):
+        dft3d.fftn_batched(xs, outs=outs, inverse=inverse)     # eager: descriptors on device
+        torch.cuda.synchronize()
+        eager = [o.clone() for o in outs]
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                dft3d.fftn_batched(xs, outs=outs, inverse=inverse)
+        torch.cuda.current_stream().wait_stream(s)
+        for rep in range(3):
+            for o in outs:
+                o.fill_(float("nan"))
+            g.replay()
+            torch.cuda.synchronize()
+            for o, e in zip(outs, eager):
+                assert torch.equal(o, e), rep
+            other = dft3d.fftn_batched(xs, inverse=inverse)   # other output buffers
+            torch.cuda.synchronize()
+            for o, e in zip(other, eager):
+                assert torch.equal(o, e)
+        new = [inputs.uniform_c64(sh, 80 + i) for i, sh in enumerate(shapes)]
+        for x, n in zip(xs, new):
+            x.copy_(torch.from_numpy(n))
+        g.replay()
+        torch.cuda.synchronize()
+        sign = 1 if inverse else -1
+        for o, n in zip(outs, new):
+            ref = oracle.dft3d(n.astype(np.complex128), sign, "fft")
+            assert oracle.rel_l2(o.cpu().numpy(), ref) <= oracle.tol(n.size)
+        for i, sh in enumerate(shapes):
+            xs[i].copy_(torch.from_numpy(inputs.uniform_c64(sh, 50 + i)))
+        del g
+
+
+def test_batched_capture_without_prior_call_is_refused():
+    shapes = [(16, 16, 16), (8, 8, 8)]
+    xs = [torch.zeros(s, dtype=torch.complex64, device="cuda") for s in shapes]
+    outs = [torch.empty_like(x) for x in xs]
+    plans = [dft3d.Plan(s, "pencil") for s in shapes]     # fresh plans: nothing on device
+    for p, x in zip(plans, xs):
+        p.bind_workspace(x.device)
+    import ctypes
+    arr = ctypes.c_void_p * len(plans)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    st = None
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            st = dft3d.lib().dft3d_execute_batched(
+                arr(*[p.handle.value for p in plans]), arr(*[x.data_ptr() for x in xs]),
+                arr(*[o.data_ptr() for o in outs]), len(plans), -1, s.cuda_stream)
+    assert st == dft3d.ERR_UNSUPPORTED_SCHEDULE
+    for p in plans:
+        p.close()
