@@ -26,9 +26,11 @@ int validate(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout) {
   if (layout != DFT3D_LAYOUT_NATURAL && layout != DFT3D_LAYOUT_SHUFFLED)
     return DFT3D_ERR_INVALID_ARG;
   const int64_t n[3] = {n0, n1, n2};
-  for (int d = 0; d < 3; ++d)
-    if (n[d] < 1 || n[d] > 4096 || (n[d] & (n[d] - 1)) != 0)
-      return DFT3D_ERR_UNSUPPORTED_SIZE;
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 1 || n[d] > 4096) return DFT3D_ERR_UNSUPPORTED_SIZE;
+    // other lengths than powers of two: up to 2048 (Bluestein, m <= 4096)
+    if ((n[d] & (n[d] - 1)) != 0 && n[d] > 2048) return DFT3D_ERR_UNSUPPORTED_SIZE;
+  }
   return DFT3D_OK;
 }
 
@@ -65,8 +67,10 @@ int rebuild(dft3d_plan_s* p) {
   }
 
   // one table per distinct root length (key n > 0) and per MFMA leaf
-  // precision (key -precision, kLeafTableFloat2 slots of 16-bit values)
+  // precision (key -precision, kLeafTableFloat2 slots of 16-bit values);
+  // Bluestein chirp and filter tables per length n (keys (1, n), (2, n))
   std::map<int64_t, int64_t> offsets;
+  std::map<std::pair<int, int64_t>, int64_t> bl_offsets;
   int64_t total = 0;
   std::vector<const Pass*> all;
   for (const Pass& ps : passes) all.push_back(&ps);
@@ -83,6 +87,12 @@ int rebuild(dft3d_plan_s* p) {
       offsets[-ps.leaf] = total;
       total += kLeafTableFloat2;
     }
+    if (ps.k->bluestein && !bl_offsets.count({1, ps.bl_n})) {
+      bl_offsets[{1, ps.bl_n}] = total;
+      total += ps.bl_n;
+      bl_offsets[{2, ps.bl_n}] = total;
+      total += bluestein_length(ps.bl_n);
+    }
   }
   std::vector<float2> host((size_t)total);
   for (auto& kv : offsets) {
@@ -90,6 +100,12 @@ int rebuild(dft3d_plan_s* p) {
       make_roots(kv.first, host.data() + kv.second);
     else
       make_leaf_table((int)-kv.first, reinterpret_cast<unsigned short*>(host.data() + kv.second));
+  }
+  for (auto& kv : bl_offsets) {
+    if (kv.first.first == 1)
+      make_chirp(kv.first.second, host.data() + kv.second);
+    else
+      make_bluestein_filter(kv.first.second, host.data() + kv.second);
   }
 
   float2* dev = nullptr;
@@ -107,11 +123,17 @@ int rebuild(dft3d_plan_s* p) {
   p->tables = dev;
   p->passes.swap(passes);
   p->ipasses.swap(ipasses);
-  auto table_offsets = [&offsets](const std::vector<Pass>& list, std::vector<int64_t>& tw,
-                                  std::vector<int64_t>& twp) {
+  auto table_offsets = [&offsets, &bl_offsets](const std::vector<Pass>& list,
+                                               std::vector<int64_t>& tw,
+                                               std::vector<int64_t>& twp) {
     tw.clear();
     twp.clear();
     for (const Pass& ps : list) {
+      if (ps.k->bluestein) {  // chirp and filter of the length
+        tw.push_back(bl_offsets[{1, ps.bl_n}]);
+        twp.push_back(bl_offsets[{2, ps.bl_n}]);
+        continue;
+      }
       tw.push_back(offsets[ps.tw_len]);
       // post-twiddle table, or the leaf operand table for MFMA passes
       twp.push_back(ps.leaf ? offsets[-ps.leaf] : (ps.twp_len > 0 ? offsets[ps.twp_len] : 0));
@@ -235,7 +257,9 @@ const char* dft3d_status_string(int status) {
   switch (status) {
     case DFT3D_OK: return "ok";
     case DFT3D_ERR_INVALID_ARG: return "invalid argument";
-    case DFT3D_ERR_UNSUPPORTED_SIZE: return "unsupported size (each n_d must be a power of two in [1, 4096])";
+    case DFT3D_ERR_UNSUPPORTED_SIZE:
+      return "unsupported size (each n_d in [1, 4096]; lengths other than powers of two at most "
+             "2048)";
     case DFT3D_ERR_UNSUPPORTED_SCHEDULE: return "unsupported schedule/layout/precision combination";
     case DFT3D_ERR_NO_DEVICE: return "no HIP device";
     case DFT3D_ERR_OUT_OF_MEMORY: return "device out of memory";

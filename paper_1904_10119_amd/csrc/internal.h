@@ -54,6 +54,7 @@ struct KernelInfo {
   int precision = 0; // DFT3D_PREC_*: FP32 butterflies or split MFMA leaves
   int plane_rows = 0; // > 0: fused 2D DFT of (plane_rows, n) planes, one per workgroup
   int fused_axes = 0; // 1: volumetric V2 of one axis fused with V1 of the next (n = a)
+  int bluestein = 0;  // 1 pad, 2 filter, 3 crop: steps of a length that is not a power of two
 };
 
 // All compiled pass kernels.
@@ -62,6 +63,8 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
                               int persistent, int nontemporal);
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
+// The kernel of one Bluestein step (1 pad, 2 filter, 3 crop).
+const KernelInfo* find_bluestein_kernel(int kind);
 // The fused volumetric two-axis kernel for split factor a, if compiled
 // (contig: V2 runs contiguous in memory; the persistent form if asked for).
 const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent);
@@ -78,6 +81,12 @@ void root_fp64(int64_t m, int64_t n, double& c, double& s);
 // MFMA leaf operand table for a precision (kLeafTableHalves 16-bit values).
 constexpr int kLeafTableFloat2 = 3 * 2 * 64 * 8 / 4;  // as float2 slots
 void make_leaf_table(int precision, unsigned short* out);
+// Bluestein tables for a length n that is not a power of two: the chirp
+// w[j] = exp(-pi i j^2 / n) (n entries) and the filter H / m, H = DFT_m of
+// the wrapped conj(w[d]), d in (-n, n) (m entries), both from FP64.
+int64_t bluestein_length(int64_t n);  // m: the power of two >= 2n - 1
+void make_chirp(int64_t n, float2* out);
+void make_bluestein_filter(int64_t n, float2* out);
 
 enum BufId { BUF_IN = 0, BUF_OUT = 1, BUF_WS = 2 };
 
@@ -89,6 +98,10 @@ struct Pass {
   int64_t tw_len = 0;   // root table of the transform length (== k->n)
   int64_t twp_len = 0;  // post-twiddle table length, 0 if none
   int leaf = 0;         // precision of the MFMA leaf table the pass reads, 0: none
+  int64_t bl_n = 0;     // Bluestein steps: the length n (tables: chirp, filter)
+  // Which ends of the pass follow the plan's buffer chain (IN -> OUT/WS
+  // alternation); the others keep the buffers the planner set.
+  bool chain_src = true, chain_dst = true;
   std::string label;
 };
 

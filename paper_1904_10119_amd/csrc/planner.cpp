@@ -94,7 +94,7 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw &&
         k.persistent == 0 && k.nontemporal == nt && k.precision == 0 && k.plane_rows == 0 &&
-        k.fused_axes == 0)
+        k.fused_axes == 0 && k.bluestein == 0)
       return &k;
   return nullptr;
 }
@@ -175,6 +175,32 @@ struct Builder {
     p.args.xcd_remap = 0;
     p.tw_len = a;
     p.twp_len = n_prev;
+    p.label = label;
+    passes.push_back(p);
+  }
+
+  // One Bluestein step (1 pad, 2 filter, 3 crop) over B pencils of length n
+  // (padded length m) with the given buffers; see bluestein.h.
+  void add_bluestein(int kind, int64_t B, int64_t n, int src, int dst, int64_t in_off,
+                     int64_t out_off, bool chain_src, bool chain_dst, const std::string& label) {
+    const KernelInfo* k = find_bluestein_kernel(kind);
+    if (!k) {
+      status = DFT3D_ERR_UNSUPPORTED_SIZE;
+      return;
+    }
+    Pass p;
+    p.k = k;
+    p.args.B = B;
+    p.args.ijs = n;
+    p.args.oks = bluestein_length(n);
+    p.args.xcd_remap = 0;
+    p.src = src;
+    p.dst = dst;
+    p.in_off = in_off;
+    p.out_off = out_off;
+    p.chain_src = chain_src;
+    p.chain_dst = chain_dst;
+    p.bl_n = n;
     p.label = label;
     passes.push_back(p);
   }
@@ -307,9 +333,37 @@ void volumetric_axis_from_shuffled(Builder& b, int64_t outer, int64_t n, int64_t
 // One rotate-on-write step of the pencil schedule on a (c0, c1, c2) array:
 // transform along c2 and write (c2, c0, c1).  With split, the c2 axis goes
 // through V1 (natural) and a rotating V2.
-void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
+void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis, int64_t ws2_off) {
   const int64_t n = cur[2], B = cur[0] * cur[1];
   char lab[64];
+  if (!is_pow2(n)) {
+    // Bluestein (bluestein.h): chain source -> padded pencils in the second
+    // workspace region -> two FFT_m passes and the filter in place -> crop,
+    // written rotated to the chain's next buffer
+    const int64_t m = bluestein_length(n);
+    std::snprintf(lab, sizeof lab, "pencil%d.pad DFT%lld via %lld x%lld", axis, (long long)n,
+                  (long long)m, (long long)B);
+    b.add_bluestein(1, B, n, BUF_IN, BUF_WS, 0, ws2_off, true, false, lab);
+    for (int half = 0; half < 2; ++half) {
+      if (half == 1) {
+        std::snprintf(lab, sizeof lab, "pencil%d.filter %lld", axis, (long long)m);
+        b.add_bluestein(2, B, n, BUF_WS, BUF_WS, ws2_off, ws2_off, false, false, lab);
+      }
+      Field f[1] = {{B, m, m}};
+      std::snprintf(lab, sizeof lab, "pencil%d.fft%d DFT%lld x%lld", axis, half, (long long)m,
+                    (long long)B);
+      b.add((int)m, MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
+      if (b.status != DFT3D_OK) return;
+      Pass& ps = b.passes.back();
+      ps.src = ps.dst = BUF_WS;
+      ps.in_off = ps.out_off = ws2_off;
+      ps.chain_src = ps.chain_dst = false;
+    }
+    std::snprintf(lab, sizeof lab, "pencil%d.crop DFT%lld x%lld rot", axis, (long long)n,
+                  (long long)B);
+    b.add_bluestein(3, B, n, BUF_WS, BUF_OUT, ws2_off, 0, false, true, lab);
+    return;
+  }
   if (!split) {
     Field f[1] = {{B, n, 1}};
     std::snprintf(lab, sizeof lab, "pencil%d DFT%lld x%lld rot", axis, (long long)n,
@@ -337,12 +391,14 @@ void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
 // Buffers for a chain of passes from IN to OUT that never writes IN and
 // never reads and writes the same buffer in one (not in-place-safe) pass.
 void assign_chain(std::vector<Pass>& passes, size_t first, size_t& ws_needed_flag) {
-  const size_t cnt = passes.size() - first;
-  // Alternate OUT / WS so that the last pass writes OUT.
+  size_t cnt = 0;  // steps of the chain (passes whose destination follows it)
+  for (size_t i = first; i < passes.size(); ++i) cnt += passes[i].chain_dst ? 1 : 0;
+  // Alternate OUT / WS so that the last step writes OUT.
   int dst = (cnt % 2 == 1) ? BUF_OUT : BUF_WS;
   int src = BUF_IN;
   for (size_t i = first; i < passes.size(); ++i) {
-    passes[i].src = src;
+    if (passes[i].chain_src) passes[i].src = src;
+    if (!passes[i].chain_dst) continue;
     passes[i].dst = dst;
     if (dst == BUF_WS) ws_needed_flag = 1;
     src = dst;
@@ -357,13 +413,24 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
                  bool from_layout) {
   passes.clear();
   ws_bytes = 0;
-  for (int d = 0; d < 3; ++d)
-    if (!is_pow2(n[d]) || n[d] > 4096) return DFT3D_ERR_UNSUPPORTED_SIZE;
+  // powers of two up to 4096; other lengths up to 2048 through Bluestein
+  // steps (pencil schedule, FP32, natural layout only)
+  bool any_other = false;
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 1 || n[d] > 4096) return DFT3D_ERR_UNSUPPORTED_SIZE;
+    if (!is_pow2(n[d])) {
+      if (n[d] > 2048) return DFT3D_ERR_UNSUPPORTED_SIZE;
+      any_other = true;
+    }
+  }
   if (schedule < DFT3D_SCHED_AUTO || schedule > DFT3D_SCHED_VOLUMETRIC)
     return DFT3D_ERR_INVALID_ARG;
   if (layout != DFT3D_LAYOUT_NATURAL && layout != DFT3D_LAYOUT_SHUFFLED)
     return DFT3D_ERR_INVALID_ARG;
   const bool shuffled = layout == DFT3D_LAYOUT_SHUFFLED;
+  if (any_other && (shuffled || opt.precision != DFT3D_PREC_FP32 ||
+                    (schedule != DFT3D_SCHED_PENCIL && schedule != DFT3D_SCHED_AUTO)))
+    return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
   // only the volumetric schedule has a digit exchange to leave out
   if (shuffled && schedule != DFT3D_SCHED_VOLUMETRIC && schedule != DFT3D_SCHED_AUTO)
     return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
@@ -373,7 +440,8 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
   resolved = schedule;
   if (schedule == DFT3D_SCHED_AUTO)
     resolved = shuffled ? DFT3D_SCHED_VOLUMETRIC
-                        : (total * 8 < kStreamBytes ? DFT3D_SCHED_SLAB : DFT3D_SCHED_PENCIL);
+                        : ((total * 8 < kStreamBytes && !any_other) ? DFT3D_SCHED_SLAB
+                                                                    : DFT3D_SCHED_PENCIL);
   // Untuned AUTO splits only 4096-long axes (a 4096 pencil leaves tiles of
   // four pencils); measured at 2048x1024x512, the 2048 pass beats its split.
   const int64_t split_max =
@@ -381,11 +449,18 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
                         : (schedule == DFT3D_SCHED_AUTO ? 2048 : int64_t(1) << 20);
 
   size_t need_ws = 0;
+  int64_t ws2 = 0;  // elements of the Bluestein region, after the chain's N
   if (resolved == DFT3D_SCHED_PENCIL) {
     int64_t cur[3] = {n[0], n[1], n[2]};
+    for (int d = 0; d < 3; ++d)
+      if (!is_pow2(n[d])) ws2 = std::max(ws2, (total / n[d]) * bluestein_length(n[d]));
     for (int step = 0; step < 3; ++step) {
       const int axis = 2 - step;
-      pencil_axis(b, cur, cur[2] > split_max && cur[2] >= 4, axis);
+      // a split needs power-of-two pencil counts (bit-field pencil indices)
+      const bool split = is_pow2(cur[2]) && cur[2] > split_max && cur[2] >= 4 &&
+                         is_pow2(cur[0] * cur[1]);
+      pencil_axis(b, cur, split, axis, total);
+      if (b.status != DFT3D_OK) break;
       const int64_t c2 = cur[2];
       cur[2] = cur[1];
       cur[1] = cur[0];
@@ -506,7 +581,8 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
     passes.clear();
     return b.status;
   }
-  ws_bytes = need_ws ? (size_t)total * 8 : 0;
+  if (ws2 > 0) need_ws = 1;  // the Bluestein region sits after the chain's N
+  ws_bytes = need_ws ? (size_t)(total + ws2) * 8 : 0;
   return DFT3D_OK;
 }
 
@@ -523,6 +599,7 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << p.k->post_twiddle << ",\"persistent\":" << p.k->persistent
        << ",\"nontemporal\":" << p.k->nontemporal << ",\"precision\":" << p.k->precision
        << ",\"plane_rows\":" << p.k->plane_rows << ",\"fused_axes\":" << p.k->fused_axes
+       << ",\"bluestein\":" << p.k->bluestein << ",\"bl_n\":" << p.bl_n
        << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""

@@ -12,6 +12,7 @@ void register_kernels_mfma_b(std::vector<KernelInfo>& v);
 void register_kernels_mfma_c(std::vector<KernelInfo>& v);
 void register_kernels_plane(std::vector<KernelInfo>& v);
 void register_kernels_fused(std::vector<KernelInfo>& v);
+void register_kernels_bluestein(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -25,6 +26,7 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_mfma_c(v);
     register_kernels_plane(v);
     register_kernels_fused(v);
+    register_kernels_bluestein(v);
     return v;
   }();
   return table;
@@ -38,6 +40,12 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
         k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0 &&
         k.fused_axes == 0)
       return &k;
+  return nullptr;
+}
+
+const KernelInfo* find_bluestein_kernel(int kind) {
+  for (const KernelInfo& k : kernel_registry())
+    if (k.bluestein == kind) return &k;
   return nullptr;
 }
 

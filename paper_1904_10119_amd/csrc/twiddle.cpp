@@ -7,6 +7,7 @@
 // +-sqrt(1/2) are exact.  Each entry is rounded once to FP32.
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "../../include/dft3d.h"
 #include "internal.h"
@@ -99,6 +100,50 @@ void make_leaf_table(int precision, unsigned short* out) {
           }
           out[((t * 2 + c) * 64 + lane) * 8 + i] = fp16 ? f16_bits(h) : bf16_bits(h);
         }
+}
+
+int64_t bluestein_length(int64_t n) {
+  int64_t m = 1;
+  while (m < 2 * n - 1) m <<= 1;
+  return m;
+}
+
+// w[j] = exp(-pi i j^2 / n) = w_{2n}^{j^2 mod 2n}, the exponent reduced in
+// integers before the FP64 root.
+void make_chirp(int64_t n, float2* out) {
+  for (int64_t j = 0; j < n; ++j) {
+    double c, s;
+    root_fp64((j * j) % (2 * n), 2 * n, c, s);
+    out[j] = make_float2((float)c, (float)(-s));
+  }
+}
+
+void make_bluestein_filter(int64_t n, float2* out) {
+  const int64_t m = bluestein_length(n);
+  // wrapped filter h[d] = conj(w[|d|]) at d mod m, in FP64
+  std::vector<double> hr(m, 0.0), hi(m, 0.0);
+  for (int64_t d = 0; d < n; ++d) {
+    double c, s;
+    root_fp64((d * d) % (2 * n), 2 * n, c, s);  // w[d] = c - i s, conj = c + i s
+    hr[d] = c;
+    hi[d] = s;
+    if (d > 0) {
+      hr[m - d] = c;
+      hi[m - d] = s;
+    }
+  }
+  std::vector<double> rc(m), rs(m);
+  for (int64_t l = 0; l < m; ++l) root_fp64(l, m, rc[l], rs[l]);
+  for (int64_t l = 0; l < m; ++l) {
+    double yr = 0.0, yi = 0.0;
+    for (int64_t d = 0; d < m; ++d) {
+      if (hr[d] == 0.0 && hi[d] == 0.0) continue;
+      const int64_t e = (d * l) % m;  // exp(-2 pi i d l / m) = rc - i rs
+      yr += hr[d] * rc[e] + hi[d] * rs[e];
+      yi += hi[d] * rc[e] - hr[d] * rs[e];
+    }
+    out[l] = make_float2((float)(yr / (double)m), (float)(yi / (double)m));
+  }
 }
 
 }  // namespace dft3d

@@ -1,0 +1,155 @@
+"""GPU parity for lengths that are not powers of two (Bluestein's chirp-z
+steps inside the pencil schedule), through the C ABI, against the FP64
+oracle's direct sums.
+
+Tolerance: each power-of-two axis of length n contributes log2(n) rounding
+levels, as in tol(N); an axis of length n done by Bluestein (convolution
+length m) contributes 2 log2(m) + 3: two FFTs of length m plus the chirp
+multiply before, the filter multiply between and the chirp multiply after
+them.  The bar is 1e-6 / 18 per level, the same rate as tol(N)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1904_10119_amd import dft3d, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_and_native_library():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dft3d.lib()
+    assert "libdft3d.so" in open("/proc/self/maps").read(), "native library not loaded"
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def levels(shape):
+    out = 0.0
+    for n in shape:
+        if n & (n - 1) == 0:
+            out += np.log2(n) if n > 1 else 0.0
+        else:
+            m = 1 << int(np.ceil(np.log2(2 * n - 1)))
+            out += 2 * np.log2(m) + 3
+    return max(out, 1.0)
+
+
+def tol_bl(shape):
+    return 1e-6 * levels(shape) / 18.0
+
+
+def gpu_fftn(x_np, inverse=False, schedule="pencil"):
+    y = dft3d.fftn(torch.from_numpy(x_np).cuda(), schedule=schedule, inverse=inverse)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+SHAPES = [
+    (3, 5, 7), (6, 10, 12), (1, 1, 3), (9, 1, 1), (1, 17, 1), (2, 3, 4),
+    (100, 30, 17), (64, 100, 64), (12, 7, 16), (15, 8, 2048), (2047, 5, 3),
+    (3, 2000, 7), (5, 3, 1025), (96, 96, 96), (33, 65, 129),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("schedule", ["pencil", "auto"])
+def test_other_lengths_forward_inverse(shape, schedule):
+    say("case bluestein", shape, schedule)
+    x = inputs.uniform_c64(shape, 31)
+    t = tol_bl(shape)
+    for sign, inv in ((-1, False), (1, True)):
+        y = gpu_fftn(x, inv, schedule)
+        ref = oracle.dft3d(x.astype(np.complex128), sign, "direct")
+        err = oracle.rel_l2(y, ref)
+        say("  sign", sign, "rel_l2", err, "tol", t)
+        assert err <= t, (shape, sign, err)
+
+
+@pytest.mark.parametrize("shape", [(3, 5, 7), (100, 30, 17), (2047, 5, 3)])
+def test_other_lengths_round_trip(shape):
+    x = inputs.uniform_c64(shape, 32)
+    y = gpu_fftn(x)
+    back = gpu_fftn(y, inverse=True) / x.size
+    assert oracle.rel_l2(back, x) <= 2 * tol_bl(shape)
+
+
+def test_other_lengths_special_inputs():
+    """Impulse at the origin gives all ones; a constant gives N at the
+    origin only; a shifted impulse gives the product of the axis roots."""
+    shape = (6, 10, 12)
+    N = 6 * 10 * 12
+    x = np.zeros(shape, np.complex64)
+    x[0, 0, 0] = 1
+    y = gpu_fftn(x)
+    assert np.max(np.abs(y - 1)) < 1e-6
+    y = gpu_fftn(np.ones(shape, np.complex64))
+    ref = np.zeros(shape)
+    ref[0, 0, 0] = N
+    assert np.max(np.abs(y - ref)) < 1e-6 * N
+    x = np.zeros(shape, np.complex64)
+    x[1, 3, 5] = 1
+    k = np.indices(shape)
+    ref = np.exp(-2j * np.pi * (k[0] * 1 / 6 + k[1] * 3 / 10 + k[2] * 5 / 12))
+    assert np.max(np.abs(gpu_fftn(x) - ref)) < 2e-6
+
+
+def test_other_lengths_full_size_sampled():
+    """A 1000 x 1000 x 100 transform (every axis by Bluestein): sampled
+    output pencils against the oracle's direct sums, Parseval, round trip."""
+    shape = (1000, 1000, 100)
+    say("case bluestein full size", shape)
+    x = inputs.uniform_c64(shape, 33)
+    xt = torch.from_numpy(x).cuda()
+    y = dft3d.fftn(xt, schedule="auto")
+    torch.cuda.synchronize()
+    N = x.size
+    t = tol_bl(shape)
+    g = np.random.default_rng(33)
+    k0 = np.concatenate([[0, 999, 500], g.integers(0, 1000, 5)])
+    k1 = np.concatenate([[0, 1, 999], g.integers(0, 1000, 5)])
+    got = y[torch.from_numpy(k0).cuda(), torch.from_numpy(k1).cuda(), :].cpu().numpy()
+    ref = oracle.sample_pencils(x, k0, k1, -1)
+    err = oracle.rel_l2(got, ref)
+    say("  sampled pencils rel_l2", err, "tol", t)
+    assert err <= t
+    ex = torch.sum(torch.view_as_real(xt).double() ** 2).item()
+    ey = torch.sum(torch.view_as_real(y).double() ** 2).item()
+    assert abs(ey / (N * ex) - 1.0) <= 2 * t
+    back = dft3d.fftn(y, schedule="auto", inverse=True)
+    d = torch.view_as_real(back).double() / N - torch.view_as_real(xt).double()
+    rt = (torch.linalg.vector_norm(d) /
+          torch.linalg.vector_norm(torch.view_as_real(xt).double())).item()
+    say("  round trip rel_l2", rt)
+    assert rt <= 2 * t
+    del xt, y, back, d
+    torch.cuda.empty_cache()
+
+
+def test_other_lengths_in_a_batch():
+    """A batch holding a Bluestein plan runs plan by plan and still matches."""
+    shapes = [(3, 5, 7), (16, 16, 16), (6, 10, 12)]
+    xs = [inputs.uniform_c64(s, 40 + i) for i, s in enumerate(shapes)]
+    ys = dft3d.fftn_batched([torch.from_numpy(x).cuda() for x in xs])
+    torch.cuda.synchronize()
+    for x, y in zip(xs, ys):
+        ref = oracle.dft3d(x.astype(np.complex128), -1, "direct")
+        assert oracle.rel_l2(y.cpu().numpy(), ref) <= tol_bl(x.shape)
+
+
+def test_other_lengths_rejected_by_other_schedules():
+    x = torch.zeros((3, 4, 4), dtype=torch.complex64, device="cuda")
+    for sched in ("slab", "volumetric"):
+        with pytest.raises(dft3d.Dft3dError):
+            dft3d.fftn(x, schedule=sched)
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.fftn(x, schedule="pencil", precision="bf16x6")

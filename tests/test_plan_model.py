@@ -73,13 +73,46 @@ def fused_model(bufs, p, sign, last):
     bufs[p["dst"]][oa] = v
 
 
+def bluestein_model(bufs, p, sign, last):
+    """Bluestein steps from their documented formulas (chirp-z identity:
+    w[j] = exp(-pi i j^2 / n), filter = DFT_m of the wrapped conj(w)),
+    computed here in numpy independently of the library's tables."""
+    a = p["args"]
+    B, n, m = a["B"], a["ijs"], a["oks"]
+    j = np.arange(n)
+    w = np.exp(-1j * np.pi * ((j * j) % (2 * n)) / n)
+    kind = p["bluestein"]
+    if kind == 1:
+        v = bufs[p["src"]][p["in_off"] + np.arange(B * n)].reshape(B, n)
+        if sign == 1 and p["src"] == "in":
+            v = np.conj(v)
+        out = np.zeros((B, m), complex)
+        out[:, :n] = v * w[None, :]
+        bufs[p["dst"]][p["out_off"] + np.arange(B * m)] = out.reshape(-1)
+    elif kind == 2:
+        h = np.zeros(m, complex)
+        h[:n] = np.conj(w)
+        h[m - np.arange(1, n)] = np.conj(w[1:])
+        H = np.fft.fft(h) / m
+        idx = p["in_off"] + np.arange(B * m)
+        bufs[p["dst"]][p["out_off"] + np.arange(B * m)] = (
+            bufs[p["src"]][idx].reshape(B, m) * H[None, :]).reshape(-1)
+    else:
+        v = bufs[p["src"]][p["in_off"] + np.arange(B * m)].reshape(B, m)
+        y = v[:, (m - j) % m] * w[None, :]                 # (B, n)
+        if sign == 1 and last:
+            y = np.conj(y)
+        bufs[p["dst"]][p["out_off"] + np.arange(n * B)] = y.T.reshape(-1)
+
+
 def run_model(x, d, sign, key=None):
     """Run a pass list; by default the one execute uses for `sign` (a
     shuffled plan's inverse runs its "inverse_passes")."""
     n_total = x.size
+    n_ws = max(n_total, d["workspace_bytes"] // 8)
     bufs = {"in": x.reshape(-1).astype(np.complex128),
             "out": np.full(n_total, np.nan, np.complex128),
-            "ws": np.full(n_total, np.nan, np.complex128)}
+            "ws": np.full(n_ws, np.nan, np.complex128)}
     if key is None:
         key = "inverse_passes" if (sign == 1 and "inverse_passes" in d) else "passes"
     passes = d[key]
@@ -87,6 +120,9 @@ def run_model(x, d, sign, key=None):
         a = p["args"]
         if p.get("fused_axes"):
             fused_model(bufs, p, sign, i == len(passes) - 1)
+            continue
+        if p.get("bluestein"):
+            bluestein_model(bufs, p, sign, i == len(passes) - 1)
             continue
         ia = addresses(a, pass_points(p), True)
         oa = addresses(a, pass_points(p), False)
@@ -120,6 +156,8 @@ def test_pass_maps_are_injective_and_in_bounds(shape, schedule):
     N = shape[0] * shape[1] * shape[2]
     for p in d["passes"]:
         a = p["args"]
+        if p.get("bluestein"):
+            continue  # covered by test_bluestein_steps_in_bounds
         if p.get("fused_axes"):
             if a["B"] * p["n"] * p["n"] * p["tile"] <= (1 << 22):
                 ia, oa, _ = fused_tiles(p)
@@ -278,3 +316,59 @@ def test_volumetric_1024_cubed_has_four_passes():
     d = dft3d.describe((1024, 1024, 1024), "volumetric")
     assert len(d["passes"]) == 4
     assert [p["fused_axes"] for p in d["passes"]] == [0, 1, 1, 0]
+
+
+OTHER_SHAPES = [(3, 5, 7), (6, 10, 12), (1, 1, 3), (9, 1, 1), (2, 3, 4), (100, 30, 17),
+                (64, 100, 64), (15, 8, 2048), (12, 7, 16)]
+
+
+@pytest.mark.parametrize("shape", OTHER_SHAPES)
+def test_bluestein_pass_lists(shape):
+    """Lengths that are not powers of two (pencil schedule, Bluestein steps):
+    the pass list computes the DFT, forward and inverse."""
+    d = dft3d.describe(shape, "auto")
+    assert d["schedule"] == "pencil"
+    assert any(p["bluestein"] for p in d["passes"])
+    g = np.random.default_rng(sum(shape))
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    for sign in (-1, 1):
+        got = run_model(x, d, sign)
+        ref = oracle.dft3d(x, sign, "direct")
+        assert oracle.rel_l2(got, ref) < 1e-12, (shape, sign)
+
+
+@pytest.mark.parametrize("shape", OTHER_SHAPES + [(2048, 1000, 3), (4096, 3, 5)])
+def test_bluestein_steps_in_bounds(shape):
+    """Every Bluestein step reads and writes inside its buffers, and the
+    region it uses in the workspace lies after the chain's N points."""
+    d = dft3d.describe(shape, "auto")
+    N = shape[0] * shape[1] * shape[2]
+    ws = d["workspace_bytes"] // 8
+    size = {"in": N, "out": N, "ws": ws}
+    for p in d["passes"]:
+        a = p["args"]
+        if not p["bluestein"] and p["src"] == p["dst"] == "ws" and p["in_off"] == N:
+            assert N + a["B"] * p["n"] <= ws          # FFT_m rows in the region
+            continue
+        if not p["bluestein"]:
+            continue
+        B, n, m = a["B"], a["ijs"], a["oks"]
+        reads = {1: B * n, 2: B * m, 3: B * m}[p["bluestein"]]
+        writes = {1: B * m, 2: B * m, 3: n * B}[p["bluestein"]]
+        assert p["in_off"] + reads <= size[p["src"]], p["label"]
+        assert p["out_off"] + writes <= size[p["dst"]], p["label"]
+        if p["src"] == "ws" and p["bluestein"] != 1:
+            assert p["in_off"] == N
+        if p["dst"] == "ws" and p["bluestein"] != 3:
+            assert p["out_off"] == N
+
+
+@pytest.mark.parametrize("schedule,opts", [("slab", {}), ("volumetric", {}),
+                                           ("pencil", {"precision": "bf16x6"})])
+def test_bluestein_limits(schedule, opts):
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((3, 4, 4), schedule, **opts)
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((2049, 4, 4), "pencil")
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((3, 4, 4), "auto", "shuffled")
