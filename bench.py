@@ -18,8 +18,9 @@ The JSON line also carries:
   configs       (unless --no-extras) the other workloads: 64^3 forward and
                 inverse (latency), every schedule at 1024^3, every leaf
                 precision at 256^3 and 1024^3, 96 uneven problems batched
-                per pass level against one plan at a time, and
-                2048 x 1024 x 512 auto vs pencil, FP32 vs bf16x6 leaves.
+                per pass level against one plan at a time,
+                2048 x 1024 x 512 auto vs pencil, FP32 vs bf16x6 leaves, and
+                lengths that are not powers of two (1000^3, 96^3).
 """
 import argparse
 import json
@@ -264,6 +265,27 @@ def extras(x1024_host, args):
     log(f"bench: 2048x1024x512 {r}")
     del x, y
     torch.cuda.empty_cache()
+
+    # lengths that are not powers of two (one Bluestein pass per axis):
+    # 1000^3 (convolution length 2048 on every axis) and 96^3 (latency);
+    # uniform[-1, 1) inputs drawn on the device from a seeded generator
+    bl = {}
+    for shape, reps in (((1000, 1000, 1000), 3), ((96, 96, 96), 100)):
+        g = torch.Generator(device="cuda").manual_seed(6)
+        x = torch.complex(torch.rand(shape, device="cuda", generator=g) * 2 - 1,
+                          torch.rand(shape, device="cuda", generator=g) * 2 - 1)
+        y = torch.empty_like(x)
+        f, n = plan_ms(shape, x, y, reps, schedule="auto")
+        i, _ = plan_ms(shape, x, y, reps, inverse=True, schedule="auto")
+        Np = x.numel()
+        bl["x".join(map(str, shape))] = {
+            "passes": n, "fwd_ms": round(f, 4), "inv_ms": round(i, 4),
+            "fwd_gflops_5nlogn": round(5.0 * Np * math.log2(Np) / (f * 1e-3) / 1e9, 1),
+            "hbm_gbs_per_pass": round(16.0 * Np / (f / n * 1e-3) / 1e9, 1)}
+        del x, y
+        torch.cuda.empty_cache()
+    out["bluestein"] = bl
+    log(f"bench: bluestein {bl}")
     return out
 
 

@@ -1,122 +1,137 @@
 // Lengths that are not powers of two: the DFT of length n as a circular
-// convolution of length m (a power of two, m >= 2n - 1) computed with the
-// power-of-two passes (Bluestein's chirp-z identity).  With the chirp
+// convolution of length m (a power of two, m >= 2n - 1) computed with two
+// power-of-two FFTs (Bluestein's chirp-z identity).  With the chirp
 // w[j] = exp(-pi i j^2 / n) and jk = (j^2 + k^2 - (k - j)^2) / 2,
 //   y[k] = w[k] sum_j (x[j] w[j]) conj(w[k - j]),
-// so one axis step of the pencil rotation becomes five passes over a
-// workspace of B pencils of length m:
-//   pad     a[b][j] = x[b][j] w[j] (j < n), 0 (n <= j < m)
-//   FFT_m   (a power-of-two pass kernel, rows in place)
-//   filter  A[b][l] *= H[l] / m,  H = FFT_m of the wrapped filter conj(w[d]),
-//           d in (-n, n)
-//   FFT_m   (again; a forward DFT read backwards is the inverse DFT)
-//   crop    y[k][b] = w[k] A'[b][(m - k) mod m] for k < n, written rotated
-//           (k, b) like every pencil-schedule pass.
-// The chirp and the filter come from FP64 tables built at plan time.
+// a circular convolution of the padded a[j] = x[j] w[j] (zero for j >= n)
+// with the filter h[d] = conj(w[d]) wrapped to length m.  Writing the
+// inverse DFT of length m as the forward one read backwards,
+//   y[k] = w[k] FFT_m( FFT_m(a) * H / m )[(m - k) mod m],   H = FFT_m(h).
 //
-// PassArgs fields used: B = pencils; ijs = n; oks = m; conj_in / conj_out
-// as for every pass (the inverse conjugates around the whole list).
+// One workgroup takes a tile of T pencils through the whole chain without
+// leaving the chip: load the n inputs of each pencil (zeros above n) times
+// the chirp, FFT_m, times H / m, FFT_m, and store output k < n times w[k]
+// at its rotated place, like every pencil-schedule pass.  The first FFT
+// ends in the row mapping (thread p of pencil q holds outputs p + P e),
+// which is the input mapping of the second FFT, so the pencil stays in
+// registers between the two; only the radix exchanges go through LDS.  The
+// pass therefore moves n reads and n writes per pencil, as a power-of-two
+// pass does.
+//
+// PassArgs fields used: pencil fields and element strides as for every
+// pass (ijs along the input pencil, oks along the output), res_mask = n.
+// Tables: tw = roots of length m; twp = the chirp (n entries) followed by
+// H / m (m entries), both from FP64.
 #pragma once
 
-#include "fft_device.h"
-#include "internal.h"
+#include "pass_kernel.h"
 
 namespace dft3d {
 
-constexpr int kBluesteinThreads = 256;
-constexpr int kBluesteinGridCap = 1 << 20;
-
-__device__ __forceinline__ int ilog2_dev(int64_t v) { return 63 - __builtin_clzll(v); }
-
-// pad: src pencils (B, n) contiguous -> dst (B, m); tw = chirp (n entries).
-__global__ void __launch_bounds__(kBluesteinThreads)
-bluestein_pad_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
-                     const float2* __restrict__ twp, const PassArgs a) {
-  const int64_t n = a.ijs, m = a.oks;
-  const int lm = ilog2_dev(m);
-  const int64_t total = a.B << lm;
-  for (int64_t idx = (int64_t)blockIdx.x * kBluesteinThreads + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kBluesteinThreads) {
-    const int64_t b = idx >> lm, j = idx & (m - 1);
-    float2 v = make_float2(0.f, 0.f);
-    if (j < n) {
-      v = src[b * n + j];
-      if (a.conj_in) v.y = -v.y;
-      v = cmul(v, tw[j]);
-    }
-    dst[idx] = v;
+// One FFT of length M over the tile held in v (thread (q, p) has elements
+// p + P e), ending in LAST_MODE; on return v[e] is output p + P e of
+// pencil q under that mapping.  The caller makes sure no thread still reads
+// lds when this starts.
+template <int M, class BL, int T, int SQ, int LAST_MODE, int E, int P>
+__device__ __forceinline__ void bluestein_fft(float2 (&v)[E], float2* lds,
+                                              const float2* __restrict__ tw, int tid, int& q,
+                                              int& p) {
+  constexpr int NST = num_stages<BL>();
+  radix_stage<M, E, P, 1, BL::R0>(v, p, tw);
+  if constexpr (NST == 2) {
+    lds_exchange<M, E, P, T, SQ, 1, BL::R0, LAST_MODE>(v, lds, tid, q, p);
+    radix_stage<M, E, P, BL::R0, BL::R1>(v, p, tw);
+  } else if constexpr (NST == 3) {
+    lds_exchange<M, E, P, T, SQ, 1, BL::R0, MODE_ROW>(v, lds, tid, q, p);
+    radix_stage<M, E, P, BL::R0, BL::R1>(v, p, tw);
+    __syncthreads();  // every read of the first exchange is done
+    lds_exchange<M, E, P, T, SQ, BL::R0, BL::R1, LAST_MODE>(v, lds, tid, q, p);
+    radix_stage<M, E, P, BL::R0 * BL::R1, BL::R2>(v, p, tw);
   }
 }
 
-// filter: (B, m) in place, times twp[l] = H[l] / m.
-__global__ void __launch_bounds__(kBluesteinThreads)
-bluestein_filter_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
-                        const float2* __restrict__ twp, const PassArgs a) {
-  const int64_t m = a.oks;
-  const int64_t total = a.B * m;
-  for (int64_t idx = (int64_t)blockIdx.x * kBluesteinThreads + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * kBluesteinThreads)
-    dst[idx] = cmul(src[idx], twp[idx & (m - 1)]);
-}
-
-// crop: (B, m) -> dst (n, B): dst[k][b] = tw[k] src[b][(m - k) mod m], through
-// a 32 x 32 LDS tile so that both the reads (along k) and the writes (along
-// b) are contiguous.  One workgroup per tile, tiles k-fastest.
-__global__ void __launch_bounds__(kBluesteinThreads)
-bluestein_crop_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
+// BL: register blocking of the length-m FFTs (E elements per thread).
+template <int M, int T, class BL>
+__global__ void __launch_bounds__(T*(M / BL::E))
+bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
                       const float2* __restrict__ twp, const PassArgs a) {
-  __shared__ float2 tile[32][33];
-  const int64_t n = a.ijs, m = a.oks, B = a.B;
-  const int64_t tiles_k = (n + 31) / 32;
-  const int64_t t = blockIdx.x;
-  const int64_t k0 = (t % tiles_k) * 32, b0 = (t / tiles_k) * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  constexpr int E = BL::E;
+  constexpr int P = M / E;
+  constexpr int NST = num_stages<BL>();
+  constexpr int SQ = lds_pencil_stride<M, T>();
+  constexpr int LDS_ELEMS = NST > 1 ? T * SQ : 1;
+  __shared__ float2 lds[LDS_ELEMS];
+  const int64_t n = a.res_mask;
+  const float2* __restrict__ chirp = twp;
+  const float2* __restrict__ filt = twp + n;
+
+  const int tid = threadIdx.x;
+  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
+  int q, p;
+  thread_map<MODE_ROW, T, P>(tid, q, p);
+  {
+    // pencils past the end of a ragged last tile read the last pencil
+    int64_t b = tile * T + q;
+    b = b < a.B ? b : a.B - 1;
+    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+    float2 v[E];
 #pragma unroll
-  for (int i = 0; i < 32; i += 8) {
-    const int64_t b = b0 + ty + i, k = k0 + tx;
-    if (b < B && k < n) tile[ty + i][tx] = src[b * m + ((m - k) & (m - 1))];
-  }
-  __syncthreads();
+    for (int e = 0; e < E; ++e) {
+      const int j = p + P * e;
+      float2 x = make_float2(0.f, 0.f);
+      if (j < n) {
+        x = s[j * a.ijs];
+        if (a.conj_in) x.y = -x.y;
+        x = cmul(x, chirp[j]);
+      }
+      v[e] = x;
+    }
+    bluestein_fft<M, BL, T, SQ, MODE_ROW, E, P>(v, lds, tw, tid, q, p);
 #pragma unroll
-  for (int i = 0; i < 32; i += 8) {
-    const int64_t k = k0 + ty + i, b = b0 + tx;
-    if (k < n && b < B) {
-      float2 v = cmul(tile[tx][ty + i], tw[k]);
-      if (a.conj_out) v.y = -v.y;
-      dst[k * B + b] = v;
+    for (int e = 0; e < E; ++e) v[e] = cmul(v[e], filt[p + P * e]);
+    if constexpr (NST > 1) __syncthreads();  // the first FFT's exchanges are read
+    bluestein_fft<M, BL, T, SQ, MODE_COL, E, P>(v, lds, tw, tid, q, p);
+    const int64_t bo = tile * T + q;
+    if (bo < a.B) {
+      float2* d = dst + pencil_offset(bo, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = (M - (p + P * e)) & (M - 1);
+        if (k < n) {
+          float2 y = cmul(v[e], chirp[k]);
+          if (a.conj_out) y.y = -y.y;
+          d[k * a.oks] = y;
+        }
+      }
     }
   }
 }
 
-inline int64_t bluestein_grid(int64_t work) {
-  int64_t g = (work + kBluesteinThreads - 1) / kBluesteinThreads;
-  return g < 1 ? 1 : (g > kBluesteinGridCap ? kBluesteinGridCap : g);
-}
-
-inline hipError_t launch_bluestein_pad(const PassArgs& a, const float2* src, float2* dst,
-                                       const float2* tw, const float2* twp, hipStream_t s) {
-  if (a.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bluestein_pad_kernel, dim3((unsigned)bluestein_grid(a.B * a.oks)),
-                     dim3(kBluesteinThreads), 0, s, src, dst, tw, twp, a);
+template <int M, int T, class BL>
+hipError_t launch_bluestein_axis(const PassArgs& a, const float2* src, float2* dst,
+                                 const float2* tw, const float2* twp, hipStream_t stream) {
+  constexpr int THREADS = T * (M / BL::E);
+  const int64_t blocks = (a.B + T - 1) / T;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (a.res_mask < 1 || 2 * a.res_mask - 1 > M) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((bluestein_axis_kernel<M, T, BL>), dim3((unsigned)blocks), dim3(THREADS),
+                     0, stream, src, dst, tw, twp, a);
   return hipGetLastError();
 }
 
-inline hipError_t launch_bluestein_filter(const PassArgs& a, const float2* src, float2* dst,
-                                          const float2* tw, const float2* twp, hipStream_t s) {
-  if (a.B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bluestein_filter_kernel, dim3((unsigned)bluestein_grid(a.B * a.oks)),
-                     dim3(kBluesteinThreads), 0, s, src, dst, tw, twp, a);
-  return hipGetLastError();
-}
-
-inline hipError_t launch_bluestein_crop(const PassArgs& a, const float2* src, float2* dst,
-                                        const float2* tw, const float2* twp, hipStream_t s) {
-  if (a.B <= 0) return hipSuccess;
-  const int64_t tiles = ((a.ijs + 31) / 32) * ((a.B + 31) / 32);
-  if (tiles > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(bluestein_crop_kernel, dim3((unsigned)tiles), dim3(kBluesteinThreads), 0,
-                     s, src, dst, tw, twp, a);
-  return hipGetLastError();
+template <int M, int T>
+KernelInfo kernel_info_bluestein() {
+  using BL = Blocking<M>;
+  constexpr int E = BL::E;
+  constexpr int SQ = lds_pencil_stride<M, T>();
+  constexpr int LDS = num_stages<BL>() > 1 ? T * SQ * 8 : 8;
+  static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
+  static_assert(T * (M / E) <= 1024, "workgroup too large");
+  KernelInfo k{M, T, MODE_ROW, MODE_COL, 0, T * (M / E), LDS,
+               &launch_bluestein_axis<M, T, BL>, 0, 0};
+  k.bluestein = 1;
+  return k;
 }
 
 }  // namespace dft3d

@@ -68,7 +68,8 @@ int rebuild(dft3d_plan_s* p) {
 
   // one table per distinct root length (key n > 0) and per MFMA leaf
   // precision (key -precision, kLeafTableFloat2 slots of 16-bit values);
-  // Bluestein chirp and filter tables per length n (keys (1, n), (2, n))
+  // Bluestein chirp and filter tables per length n (keys (1, n), (2, n),
+  // the filter stored right after the chirp)
   std::map<int64_t, int64_t> offsets;
   std::map<std::pair<int, int64_t>, int64_t> bl_offsets;
   int64_t total = 0;
@@ -129,9 +130,9 @@ int rebuild(dft3d_plan_s* p) {
     tw.clear();
     twp.clear();
     for (const Pass& ps : list) {
-      if (ps.k->bluestein) {  // chirp and filter of the length
-        tw.push_back(bl_offsets[{1, ps.bl_n}]);
-        twp.push_back(bl_offsets[{2, ps.bl_n}]);
+      if (ps.k->bluestein) {  // roots of m; the chirp, with the filter right after it
+        tw.push_back(offsets[ps.tw_len]);
+        twp.push_back(bl_offsets[{1, ps.bl_n}]);
         continue;
       }
       tw.push_back(offsets[ps.tw_len]);

@@ -54,7 +54,7 @@ struct KernelInfo {
   int precision = 0; // DFT3D_PREC_*: FP32 butterflies or split MFMA leaves
   int plane_rows = 0; // > 0: fused 2D DFT of (plane_rows, n) planes, one per workgroup
   int fused_axes = 0; // 1: volumetric V2 of one axis fused with V1 of the next (n = a)
-  int bluestein = 0;  // 1 pad, 2 filter, 3 crop: steps of a length that is not a power of two
+  int bluestein = 0;  // 1: one-pass Bluestein axis (length not a power of two, n = m)
 };
 
 // All compiled pass kernels.
@@ -63,8 +63,9 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
                               int persistent, int nontemporal);
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
-// The kernel of one Bluestein step (1 pad, 2 filter, 3 crop).
-const KernelInfo* find_bluestein_kernel(int kind);
+// The one-pass Bluestein axis kernel of convolution length m with the given
+// tile, else the length's default tile; null if none is compiled.
+const KernelInfo* find_bluestein_kernel(int m, int tile);
 // The fused volumetric two-axis kernel for split factor a, if compiled
 // (contig: V2 runs contiguous in memory; the persistent form if asked for).
 const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent);
@@ -98,7 +99,7 @@ struct Pass {
   int64_t tw_len = 0;   // root table of the transform length (== k->n)
   int64_t twp_len = 0;  // post-twiddle table length, 0 if none
   int leaf = 0;         // precision of the MFMA leaf table the pass reads, 0: none
-  int64_t bl_n = 0;     // Bluestein steps: the length n (tables: chirp, filter)
+  int64_t bl_n = 0;     // Bluestein axis: the length n (tables: chirp, then filter)
   // Which ends of the pass follow the plan's buffer chain (IN -> OUT/WS
   // alternation); the others keep the buffers the planner set.
   bool chain_src = true, chain_dst = true;

@@ -1,16 +1,36 @@
-// Kernels of the Bluestein steps (lengths that are not powers of two).
+// One-pass Bluestein axis kernels (lengths that are not powers of two), one
+// per convolution length m = 8 .. 4096 and tile.
 #include "bluestein.h"
 
 namespace dft3d {
 void register_kernels_bluestein(std::vector<KernelInfo>& v) {
-  const LaunchFn fns[3] = {&launch_bluestein_pad, &launch_bluestein_filter,
-                           &launch_bluestein_crop};
-  const int lds[3] = {0, 0, 32 * 33 * 8};
-  for (int kind = 1; kind <= 3; ++kind) {
-    KernelInfo k{0, 0, MODE_ROW, kind == 3 ? MODE_COL : MODE_ROW, 0, kBluesteinThreads,
-                 lds[kind - 1], fns[kind - 1], 0, 0, 0};
-    k.bluestein = kind;
-    v.push_back(k);
-  }
+  // The first tile of each length is its default.  Measured on MI355X
+  // (250^3 .. 2000^2 x 256): smaller tiles, or 16 elements per thread with
+  // twice the waves per SIMD, do not run faster except at m = 512, where
+  // four pencils per workgroup beat sixteen by 10%; the kernel is bound by
+  // its arithmetic and memory-instruction issue, not by occupancy.
+  v.push_back(kernel_info_bluestein<8, 256>());
+  v.push_back(kernel_info_bluestein<16, 256>());
+  v.push_back(kernel_info_bluestein<16, 64>());
+  v.push_back(kernel_info_bluestein<32, 128>());
+  v.push_back(kernel_info_bluestein<32, 32>());
+  v.push_back(kernel_info_bluestein<64, 64>());
+  v.push_back(kernel_info_bluestein<64, 16>());
+  v.push_back(kernel_info_bluestein<128, 32>());
+  v.push_back(kernel_info_bluestein<128, 8>());
+  v.push_back(kernel_info_bluestein<256, 32>());
+  v.push_back(kernel_info_bluestein<256, 8>());
+  v.push_back(kernel_info_bluestein<512, 4>());
+  v.push_back(kernel_info_bluestein<512, 8>());
+  v.push_back(kernel_info_bluestein<512, 16>());
+  v.push_back(kernel_info_bluestein<1024, 16>());
+  v.push_back(kernel_info_bluestein<1024, 8>());
+  v.push_back(kernel_info_bluestein<1024, 4>());
+  v.push_back(kernel_info_bluestein<2048, 8>());
+  v.push_back(kernel_info_bluestein<2048, 4>());
+  v.push_back(kernel_info_bluestein<2048, 2>());
+  v.push_back(kernel_info_bluestein<4096, 4>());
+  v.push_back(kernel_info_bluestein<4096, 2>());
+  v.push_back(kernel_info_bluestein<4096, 1>());
 }
 }  // namespace dft3d

@@ -179,27 +179,24 @@ struct Builder {
     passes.push_back(p);
   }
 
-  // One Bluestein step (1 pad, 2 filter, 3 crop) over B pencils of length n
-  // (padded length m) with the given buffers; see bluestein.h.
-  void add_bluestein(int kind, int64_t B, int64_t n, int src, int dst, int64_t in_off,
-                     int64_t out_off, bool chain_src, bool chain_dst, const std::string& label) {
-    const KernelInfo* k = find_bluestein_kernel(kind);
+  // One-pass Bluestein axis of length n (convolution length m) over the
+  // pencils of fields f (bluestein.h documents the argument fields).
+  void add_bluestein(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
+                     const std::string& label) {
+    const int64_t m = bluestein_length(n);
+    const KernelInfo* k = find_bluestein_kernel((int)m, opt.tile);
     if (!k) {
       status = DFT3D_ERR_UNSUPPORTED_SIZE;
       return;
     }
     Pass p;
     p.k = k;
-    p.args.B = B;
-    p.args.ijs = n;
-    p.args.oks = bluestein_length(n);
-    p.args.xcd_remap = 0;
-    p.src = src;
-    p.dst = dst;
-    p.in_off = in_off;
-    p.out_off = out_off;
-    p.chain_src = chain_src;
-    p.chain_dst = chain_dst;
+    set_fields(p.args, f, nf);
+    p.args.ijs = ijs;
+    p.args.oks = oks;
+    p.args.res_mask = n;
+    p.args.xcd_remap = opt.xcd_remap;
+    p.tw_len = m;
     p.bl_n = n;
     p.label = label;
     passes.push_back(p);
@@ -333,35 +330,15 @@ void volumetric_axis_from_shuffled(Builder& b, int64_t outer, int64_t n, int64_t
 // One rotate-on-write step of the pencil schedule on a (c0, c1, c2) array:
 // transform along c2 and write (c2, c0, c1).  With split, the c2 axis goes
 // through V1 (natural) and a rotating V2.
-void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis, int64_t ws2_off) {
+void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
   const int64_t n = cur[2], B = cur[0] * cur[1];
   char lab[64];
   if (!is_pow2(n)) {
-    // Bluestein (bluestein.h): chain source -> padded pencils in the second
-    // workspace region -> two FFT_m passes and the filter in place -> crop,
-    // written rotated to the chain's next buffer
-    const int64_t m = bluestein_length(n);
-    std::snprintf(lab, sizeof lab, "pencil%d.pad DFT%lld via %lld x%lld", axis, (long long)n,
-                  (long long)m, (long long)B);
-    b.add_bluestein(1, B, n, BUF_IN, BUF_WS, 0, ws2_off, true, false, lab);
-    for (int half = 0; half < 2; ++half) {
-      if (half == 1) {
-        std::snprintf(lab, sizeof lab, "pencil%d.filter %lld", axis, (long long)m);
-        b.add_bluestein(2, B, n, BUF_WS, BUF_WS, ws2_off, ws2_off, false, false, lab);
-      }
-      Field f[1] = {{B, m, m}};
-      std::snprintf(lab, sizeof lab, "pencil%d.fft%d DFT%lld x%lld", axis, half, (long long)m,
-                    (long long)B);
-      b.add((int)m, MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
-      if (b.status != DFT3D_OK) return;
-      Pass& ps = b.passes.back();
-      ps.src = ps.dst = BUF_WS;
-      ps.in_off = ps.out_off = ws2_off;
-      ps.chain_src = ps.chain_dst = false;
-    }
-    std::snprintf(lab, sizeof lab, "pencil%d.crop DFT%lld x%lld rot", axis, (long long)n,
-                  (long long)B);
-    b.add_bluestein(3, B, n, BUF_WS, BUF_OUT, ws2_off, 0, false, true, lab);
+    // Bluestein (bluestein.h): the whole axis in one rotate-on-write pass
+    Field f[1] = {{B, n, 1}};
+    std::snprintf(lab, sizeof lab, "pencil%d DFT%lld via %lld x%lld rot", axis, (long long)n,
+                  (long long)bluestein_length(n), (long long)B);
+    b.add_bluestein(n, f, 1, 1, B, lab);
     return;
   }
   if (!split) {
@@ -449,17 +426,14 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
                         : (schedule == DFT3D_SCHED_AUTO ? 2048 : int64_t(1) << 20);
 
   size_t need_ws = 0;
-  int64_t ws2 = 0;  // elements of the Bluestein region, after the chain's N
   if (resolved == DFT3D_SCHED_PENCIL) {
     int64_t cur[3] = {n[0], n[1], n[2]};
-    for (int d = 0; d < 3; ++d)
-      if (!is_pow2(n[d])) ws2 = std::max(ws2, (total / n[d]) * bluestein_length(n[d]));
     for (int step = 0; step < 3; ++step) {
       const int axis = 2 - step;
       // a split needs power-of-two pencil counts (bit-field pencil indices)
       const bool split = is_pow2(cur[2]) && cur[2] > split_max && cur[2] >= 4 &&
                          is_pow2(cur[0] * cur[1]);
-      pencil_axis(b, cur, split, axis, total);
+      pencil_axis(b, cur, split, axis);
       if (b.status != DFT3D_OK) break;
       const int64_t c2 = cur[2];
       cur[2] = cur[1];
@@ -581,8 +555,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
     passes.clear();
     return b.status;
   }
-  if (ws2 > 0) need_ws = 1;  // the Bluestein region sits after the chain's N
-  ws_bytes = need_ws ? (size_t)(total + ws2) * 8 : 0;
+  ws_bytes = need_ws ? (size_t)total * 8 : 0;
   return DFT3D_OK;
 }
 

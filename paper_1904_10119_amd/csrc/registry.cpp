@@ -38,15 +38,19 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
         k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0 &&
-        k.fused_axes == 0)
+        k.fused_axes == 0 && k.bluestein == 0)
       return &k;
   return nullptr;
 }
 
-const KernelInfo* find_bluestein_kernel(int kind) {
+const KernelInfo* find_bluestein_kernel(int m, int tile) {
+  const KernelInfo* first = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.bluestein == kind) return &k;
-  return nullptr;
+    if (k.bluestein && k.n == m) {
+      if (k.tile == tile) return &k;
+      if (!first) first = &k;
+    }
+  return first;
 }
 
 const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent) {

@@ -32,6 +32,8 @@ def addresses(args, n, inp):
 
 def pass_points(p):
     """Points one work item (pencil, or plane for fused plane passes) covers."""
+    if p.get("bluestein"):
+        return p["bl_n"]
     return p["n"] * max(1, p.get("plane_rows", 0))
 
 
@@ -74,35 +76,30 @@ def fused_model(bufs, p, sign, last):
 
 
 def bluestein_model(bufs, p, sign, last):
-    """Bluestein steps from their documented formulas (chirp-z identity:
-    w[j] = exp(-pi i j^2 / n), filter = DFT_m of the wrapped conj(w)),
-    computed here in numpy independently of the library's tables."""
+    """A one-pass Bluestein axis from its documented steps (chirp-z identity:
+    w[j] = exp(-pi i j^2 / n); pad x w to length m, FFT_m, times H / m with
+    H = FFT_m of the wrapped conj(w), FFT_m, read back at (m - k) mod m,
+    times w[k]), computed in numpy independently of the library's tables."""
     a = p["args"]
-    B, n, m = a["B"], a["ijs"], a["oks"]
+    n, m = p["bl_n"], p["n"]
+    ia = addresses(a, n, True)
+    oa = addresses(a, n, False)
+    v = bufs[p["src"]][ia + p["in_off"]]                   # (B, n)
+    if sign == 1 and p["src"] == "in":
+        v = np.conj(v)
     j = np.arange(n)
     w = np.exp(-1j * np.pi * ((j * j) % (2 * n)) / n)
-    kind = p["bluestein"]
-    if kind == 1:
-        v = bufs[p["src"]][p["in_off"] + np.arange(B * n)].reshape(B, n)
-        if sign == 1 and p["src"] == "in":
-            v = np.conj(v)
-        out = np.zeros((B, m), complex)
-        out[:, :n] = v * w[None, :]
-        bufs[p["dst"]][p["out_off"] + np.arange(B * m)] = out.reshape(-1)
-    elif kind == 2:
-        h = np.zeros(m, complex)
-        h[:n] = np.conj(w)
-        h[m - np.arange(1, n)] = np.conj(w[1:])
-        H = np.fft.fft(h) / m
-        idx = p["in_off"] + np.arange(B * m)
-        bufs[p["dst"]][p["out_off"] + np.arange(B * m)] = (
-            bufs[p["src"]][idx].reshape(B, m) * H[None, :]).reshape(-1)
-    else:
-        v = bufs[p["src"]][p["in_off"] + np.arange(B * m)].reshape(B, m)
-        y = v[:, (m - j) % m] * w[None, :]                 # (B, n)
-        if sign == 1 and last:
-            y = np.conj(y)
-        bufs[p["dst"]][p["out_off"] + np.arange(n * B)] = y.T.reshape(-1)
+    h = np.zeros(m, complex)
+    h[:n] = np.conj(w)
+    h[m - np.arange(1, n)] = np.conj(w[1:])
+    H = np.fft.fft(h) / m
+    pad = np.zeros((v.shape[0], m), complex)
+    pad[:, :n] = v * w[None, :]
+    c = np.fft.fft(np.fft.fft(pad, axis=1) * H[None, :], axis=1)
+    y = c[:, (m - j) % m] * w[None, :]
+    if sign == 1 and last:
+        y = np.conj(y)
+    bufs[p["dst"]][oa + p["out_off"]] = y
 
 
 def run_model(x, d, sign, key=None):
@@ -153,11 +150,14 @@ def test_pass_maps_are_injective_and_in_bounds(shape, schedule):
         d = dft3d.describe(shape, "slab", slab_group=max(1, shape[0] // 4))
     else:
         d = dft3d.describe(shape, schedule)
-    N = shape[0] * shape[1] * shape[2]
+    check_pass_maps(d, shape[0] * shape[1] * shape[2])
+
+
+def check_pass_maps(d, N):
+    """Every pass reads and writes inside its N-point buffers, each point
+    once (sampled for very large passes)."""
     for p in d["passes"]:
         a = p["args"]
-        if p.get("bluestein"):
-            continue  # covered by test_bluestein_steps_in_bounds
         if p.get("fused_axes"):
             if a["B"] * p["n"] * p["n"] * p["tile"] <= (1 << 22):
                 ia, oa, _ = fused_tiles(p)
@@ -337,30 +337,28 @@ def test_bluestein_pass_lists(shape):
         assert oracle.rel_l2(got, ref) < 1e-12, (shape, sign)
 
 
-@pytest.mark.parametrize("shape", OTHER_SHAPES + [(2048, 1000, 3), (4096, 3, 5)])
-def test_bluestein_steps_in_bounds(shape):
-    """Every Bluestein step reads and writes inside its buffers, and the
-    region it uses in the workspace lies after the chain's N points."""
+@pytest.mark.parametrize("shape", OTHER_SHAPES + [(2048, 1000, 3), (4096, 3, 5),
+                                                  (1000, 1000, 1000)])
+def test_bluestein_axis_passes(shape):
+    """One pass per axis whose length is not a power of two, with its
+    convolution length, reading and writing N points of the chain's
+    buffers (no region beyond N in the workspace)."""
     d = dft3d.describe(shape, "auto")
     N = shape[0] * shape[1] * shape[2]
-    ws = d["workspace_bytes"] // 8
-    size = {"in": N, "out": N, "ws": ws}
+    assert d["workspace_bytes"] <= 8 * N
+    assert len(d["passes"]) == 3
     for p in d["passes"]:
-        a = p["args"]
-        if not p["bluestein"] and p["src"] == p["dst"] == "ws" and p["in_off"] == N:
-            assert N + a["B"] * p["n"] <= ws          # FFT_m rows in the region
-            continue
-        if not p["bluestein"]:
-            continue
-        B, n, m = a["B"], a["ijs"], a["oks"]
-        reads = {1: B * n, 2: B * m, 3: B * m}[p["bluestein"]]
-        writes = {1: B * m, 2: B * m, 3: n * B}[p["bluestein"]]
-        assert p["in_off"] + reads <= size[p["src"]], p["label"]
-        assert p["out_off"] + writes <= size[p["dst"]], p["label"]
-        if p["src"] == "ws" and p["bluestein"] != 1:
-            assert p["in_off"] == N
-        if p["dst"] == "ws" and p["bluestein"] != 3:
-            assert p["out_off"] == N
+        n = p["bl_n"] if p["bluestein"] else p["n"]
+        assert p["args"]["B"] * n == N
+        if p["bluestein"]:
+            m = p["n"]
+            assert m & (m - 1) == 0 and 2 * n - 1 <= m < 4 * n - 2
+            assert p["args"]["res_mask"] == n
+
+
+@pytest.mark.parametrize("shape", OTHER_SHAPES + [(1000, 1000, 1000), (2047, 2047, 64)])
+def test_bluestein_pass_maps_injective_and_in_bounds(shape):
+    check_pass_maps(dft3d.describe(shape, "pencil"), shape[0] * shape[1] * shape[2])
 
 
 @pytest.mark.parametrize("schedule,opts", [("slab", {}), ("volumetric", {}),
