@@ -97,7 +97,7 @@ constexpr size_t kCacheMax = 8;
 
 bool batchable(const dft3d_plan_s* p) {
   for (const Pass& ps : p->passes) {
-    if (ps.k->bluestein) return false;
+    if (ps.k->bluestein || ps.k->mixed) return false;
     if (ps.k->plane_rows) {
       if (!batch_plane_shape(ps.k->plane_rows, ps.k->n)) return false;
       continue;

@@ -27,9 +27,7 @@ int validate(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout) {
     return DFT3D_ERR_INVALID_ARG;
   const int64_t n[3] = {n0, n1, n2};
   for (int d = 0; d < 3; ++d) {
-    if (n[d] < 1 || n[d] > 4096) return DFT3D_ERR_UNSUPPORTED_SIZE;
-    // other lengths than powers of two: up to 2048 (Bluestein, m <= 4096)
-    if ((n[d] & (n[d] - 1)) != 0 && n[d] > 2048) return DFT3D_ERR_UNSUPPORTED_SIZE;
+    if (!length_supported(n[d])) return DFT3D_ERR_UNSUPPORTED_SIZE;
   }
   return DFT3D_OK;
 }
@@ -259,8 +257,8 @@ const char* dft3d_status_string(int status) {
     case DFT3D_OK: return "ok";
     case DFT3D_ERR_INVALID_ARG: return "invalid argument";
     case DFT3D_ERR_UNSUPPORTED_SIZE:
-      return "unsupported size (each n_d in [1, 4096]; lengths other than powers of two at most "
-             "2048)";
+      return "unsupported size (each n_d in [1, 4096]; lengths with a prime factor above 13 at "
+             "most 2048)";
     case DFT3D_ERR_UNSUPPORTED_SCHEDULE: return "unsupported schedule/layout/precision combination";
     case DFT3D_ERR_NO_DEVICE: return "no HIP device";
     case DFT3D_ERR_OUT_OF_MEMORY: return "device out of memory";

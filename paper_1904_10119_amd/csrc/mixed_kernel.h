@@ -1,0 +1,236 @@
+// Lengths whose prime factors are all at most 13: one rotate-on-write
+// pencil pass whose radix stages run in LDS (the Stockham factorisation of
+// eq. (3) with mixed radices 2, 3, 4, 5, 7, 8, 11, 13).
+//
+// A workgroup of TH threads takes a tile of T pencils (T * NMAX points fit
+// in 64 KB of LDS, so two workgroups share a CU; the roots of n are copied
+// next to them where the LDS has room, NMAX <= 2048).  The pencils are
+// loaded into LDS with lanes along each pencil; every stage reads its
+// butterflies' inputs into registers, waits, transforms and writes the
+// outputs back to their Stockham places, and waits again; the finished
+// pencils are stored rotated (T consecutive pencils per output row).
+//
+// Stage s has radix R and ns = the product of the earlier radices.
+// Butterfly t (t < n / R) of a pencil takes inputs t + r n / R (r < R),
+// multiplies input r by w_{ns R}^{(t mod ns) r} = w_n^{(t mod ns) r n / (ns R)}
+// (the table of the n roots of n), transforms them with DFT_R and writes
+// output r to (t div ns) ns R + (t mod ns) + r ns.  After the last stage
+// the pencil is in natural order.
+//
+// PassArgs fields used: pencil fields and element strides as for every
+// pass, res_mask = n, twp_mask = the radices of the stages, 4 bits each,
+// the first stage in the lowest bits (a zero nibble ends the list).
+#pragma once
+
+#include "pass_kernel.h"
+
+namespace dft3d {
+
+// Forward DFT of odd length R in registers, from the pairs x_k + x_{R-k}
+// and x_k - x_{R-k}:  y_j = x_0 + sum_k (x_k + x_{R-k}) cos(2 pi j k / R)
+// - i sum_k (x_k - x_{R-k}) sin(2 pi j k / R), and y_{R-j} with + i.
+template <int R>
+__device__ __forceinline__ void dft_odd(float2* x) {
+  constexpr int H = (R - 1) / 2;
+  float2 s[H], d[H];
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    s[k - 1] = cadd(x[k], x[R - k]);
+    d[k - 1] = csub(x[k], x[R - k]);
+  }
+  float2 y0 = x[0];
+#pragma unroll
+  for (int k = 0; k < H; ++k) y0 = cadd(y0, s[k]);
+  const float2 x0 = x[0];
+  static_for<H>([&](auto ji) {
+    constexpr int j = decltype(ji)::value + 1;
+    float2 a = x0, b = make_float2(0.f, 0.f);
+    static_for<H>([&](auto ki) {
+      constexpr int k = decltype(ki)::value + 1;
+      constexpr CosSin cs = unit_angle((long)j * k, R);
+      constexpr float c = (float)cs.c, sn = (float)cs.s;
+      a.x += s[k - 1].x * c;
+      a.y += s[k - 1].y * c;
+      b.x += d[k - 1].x * sn;
+      b.y += d[k - 1].y * sn;
+    });
+    x[j] = make_float2(a.x + b.y, a.y - b.x);      // a - i b
+    x[R - j] = make_float2(a.x - b.y, a.y + b.x);  // a + i b
+  });
+  x[0] = y0;
+}
+
+template <int R>
+__device__ __forceinline__ void dft_mixed(float2* x) {
+  if constexpr ((R & (R - 1)) == 0) {
+    dft<R>(x);
+  } else {
+    dft_odd<R>(x);
+  }
+}
+
+// One radix-R stage over pencil q (pen = its LDS row, n points): thread p
+// of the P threads of the pencil runs butterflies t = p, p + P, ... (at most
+// K = ceil(V / R) of them, V = NMAX / P).
+template <int R, int V>
+__device__ __forceinline__ void mixed_stage(float2* pen, int n, int ns,
+                                            const float2* __restrict__ tw, int p, int P) {
+  constexpr int K = (V + R - 1) / R;
+  const int nr = n / R;
+  const int step = nr / ns;  // n / (ns R)
+  const int dq = P / ns, dr = P - dq * ns;
+  int g = p / ns, tm = p - g * ns;  // t div ns, t mod ns for t = p
+  float2 a[K][R];
+  int ob[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int t = p + P * i;
+    ob[i] = g * ns * R + tm;
+    if (t < nr) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[i][r] = pen[t + r * nr];
+      if (ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) a[i][r] = cmul(a[i][r], tw[tm * r * step]);
+      }
+      dft_mixed<R>(a[i]);
+    }
+    tm += dr;
+    g += dq;
+    if (tm >= ns) {
+      tm -= ns;
+      ++g;
+    }
+  }
+  __syncthreads();  // every input of the stage is read
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    if (p + P * i < nr) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) pen[ob[i] + r * ns] = a[i][r];
+    }
+  }
+  __syncthreads();  // every output of the stage is written
+}
+
+// RMAX: the largest radix compiled in (8, or 13 with the 11 and 13 stages,
+// whose registers lower the occupancy of every other stage too).
+template <int T, int NMAX, int TH, int RMAX>
+__global__ void __launch_bounds__(TH)
+fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
+                 const float2* __restrict__ twp, const PassArgs a) {
+  constexpr int P = TH / T;             // threads per pencil
+  constexpr int V = NMAX / P;           // points per thread
+  // roots in LDS where two workgroups per CU still fit
+  constexpr bool TWL = 2 * (T * NMAX + NMAX) * 8 <= 160 * 1024;
+  __shared__ float2 buf[T * NMAX + (TWL ? NMAX : 0)];
+  const int n = (int)a.res_mask;  // n < NMAX (NMAX is a power of two, n is not)
+  const int sq = n + 1;           // LDS pencil stride; T sq <= T NMAX
+  const int tid = threadIdx.x;
+  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int q = tid / P, p = tid % P;
+  float2* pen = buf + q * sq;
+  {
+    // pencils past the end of a ragged last tile read the last pencil
+    int64_t b = tile * T + q;
+    b = b < a.B ? b : a.B - 1;
+    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+    // all loads of the thread in flight at once, then into LDS
+    float2 v[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int j = p + P * i;
+      if (j < n) v[i] = s[j * a.ijs];
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const int j = p + P * i;
+      if (j < n) {
+        if (a.conj_in) v[i].y = -v[i].y;
+        pen[j] = v[i];
+      }
+    }
+    if constexpr (TWL) {
+      float2* tl = buf + T * NMAX;
+#pragma unroll
+      for (int i = 0; i < (NMAX + TH - 1) / TH; ++i) {
+        const int j = tid + TH * i;
+        if (j < n) tl[j] = tw[j];
+      }
+    }
+  }
+  __syncthreads();
+  const float2* twv = TWL ? buf + T * NMAX : tw;
+  uint64_t code = (uint64_t)a.twp_mask;
+  int ns = 1;
+  while (code) {
+    const int R = (int)(code & 15);
+    code >>= 4;
+    switch (R) {
+      case 2: mixed_stage<2, V>(pen, n, ns, twv, p, P); break;
+      case 3: mixed_stage<3, V>(pen, n, ns, twv, p, P); break;
+      case 4: mixed_stage<4, V>(pen, n, ns, twv, p, P); break;
+      case 5: mixed_stage<5, V>(pen, n, ns, twv, p, P); break;
+      case 7: mixed_stage<7, V>(pen, n, ns, twv, p, P); break;
+      case 8: mixed_stage<8, V>(pen, n, ns, twv, p, P); break;
+      case 11:
+        if constexpr (RMAX >= 11) mixed_stage<11, V>(pen, n, ns, twv, p, P);
+        break;
+      case 13:
+        if constexpr (RMAX >= 13) mixed_stage<13, V>(pen, n, ns, twv, p, P);
+        break;
+      default: break;  // the host never encodes other radices
+    }
+    ns *= R;
+  }
+  {
+    // rotated store: thread covers pencil tid mod T, outputs k = tid / T + ...
+    const int qs = tid % T;
+    const int64_t b = tile * T + qs;
+    if (b < a.B) {
+      float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+      const float2* ps = buf + qs * sq;
+      constexpr int S = T * NMAX / TH;  // outputs per thread, at most
+      constexpr int KS = TH / T;
+      float2 w[S];
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        const int k = tid / T + KS * i;
+        if (k < n) w[i] = ps[k];
+      }
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        const int k = tid / T + KS * i;
+        if (k < n) {
+          if (a.conj_out) w[i].y = -w[i].y;
+          d[k * a.oks] = w[i];
+        }
+      }
+    }
+  }
+}
+
+template <int T, int NMAX, int TH, int RMAX>
+hipError_t launch_mixed(const PassArgs& a, const float2* src, float2* dst, const float2* tw,
+                        const float2* twp, hipStream_t stream) {
+  const int64_t blocks = (a.B + T - 1) / T;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (a.res_mask < 2 || a.res_mask >= NMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fft_mixed_kernel<T, NMAX, TH, RMAX>), dim3((unsigned)blocks), dim3(TH), 0,
+                     stream, src, dst, tw, twp, a);
+  return hipGetLastError();
+}
+
+template <int T, int NMAX, int TH, int RMAX>
+KernelInfo kernel_info_mixed() {
+  constexpr int LDS = (T * NMAX + (2 * (T * NMAX + NMAX) * 8 <= 160 * 1024 ? NMAX : 0)) * 8;
+  static_assert(2 * LDS <= 160 * 1024, "two workgroups per CU");
+  static_assert(TH % T == 0 && NMAX % (TH / T) == 0 && TH <= 1024, "tile shape");
+  KernelInfo k{NMAX, T, MODE_ROW, MODE_COL, 0, TH, LDS, &launch_mixed<T, NMAX, TH, RMAX>, 0,
+               0};
+  k.mixed = RMAX;
+  return k;
+}
+
+}  // namespace dft3d

@@ -202,6 +202,31 @@ struct Builder {
     passes.push_back(p);
   }
 
+  // Mixed-radix pass of length n over the pencils of fields f
+  // (mixed_kernel.h documents the argument fields).
+  void add_mixed(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
+                 const std::string& label) {
+    const uint64_t code = mixed_radix_code(n);
+    int max_radix = 0;
+    for (uint64_t c = code; c; c >>= 4) max_radix = std::max(max_radix, (int)(c & 15));
+    const KernelInfo* k = find_mixed_kernel(n, max_radix);
+    if (!k || !code) {
+      status = DFT3D_ERR_UNSUPPORTED_SIZE;
+      return;
+    }
+    Pass p;
+    p.k = k;
+    set_fields(p.args, f, nf);
+    p.args.ijs = ijs;
+    p.args.oks = oks;
+    p.args.res_mask = n;
+    p.args.twp_mask = (int64_t)code;
+    p.args.xcd_remap = opt.xcd_remap;
+    p.tw_len = n;
+    p.label = label;
+    passes.push_back(p);
+  }
+
   // Fused 2D DFT of n0 contiguous (n1, n2) planes, in layout.
   void add_plane(const KernelInfo* k, int64_t n0, int64_t n1, int64_t n2,
                  const std::string& label) {
@@ -333,6 +358,14 @@ void volumetric_axis_from_shuffled(Builder& b, int64_t outer, int64_t n, int64_t
 void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
   const int64_t n = cur[2], B = cur[0] * cur[1];
   char lab[64];
+  if (!is_pow2(n) && mixed_radix_code(n)) {
+    // prime factors <= 13 (mixed_kernel.h): one rotate-on-write pass
+    Field f[1] = {{B, n, 1}};
+    std::snprintf(lab, sizeof lab, "pencil%d DFT%lld mixed x%lld rot", axis, (long long)n,
+                  (long long)B);
+    b.add_mixed(n, f, 1, 1, B, lab);
+    return;
+  }
   if (!is_pow2(n)) {
     // Bluestein (bluestein.h): the whole axis in one rotate-on-write pass
     Field f[1] = {{B, n, 1}};
@@ -390,15 +423,12 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
                  bool from_layout) {
   passes.clear();
   ws_bytes = 0;
-  // powers of two up to 4096; other lengths up to 2048 through Bluestein
-  // steps (pencil schedule, FP32, natural layout only)
+  // powers of two up to 4096; other lengths through the mixed-radix or the
+  // Bluestein pass (pencil schedule, FP32, natural layout only)
   bool any_other = false;
   for (int d = 0; d < 3; ++d) {
-    if (n[d] < 1 || n[d] > 4096) return DFT3D_ERR_UNSUPPORTED_SIZE;
-    if (!is_pow2(n[d])) {
-      if (n[d] > 2048) return DFT3D_ERR_UNSUPPORTED_SIZE;
-      any_other = true;
-    }
+    if (!length_supported(n[d])) return DFT3D_ERR_UNSUPPORTED_SIZE;
+    if (!is_pow2(n[d])) any_other = true;
   }
   if (schedule < DFT3D_SCHED_AUTO || schedule > DFT3D_SCHED_VOLUMETRIC)
     return DFT3D_ERR_INVALID_ARG;
@@ -573,6 +603,13 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << ",\"nontemporal\":" << p.k->nontemporal << ",\"precision\":" << p.k->precision
        << ",\"plane_rows\":" << p.k->plane_rows << ",\"fused_axes\":" << p.k->fused_axes
        << ",\"bluestein\":" << p.k->bluestein << ",\"bl_n\":" << p.bl_n
+       << ",\"mixed\":" << p.k->mixed << ",\"radices\":[";
+    if (p.k->mixed) {  // the stage radices, first stage first
+      bool first = true;
+      for (uint64_t c = (uint64_t)p.args.twp_mask; c; c >>= 4, first = false)
+        os << (first ? "" : ",") << (c & 15);
+    }
+    os << "]"
        << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""

@@ -13,6 +13,7 @@ void register_kernels_mfma_c(std::vector<KernelInfo>& v);
 void register_kernels_plane(std::vector<KernelInfo>& v);
 void register_kernels_fused(std::vector<KernelInfo>& v);
 void register_kernels_bluestein(std::vector<KernelInfo>& v);
+void register_kernels_mixed(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -27,6 +28,7 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_plane(v);
     register_kernels_fused(v);
     register_kernels_bluestein(v);
+    register_kernels_mixed(v);
     return v;
   }();
   return table;
@@ -38,9 +40,45 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
         k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0 &&
-        k.fused_axes == 0 && k.bluestein == 0)
+        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0)
       return &k;
   return nullptr;
+}
+
+const KernelInfo* find_mixed_kernel(int64_t n, int max_radix) {
+  const KernelInfo* best = nullptr;
+  for (const KernelInfo& k : kernel_registry())
+    if (k.mixed >= max_radix && k.n >= n &&
+        (!best || k.n < best->n || (k.n == best->n && k.mixed < best->mixed)))
+      best = &k;
+  return best;
+}
+
+uint64_t mixed_radix_code(int64_t n) {
+  if (n < 2) return 0;
+  int count[14] = {0};
+  for (int f : {2, 3, 5, 7, 11, 13})
+    while (n % f == 0) {
+      n /= f;
+      ++count[f];
+    }
+  if (n != 1) return 0;
+  std::vector<int> radices;
+  for (; count[2] >= 3; count[2] -= 3) radices.push_back(8);
+  if (count[2] == 2) radices.push_back(4);
+  if (count[2] == 1) radices.push_back(2);
+  for (int f : {3, 5, 7, 11, 13})
+    for (int i = 0; i < count[f]; ++i) radices.push_back(f);
+  if (radices.size() > 16) return 0;
+  uint64_t code = 0;
+  for (size_t i = 0; i < radices.size(); ++i) code |= (uint64_t)radices[i] << (4 * i);
+  return code;
+}
+
+bool length_supported(int64_t n) {
+  if (n < 1 || n > 4096) return false;
+  if ((n & (n - 1)) == 0) return true;
+  return mixed_radix_code(n) != 0 || n <= 2048;
 }
 
 const KernelInfo* find_bluestein_kernel(int m, int tile) {

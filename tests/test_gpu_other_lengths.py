@@ -1,12 +1,13 @@
-"""GPU parity for lengths that are not powers of two (Bluestein's chirp-z
-steps inside the pencil schedule), through the C ABI, against the FP64
-oracle's direct sums.
+"""GPU parity for lengths that are not powers of two, through the C ABI,
+against the FP64 oracle's direct sums: the mixed-radix pass (prime factors
+at most 13) and the Bluestein pass (other lengths up to 2048).
 
 Tolerance: each power-of-two axis of length n contributes log2(n) rounding
-levels, as in tol(N); an axis of length n done by Bluestein (convolution
-length m) contributes 2 log2(m) + 3: two FFTs of length m plus the chirp
-multiply before, the filter multiply between and the chirp multiply after
-them.  The bar is 1e-6 / 18 per level, the same rate as tol(N)."""
+levels, as in tol(N); a mixed-radix axis log2(n) + 1 (its odd radices are
+computed from pairs with rounded constants); a Bluestein axis (convolution
+length m) 2 log2(m) + 3: two FFTs of length m plus the chirp multiply
+before, the filter multiply between and the chirp multiply after them.  The
+bar is 1e-6 / 18 per level, the same rate as tol(N)."""
 import sys
 
 import numpy as np
@@ -33,11 +34,20 @@ def say(*a):
     sys.stdout.flush()
 
 
+def smooth13(n):
+    for f in (2, 3, 5, 7, 11, 13):
+        while n % f == 0:
+            n //= f
+    return n == 1
+
+
 def levels(shape):
     out = 0.0
     for n in shape:
         if n & (n - 1) == 0:
             out += np.log2(n) if n > 1 else 0.0
+        elif smooth13(n):
+            out += np.log2(n) + 1
         else:
             m = 1 << int(np.ceil(np.log2(2 * n - 1)))
             out += 2 * np.log2(m) + 3
@@ -55,16 +65,20 @@ def gpu_fftn(x_np, inverse=False, schedule="pencil"):
 
 
 SHAPES = [
-    (3, 5, 7), (6, 10, 12), (1, 1, 3), (9, 1, 1), (1, 17, 1), (2, 3, 4),
-    (100, 30, 17), (64, 100, 64), (12, 7, 16), (15, 8, 2048), (2047, 5, 3),
-    (3, 2000, 7), (5, 3, 1025), (96, 96, 96), (33, 65, 129),
+    # mixed radix (prime factors <= 13), every tile shape of the kernel
+    (3, 5, 7), (6, 10, 12), (1, 1, 3), (9, 1, 1), (2, 3, 4), (11, 13, 26),
+    (64, 100, 64), (12, 7, 16), (15, 8, 2048), (3, 2000, 7), (96, 96, 96),
+    (33, 65, 1001), (4095, 2, 3), (3, 3000, 2), (120, 384, 5), (243, 169, 4),
+    # Bluestein (a prime factor above 13), with mixed and power-of-two axes
+    (1, 17, 1), (100, 30, 17), (2047, 5, 3), (5, 3, 1025), (19, 23, 31),
+    (1009, 2, 6), (2039, 3, 1), (34, 37, 8),
 ]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("schedule", ["pencil", "auto"])
 def test_other_lengths_forward_inverse(shape, schedule):
-    say("case bluestein", shape, schedule)
+    say("case other length", shape, schedule)
     x = inputs.uniform_c64(shape, 31)
     t = tol_bl(shape)
     for sign, inv in ((-1, False), (1, True)):
@@ -75,7 +89,7 @@ def test_other_lengths_forward_inverse(shape, schedule):
         assert err <= t, (shape, sign, err)
 
 
-@pytest.mark.parametrize("shape", [(3, 5, 7), (100, 30, 17), (2047, 5, 3)])
+@pytest.mark.parametrize("shape", [(3, 5, 7), (100, 30, 17), (2047, 5, 3), (1000, 12, 9)])
 def test_other_lengths_round_trip(shape):
     x = inputs.uniform_c64(shape, 32)
     y = gpu_fftn(x)
@@ -103,11 +117,12 @@ def test_other_lengths_special_inputs():
     assert np.max(np.abs(gpu_fftn(x) - ref)) < 2e-6
 
 
-def test_other_lengths_full_size_sampled():
-    """A 1000 x 1000 x 100 transform (every axis by Bluestein): sampled
-    output pencils against the oracle's direct sums, Parseval, round trip."""
-    shape = (1000, 1000, 100)
-    say("case bluestein full size", shape)
+@pytest.mark.parametrize("shape", [(1000, 1000, 100), (1009, 1000, 64)])
+def test_other_lengths_full_size_sampled(shape):
+    """1000 x 1000 x 100 (mixed radix on every axis) and 1009 x 1000 x 64
+    (Bluestein, mixed radix, power of two): sampled output pencils against
+    the oracle's direct sums, Parseval, round trip."""
+    say("case other lengths full size", shape)
     x = inputs.uniform_c64(shape, 33)
     xt = torch.from_numpy(x).cuda()
     y = dft3d.fftn(xt, schedule="auto")
@@ -115,8 +130,8 @@ def test_other_lengths_full_size_sampled():
     N = x.size
     t = tol_bl(shape)
     g = np.random.default_rng(33)
-    k0 = np.concatenate([[0, 999, 500], g.integers(0, 1000, 5)])
-    k1 = np.concatenate([[0, 1, 999], g.integers(0, 1000, 5)])
+    k0 = np.concatenate([[0, shape[0] - 1, shape[0] // 2], g.integers(0, shape[0], 5)])
+    k1 = np.concatenate([[0, 1, shape[1] - 1], g.integers(0, shape[1], 5)])
     got = y[torch.from_numpy(k0).cuda(), torch.from_numpy(k1).cuda(), :].cpu().numpy()
     ref = oracle.sample_pencils(x, k0, k1, -1)
     err = oracle.rel_l2(got, ref)
@@ -136,8 +151,9 @@ def test_other_lengths_full_size_sampled():
 
 
 def test_other_lengths_in_a_batch():
-    """A batch holding a Bluestein plan runs plan by plan and still matches."""
-    shapes = [(3, 5, 7), (16, 16, 16), (6, 10, 12)]
+    """A batch holding plans of other lengths runs plan by plan and still
+    matches."""
+    shapes = [(3, 5, 7), (16, 16, 16), (6, 10, 17)]
     xs = [inputs.uniform_c64(s, 40 + i) for i, s in enumerate(shapes)]
     ys = dft3d.fftn_batched([torch.from_numpy(x).cuda() for x in xs])
     torch.cuda.synchronize()

@@ -34,6 +34,8 @@ def pass_points(p):
     """Points one work item (pencil, or plane for fused plane passes) covers."""
     if p.get("bluestein"):
         return p["bl_n"]
+    if p.get("mixed"):
+        return p["args"]["res_mask"]
     return p["n"] * max(1, p.get("plane_rows", 0))
 
 
@@ -319,7 +321,15 @@ def test_volumetric_1024_cubed_has_four_passes():
 
 
 OTHER_SHAPES = [(3, 5, 7), (6, 10, 12), (1, 1, 3), (9, 1, 1), (2, 3, 4), (100, 30, 17),
-                (64, 100, 64), (15, 8, 2048), (12, 7, 16)]
+                (64, 100, 64), (15, 8, 2048), (12, 7, 16), (19, 23, 4), (1009, 2, 3),
+                (11, 13, 26), (2039, 3, 1), (4095, 2, 1)]
+
+
+def is_smooth13(n):
+    for f in (2, 3, 5, 7, 11, 13):
+        while n % f == 0:
+            n //= f
+    return n == 1
 
 
 @pytest.mark.parametrize("shape", OTHER_SHAPES)
@@ -328,7 +338,7 @@ def test_bluestein_pass_lists(shape):
     the pass list computes the DFT, forward and inverse."""
     d = dft3d.describe(shape, "auto")
     assert d["schedule"] == "pencil"
-    assert any(p["bluestein"] for p in d["passes"])
+    assert any(p["bluestein"] or p["mixed"] for p in d["passes"])
     g = np.random.default_rng(sum(shape))
     x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
     for sign in (-1, 1):
@@ -340,16 +350,22 @@ def test_bluestein_pass_lists(shape):
 @pytest.mark.parametrize("shape", OTHER_SHAPES + [(2048, 1000, 3), (4096, 3, 5),
                                                   (1000, 1000, 1000)])
 def test_bluestein_axis_passes(shape):
-    """One pass per axis whose length is not a power of two, with its
-    convolution length, reading and writing N points of the chain's
+    """One pass per axis whose length is not a power of two (mixed radix
+    when its prime factors are at most 13, else Bluestein with its
+    convolution length), reading and writing N points of the chain's
     buffers (no region beyond N in the workspace)."""
     d = dft3d.describe(shape, "auto")
     N = shape[0] * shape[1] * shape[2]
     assert d["workspace_bytes"] <= 8 * N
     assert len(d["passes"]) == 3
     for p in d["passes"]:
-        n = p["bl_n"] if p["bluestein"] else p["n"]
+        n = pass_points(p)
         assert p["args"]["B"] * n == N
+        if n & (n - 1):
+            assert bool(p["mixed"]) == is_smooth13(n) and bool(p["bluestein"]) != is_smooth13(n)
+        if p["mixed"]:
+            assert int(np.prod(p["radices"])) == n and p["n"] >= n
+            assert set(p["radices"]) <= {2, 3, 4, 5, 7, 8, 11, 13}
         if p["bluestein"]:
             m = p["n"]
             assert m & (m - 1) == 0 and 2 * n - 1 <= m < 4 * n - 2
@@ -370,3 +386,56 @@ def test_bluestein_limits(schedule, opts):
         dft3d.describe((2049, 4, 4), "pencil")
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((3, 4, 4), "auto", "shuffled")
+
+
+def test_every_length_up_to_4096():
+    """Each length 1..4096 is planned as a power-of-two pass, a mixed-radix
+    pass (prime factors <= 13) or a Bluestein pass (other lengths up to
+    2048), or rejected (other lengths above 2048)."""
+    for n in range(1, 4097):
+        pow2 = n & (n - 1) == 0
+        if not pow2 and not is_smooth13(n) and n > 2048:
+            with pytest.raises(dft3d.Dft3dError):
+                dft3d.describe((n, 1, 1), "pencil")
+            continue
+        p = dft3d.describe((1, 1, n), "pencil")["passes"][0]
+        if n == 1:
+            continue
+        assert bool(p["mixed"]) == (not pow2 and is_smooth13(n)), n
+        assert bool(p["bluestein"]) == (not pow2 and not is_smooth13(n)), n
+        if p["mixed"]:
+            assert int(np.prod(p["radices"])) == n and p["n"] >= n
+
+
+def stockham_mixed(x, radices):
+    """The mixed-radix pass's stage formulas (index by index, as documented
+    with the kernel) on one pencil, in FP64."""
+    n = x.size
+    buf = x.astype(complex).copy()
+    ns = 1
+    for R in radices:
+        nr = n // R
+        out = np.empty_like(buf)
+        t = np.arange(nr)
+        g, tm = t // ns, t % ns
+        a = np.stack([buf[t + r * nr] for r in range(R)])              # (R, nr)
+        w = np.exp(-2j * np.pi * ((tm[None, :] * np.arange(R)[:, None]) % (ns * R))
+                   / (ns * R))
+        a = np.fft.fft(a * w, axis=0)                                   # DFT_R
+        for r in range(R):
+            out[g * ns * R + tm + r * ns] = a[r]
+        buf = out
+        ns *= R
+    return buf
+
+
+@pytest.mark.parametrize("n", [3, 5, 6, 7, 9, 11, 12, 13, 15, 24, 45, 96, 100, 120, 143,
+                               169, 243, 384, 1000, 1001, 1144, 2310, 3000, 4095])
+def test_mixed_stage_formulas(n):
+    """The stage indexing and twiddles of the mixed-radix pass, with the
+    radices the planner encodes, give the DFT of the pencil."""
+    p = dft3d.describe((1, 1, n), "pencil")["passes"][0]
+    assert p["mixed"]
+    x = np.random.default_rng(n).standard_normal(n) + 1j * np.random.default_rng(n + 1).standard_normal(n)
+    got = stockham_mixed(x, p["radices"])
+    assert oracle.rel_l2(got, oracle.dft3d(x.reshape(n, 1, 1), -1, "direct").reshape(-1)) < 1e-12
