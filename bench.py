@@ -20,7 +20,7 @@ The JSON line also carries:
                 precision at 256^3 and 1024^3, 96 uneven problems batched
                 per pass level against one plan at a time,
                 2048 x 1024 x 512 auto vs pencil, FP32 vs bf16x6 leaves, and
-                lengths that are not powers of two (1000^3, 96^3).
+                lengths that are not powers of two (1000^3, 1009^3, 96^3).
 """
 import argparse
 import json
@@ -266,11 +266,12 @@ def extras(x1024_host, args):
     del x, y
     torch.cuda.empty_cache()
 
-    # lengths that are not powers of two (one Bluestein pass per axis):
-    # 1000^3 (convolution length 2048 on every axis) and 96^3 (latency);
+    # lengths that are not powers of two, one pass per axis: 1000^3 and
+    # 96^3 (mixed radix) and 1009^3 (Bluestein, convolution length 2048);
     # uniform[-1, 1) inputs drawn on the device from a seeded generator
     bl = {}
-    for shape, reps in (((1000, 1000, 1000), 3), ((96, 96, 96), 100)):
+    for shape, reps in (((1000, 1000, 1000), 3), ((1009, 1009, 1009), 3),
+                        ((96, 96, 96), 100)):
         g = torch.Generator(device="cuda").manual_seed(6)
         x = torch.complex(torch.rand(shape, device="cuda", generator=g) * 2 - 1,
                           torch.rand(shape, device="cuda", generator=g) * 2 - 1)
@@ -284,8 +285,8 @@ def extras(x1024_host, args):
             "hbm_gbs_per_pass": round(16.0 * Np / (f / n * 1e-3) / 1e9, 1)}
         del x, y
         torch.cuda.empty_cache()
-    out["bluestein"] = bl
-    log(f"bench: bluestein {bl}")
+    out["other lengths"] = bl
+    log(f"bench: other lengths {bl}")
     return out
 
 

@@ -83,8 +83,8 @@ enum dft3d_precision {
 enum dft3d_status {
   DFT3D_OK = 0,
   DFT3D_ERR_INVALID_ARG = -1,          /* null pointer, bad enum, bad sign */
-  DFT3D_ERR_UNSUPPORTED_SIZE = -2,     /* n_d outside [1, 4096], or not a power
-                                          of two and above 2048 */
+  DFT3D_ERR_UNSUPPORTED_SIZE = -2,     /* n_d outside [1, 4096], or above 2048
+                                          with a prime factor above 13 */
   DFT3D_ERR_UNSUPPORTED_SCHEDULE = -3, /* schedule/layout/precision combination */
   DFT3D_ERR_NO_DEVICE = -4,            /* no HIP device visible */
   DFT3D_ERR_OUT_OF_MEMORY = -5,        /* device allocation failed */
@@ -124,14 +124,17 @@ enum dft3d_option {
 const char* dft3d_status_string(int status);
 
 /* Build a plan for a (n0, n1, n2) complex64 transform.  Each n_d is in
- * [1, 4096]; a length that is not a power of two must be at most 2048 and
- * is computed with Bluestein's chirp-z identity (the DFT of length n as a
- * circular convolution of length m, the power of two >= 2n - 1, done with
- * power-of-two FFTs; a standard method, not one of the paper's): only the
- * pencil schedule (or AUTO, which then picks it) with FP32 precision and
- * the natural layout takes such shapes, the others return
- * UNSUPPORTED_SCHEDULE, and the workspace grows by B * m * 8 bytes for the
- * largest B * m of its axes (B = N / n pencils).  Validates the arguments first
+ * [1, 4096].  Powers of two run on every schedule.  Other lengths (the
+ * paper's experiments use powers of two) run on the pencil schedule (or AUTO,
+ * which then picks it) with FP32 precision and the natural layout, one
+ * rotate-on-write pass per axis: a mixed-radix pass (radices 2, 3, 4, 5,
+ * 7, 8, 11, 13) when every prime factor of n_d is at most 13, else, for
+ * n_d <= 2048, a Bluestein pass (the DFT of length n as a circular
+ * convolution of length m, the power of two >= 2n - 1, done with two
+ * power-of-two FFTs in the same workgroup).  Other schedules, precisions
+ * or layouts with such lengths return UNSUPPORTED_SCHEDULE; lengths above
+ * 2048 with a prime factor above 13 return UNSUPPORTED_SIZE.  The
+ * workspace is N * 8 bytes as for powers of two.  Validates the arguments first
  * (INVALID_ARG / UNSUPPORTED_SIZE / UNSUPPORTED_SCHEDULE), then needs a HIP
  * device (NO_DEVICE), then allocates and uploads the twiddle tables on the
  * current device (OUT_OF_MEMORY / HIP_ERROR).  *out receives the handle, or
