@@ -70,12 +70,22 @@ int rebuild(dft3d_plan_s* p) {
   // the filter stored right after the chirp)
   std::map<int64_t, int64_t> offsets;
   std::map<std::pair<int, int64_t>, int64_t> bl_offsets;
+  // mixed-radix stage twiddles per length n (key: n, value: offset)
+  std::map<int64_t, std::pair<int64_t, uint64_t>> mx_offsets;
   int64_t total = 0;
   std::vector<const Pass*> all;
   for (const Pass& ps : passes) all.push_back(&ps);
   for (const Pass& ps : ipasses) all.push_back(&ps);
   for (const Pass* pp : all) {
     const Pass& ps = *pp;
+    if (ps.k->mixed) {
+      const int64_t len = ps.args.res_mask;
+      if (!mx_offsets.count(len)) {
+        mx_offsets[len] = {total, (uint64_t)ps.args.twp_mask};
+        total += len;
+      }
+      continue;
+    }
     for (int64_t len : {ps.tw_len, ps.twp_len}) {
       if (len > 0 && !offsets.count(len)) {
         offsets[len] = total;
@@ -100,6 +110,8 @@ int rebuild(dft3d_plan_s* p) {
     else
       make_leaf_table((int)-kv.first, reinterpret_cast<unsigned short*>(host.data() + kv.second));
   }
+  for (auto& kv : mx_offsets)
+    make_mixed_twiddles(kv.first, kv.second.second, host.data() + kv.second.first);
   for (auto& kv : bl_offsets) {
     if (kv.first.first == 1)
       make_chirp(kv.first.second, host.data() + kv.second);
@@ -122,12 +134,17 @@ int rebuild(dft3d_plan_s* p) {
   p->tables = dev;
   p->passes.swap(passes);
   p->ipasses.swap(ipasses);
-  auto table_offsets = [&offsets, &bl_offsets](const std::vector<Pass>& list,
-                                               std::vector<int64_t>& tw,
-                                               std::vector<int64_t>& twp) {
+  auto table_offsets = [&offsets, &bl_offsets, &mx_offsets](const std::vector<Pass>& list,
+                                                            std::vector<int64_t>& tw,
+                                                            std::vector<int64_t>& twp) {
     tw.clear();
     twp.clear();
     for (const Pass& ps : list) {
+      if (ps.k->mixed) {  // the stage twiddles of the length
+        tw.push_back(mx_offsets[ps.args.res_mask].first);
+        twp.push_back(0);
+        continue;
+      }
       if (ps.k->bluestein) {  // roots of m; the chirp, with the filter right after it
         tw.push_back(offsets[ps.tw_len]);
         twp.push_back(bl_offsets[{1, ps.bl_n}]);

@@ -97,6 +97,10 @@ void make_leaf_table(int precision, unsigned short* out);
 // w[j] = exp(-pi i j^2 / n) (n entries) and the filter H / m, H = DFT_m of
 // the wrapped conj(w[d]), d in (-n, n) (m entries), both from FP64.
 int64_t bluestein_length(int64_t n);  // m: the power of two >= 2n - 1
+// Stage twiddles of a mixed-radix pass (n - 1 entries): for the stage of
+// radix R after ns = product of the earlier radices, entry
+// (ns - 1) + (r - 1) ns + tm = w_{ns R}^{tm r} (r < R, tm < ns), from FP64.
+void make_mixed_twiddles(int64_t n, uint64_t code, float2* out);
 void make_chirp(int64_t n, float2* out);
 void make_bluestein_filter(int64_t n, float2* out);
 

@@ -3,8 +3,8 @@
 // eq. (3) with mixed radices 2, 3, 4, 5, 7, 8, 11, 13).
 //
 // A workgroup of TH threads takes a tile of T pencils (T * NMAX points fit
-// in 64 KB of LDS, so two workgroups share a CU; the roots of n are copied
-// next to them where the LDS has room, NMAX <= 2048).  The pencils are
+// in 64 KB of LDS, so two workgroups share a CU; the twiddle table is
+// copied next to them where the LDS has room, NMAX <= 2048).  The pencils are
 // loaded into LDS with lanes along each pencil; every stage reads its
 // butterflies' inputs into registers, waits, transforms and writes the
 // outputs back to their Stockham places, and waits again; the finished
@@ -12,10 +12,12 @@
 //
 // Stage s has radix R and ns = the product of the earlier radices.
 // Butterfly t (t < n / R) of a pencil takes inputs t + r n / R (r < R),
-// multiplies input r by w_{ns R}^{(t mod ns) r} = w_n^{(t mod ns) r n / (ns R)}
-// (the table of the n roots of n), transforms them with DFT_R and writes
-// output r to (t div ns) ns R + (t mod ns) + r ns.  After the last stage
-// the pencil is in natural order.
+// multiplies input r by w_{ns R}^{(t mod ns) r}, transforms them with DFT_R
+// and writes output r to (t div ns) ns R + (t mod ns) + r ns.  After the
+// last stage the pencil is in natural order.  The twiddles come from a
+// per-length table (n - 1 entries, FP64-built) holding w_{ns R}^{tm r} at
+// (ns - 1) + (r - 1) ns + tm, so that lanes with consecutive tm read
+// consecutive entries (conflict-free in LDS).
 //
 // PassArgs fields used: pencil fields and element strides as for every
 // pass, res_mask = n, twp_mask = the radices of the stages, 4 bits each,
@@ -77,7 +79,6 @@ __device__ __forceinline__ void mixed_stage(float2* pen, int n, int ns,
                                             const float2* __restrict__ tw, int p, int P) {
   constexpr int K = (V + R - 1) / R;
   const int nr = n / R;
-  const int step = nr / ns;  // n / (ns R)
   const int dq = P / ns, dr = P - dq * ns;
   int g = p / ns, tm = p - g * ns;  // t div ns, t mod ns for t = p
   float2 a[K][R];
@@ -91,7 +92,7 @@ __device__ __forceinline__ void mixed_stage(float2* pen, int n, int ns,
       for (int r = 0; r < R; ++r) a[i][r] = pen[t + r * nr];
       if (ns > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) a[i][r] = cmul(a[i][r], tw[tm * r * step]);
+        for (int r = 1; r < R; ++r) a[i][r] = cmul(a[i][r], tw[(ns - 1) + (r - 1) * ns + tm]);
       }
       dft_mixed<R>(a[i]);
     }
@@ -121,7 +122,7 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
                  const float2* __restrict__ twp, const PassArgs a) {
   constexpr int P = TH / T;             // threads per pencil
   constexpr int V = NMAX / P;           // points per thread
-  // roots in LDS where two workgroups per CU still fit
+  // twiddle table in LDS where two workgroups per CU still fit
   constexpr bool TWL = 2 * (T * NMAX + NMAX) * 8 <= 160 * 1024;
   __shared__ float2 buf[T * NMAX + (TWL ? NMAX : 0)];
   const int n = (int)a.res_mask;  // n < NMAX (NMAX is a power of two, n is not)
@@ -155,7 +156,7 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
 #pragma unroll
       for (int i = 0; i < (NMAX + TH - 1) / TH; ++i) {
         const int j = tid + TH * i;
-        if (j < n) tl[j] = tw[j];
+        if (j < n - 1) tl[j] = tw[j];  // the table's n - 1 entries
       }
     }
   }

@@ -63,12 +63,16 @@ uint64_t mixed_radix_code(int64_t n) {
       ++count[f];
     }
   if (n != 1) return 0;
+  // Odd radices first, then 2 or 4, then the 8s: the first stage writes
+  // its outputs at stride R in LDS, which an odd R spreads over every bank
+  // (measured with SQ_LDS_BANK_CONFLICT at 1000^3: stride 8 first stalls
+  // on conflicts); later stages write runs of ns consecutive points.
   std::vector<int> radices;
-  for (; count[2] >= 3; count[2] -= 3) radices.push_back(8);
-  if (count[2] == 2) radices.push_back(4);
-  if (count[2] == 1) radices.push_back(2);
   for (int f : {3, 5, 7, 11, 13})
     for (int i = 0; i < count[f]; ++i) radices.push_back(f);
+  if (count[2] % 3 == 2) radices.push_back(4);
+  if (count[2] % 3 == 1) radices.push_back(2);
+  for (int i = 0; i < count[2] / 3; ++i) radices.push_back(8);
   if (radices.size() > 16) return 0;
   uint64_t code = 0;
   for (size_t i = 0; i < radices.size(); ++i) code |= (uint64_t)radices[i] << (4 * i);

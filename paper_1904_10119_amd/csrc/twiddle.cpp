@@ -146,4 +146,19 @@ void make_bluestein_filter(int64_t n, float2* out) {
   }
 }
 
+void make_mixed_twiddles(int64_t n, uint64_t code, float2* out) {
+  int64_t ns = 1;
+  for (uint64_t c = code; c; c >>= 4) {
+    const int64_t R = (int64_t)(c & 15);
+    for (int64_t r = 1; r < R; ++r)
+      for (int64_t tm = 0; tm < ns; ++tm) {
+        double cr, sr;
+        root_fp64(tm * r, ns * R, cr, sr);
+        out[(ns - 1) + (r - 1) * ns + tm] = make_float2((float)cr, (float)(-sr));
+      }
+    ns *= R;
+  }
+  if (ns != n) return;  // the code always multiplies to n (mixed_radix_code)
+}
+
 }  // namespace dft3d
