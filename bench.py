@@ -42,21 +42,24 @@ def log(*a):
 
 
 def time_plan(plan, x, out, steps, warmup, inverse=False):
+    """Mean ms per step over the timed region (HIP events on the launch
+    stream, one between consecutive steps), the wall-clock seconds of the
+    region, and the per-step times (for the median and the minimum)."""
     import torch
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         plan.execute(x, out, inverse=inverse, stream=stream)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for i in range(steps):
         plan.execute(x, out, inverse=inverse, stream=stream)
-    e1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / steps, wall
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / steps, wall, per
 
 
 def cpu_baseline(x_host, budget_s=25.0, chunk=32768):
@@ -327,8 +330,12 @@ def main():
     desc = dft3d.describe(shape, args.schedule)
     log(f"bench: schedule {desc['schedule']} passes "
         f"{[p['label'] for p in desc['passes']]}")
-    ms, wall = time_plan(plan, x, out, args.steps, args.warmup)
-    log(f"bench: {ms:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms)")
+    ms, wall, per = time_plan(plan, x, out, args.steps, args.warmup)
+    per_sorted = sorted(per)
+    ms_median = per_sorted[len(per) // 2] if len(per) % 2 else \
+        0.5 * (per_sorted[len(per) // 2 - 1] + per_sorted[len(per) // 2])
+    log(f"bench: {ms:.3f} ms/step (median {ms_median:.3f}, min {per_sorted[0]:.3f}, "
+        f"wall {wall / args.steps * 1e3:.3f} ms)")
 
     per_launch_ms = ms / npass
     achieved = 16.0 * N / (per_launch_ms * 1e-3) / 1e9
@@ -344,6 +351,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_median": round(ms_median, 4),
+        "ms_min": round(per_sorted[0], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -439,3 +439,27 @@ def test_mixed_stage_formulas(n):
     x = np.random.default_rng(n).standard_normal(n) + 1j * np.random.default_rng(n + 1).standard_normal(n)
     got = stockham_mixed(x, p["radices"])
     assert oracle.rel_l2(got, oracle.dft3d(x.reshape(n, 1, 1), -1, "direct").reshape(-1)) < 1e-12
+
+
+try:
+    from hypothesis import given, settings, strategies as st
+except ImportError:  # pragma: no cover
+    given = None
+
+if given is not None:
+    LENGTHS = st.integers(min_value=1, max_value=40)
+
+    @settings(max_examples=40, deadline=None)
+    @given(st.tuples(LENGTHS, LENGTHS, LENGTHS), st.integers(0, 2**31 - 1),
+           st.sampled_from([-1, 1]))
+    def test_any_small_shape_pass_list(shape, seed, sign):
+        """Random shapes with lengths 1..40 (powers of two, mixed radix and
+        Bluestein axes mixed): the auto plan's pass list, run by the model,
+        gives the oracle's direct DFT, and its maps stay in bounds."""
+        d = dft3d.describe(shape, "auto")
+        N = shape[0] * shape[1] * shape[2]
+        check_pass_maps(d, N)
+        g = np.random.default_rng(seed)
+        x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+        got = run_model(x, d, sign)
+        assert oracle.rel_l2(got, oracle.dft3d(x, sign, "direct")) < 1e-12
