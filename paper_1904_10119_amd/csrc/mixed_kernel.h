@@ -4,10 +4,11 @@
 //
 // A workgroup of TH threads takes a tile of T pencils (T * NMAX points fit
 // in 64 KB of LDS, so two workgroups share a CU; the twiddle table is
-// copied next to them where the LDS has room, NMAX <= 2048).  The pencils are
-// loaded into LDS with lanes along each pencil; every stage reads its
-// butterflies' inputs into registers, waits, transforms and writes the
-// outputs back to their Stockham places, and waits again; the finished
+// copied next to them where the LDS has room, NMAX <= 2048).  The first
+// stage reads its butterflies straight from global memory (lanes along each
+// pencil) and writes its outputs to LDS; every later stage reads its
+// butterflies' inputs from LDS into registers, waits, transforms and writes
+// the outputs back to their Stockham places, and waits again; the finished
 // pencils are stored rotated (T consecutive pencils per output row).
 //
 // Stage s has radix R and ns = the product of the earlier radices.
@@ -114,6 +115,40 @@ __device__ __forceinline__ void mixed_stage(float2* pen, int n, int ns,
   __syncthreads();  // every output of the stage is written
 }
 
+// The first stage (ns = 1) straight from global memory: butterfly t reads
+// the pencil's points t + r n / R (consecutive t on consecutive lanes),
+// all of the thread's loads in flight before the transforms, and writes
+// its outputs to t R + r in LDS; no twiddles.
+template <int R, int V>
+__device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, int conj,
+                                                  float2* pen, int n, int p, int P) {
+  constexpr int K = (V + R - 1) / R;
+  const int nr = n / R;
+  float2 a[K][R];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int t = p + P * i;
+    if (t < nr) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[i][r] = s[(int64_t)(t + r * nr) * ijs];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int t = p + P * i;
+    if (t < nr) {
+      if (conj) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[i][r].y = -a[i][r].y;
+      }
+      dft_mixed<R>(a[i]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) pen[t * R + r] = a[i][r];
+    }
+  }
+  __syncthreads();  // every output of the stage is written
+}
+
 // RMAX: the largest radix compiled in (8, or 13 with the 11 and 13 stages,
 // whose registers lower the occupancy of every other stage too).
 template <int T, int NMAX, int TH, int RMAX>
@@ -131,39 +166,41 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
   const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
   const int q = tid / P, p = tid % P;
   float2* pen = buf + q * sq;
+  const float2* twv = TWL ? buf + T * NMAX : tw;
+  if constexpr (TWL) {  // the twiddle table's n - 1 entries into LDS
+    float2* tl = buf + T * NMAX;
+#pragma unroll
+    for (int i = 0; i < (NMAX + TH - 1) / TH; ++i) {
+      const int j = tid + TH * i;
+      if (j < n - 1) tl[j] = tw[j];
+    }
+  }
+  uint64_t code = (uint64_t)a.twp_mask;
+  int ns;
   {
     // pencils past the end of a ragged last tile read the last pencil
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
     const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
-    // all loads of the thread in flight at once, then into LDS
-    float2 v[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const int j = p + P * i;
-      if (j < n) v[i] = s[j * a.ijs];
+    const int R = (int)(code & 15);
+    code >>= 4;
+    switch (R) {
+      case 2: mixed_first_stage<2, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
+      case 3: mixed_first_stage<3, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
+      case 4: mixed_first_stage<4, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
+      case 5: mixed_first_stage<5, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
+      case 7: mixed_first_stage<7, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
+      case 8: mixed_first_stage<8, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
+      case 11:
+        if constexpr (RMAX >= 11) mixed_first_stage<11, V>(s, a.ijs, a.conj_in, pen, n, p, P);
+        break;
+      case 13:
+        if constexpr (RMAX >= 13) mixed_first_stage<13, V>(s, a.ijs, a.conj_in, pen, n, p, P);
+        break;
+      default: break;  // the host never encodes other radices
     }
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const int j = p + P * i;
-      if (j < n) {
-        if (a.conj_in) v[i].y = -v[i].y;
-        pen[j] = v[i];
-      }
-    }
-    if constexpr (TWL) {
-      float2* tl = buf + T * NMAX;
-#pragma unroll
-      for (int i = 0; i < (NMAX + TH - 1) / TH; ++i) {
-        const int j = tid + TH * i;
-        if (j < n - 1) tl[j] = tw[j];  // the table's n - 1 entries
-      }
-    }
+    ns = R;
   }
-  __syncthreads();
-  const float2* twv = TWL ? buf + T * NMAX : tw;
-  uint64_t code = (uint64_t)a.twp_mask;
-  int ns = 1;
   while (code) {
     const int R = (int)(code & 15);
     code >>= 4;
