@@ -55,7 +55,7 @@ struct KernelInfo {
   int plane_rows = 0; // > 0: fused 2D DFT of (plane_rows, n) planes, one per workgroup
   int fused_axes = 0; // 1: volumetric V2 of one axis fused with V1 of the next (n = a)
   int bluestein = 0;  // 1: one-pass Bluestein axis (length not a power of two, n = m)
-  int mixed = 0;      // > 0: mixed-radix pass in LDS for lengths up to n, radices up to this
+  int mixed = 0;      // > 0: mixed-radix pass in LDS for lengths up to n (the variant)
 };
 
 // All compiled pass kernels.
@@ -64,12 +64,14 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
                               int persistent, int nontemporal);
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
-// The mixed-radix pass kernel with the smallest tile length >= n that runs
-// radices up to max_radix (the leanest such kernel), if any.
-const KernelInfo* find_mixed_kernel(int64_t n, int max_radix);
-// Stage radices of a mixed-radix pass of length n, 4 bits per stage, first
+// The mixed-radix pass kernel of a variant (1: radices without 11 and 13,
+// 2: all) with the smallest tile length >= n, if any.
+const KernelInfo* find_mixed_kernel(int64_t n, int variant);
+// Stage radices of a mixed-radix pass of length n, 8 bits per stage, first
 // stage lowest; 0 if n has a prime factor above 13 or is 1.
 uint64_t mixed_radix_code(int64_t n);
+// The kernel variant a radix code needs.
+int mixed_variant(uint64_t code);
 // Whether a length is supported: powers of two up to 4096; lengths whose
 // prime factors are at most 13 up to 4096 (mixed radix); others up to 2048
 // (Bluestein).

@@ -1,22 +1,23 @@
 // Mixed-radix pencil pass kernels (lengths whose prime factors are at most
 // 13), per tile shape (T pencils of up to NMAX points, T * NMAX = 8192) and
-// largest radix: 8 for lengths without the factors 11 and 13 (512 threads),
-// else 13 (256 threads: its registers leave room for two workgroups per CU).
+// variant: 1 for lengths without the factors 11 and 13 (512 threads), 2
+// with them (256 threads: its registers leave room for two workgroups per
+// CU).
 #include "mixed_kernel.h"
 
 namespace dft3d {
 void register_kernels_mixed(std::vector<KernelInfo>& v) {
-  v.push_back(kernel_info_mixed<256, 32, 512, 8>());
-  v.push_back(kernel_info_mixed<64, 128, 512, 8>());
-  v.push_back(kernel_info_mixed<16, 512, 512, 8>());
-  v.push_back(kernel_info_mixed<8, 1024, 512, 8>());
-  v.push_back(kernel_info_mixed<4, 2048, 512, 8>());
-  v.push_back(kernel_info_mixed<2, 4096, 512, 8>());
-  v.push_back(kernel_info_mixed<256, 32, 256, 13>());
-  v.push_back(kernel_info_mixed<64, 128, 256, 13>());
-  v.push_back(kernel_info_mixed<16, 512, 256, 13>());
-  v.push_back(kernel_info_mixed<8, 1024, 256, 13>());
-  v.push_back(kernel_info_mixed<4, 2048, 256, 13>());
-  v.push_back(kernel_info_mixed<2, 4096, 256, 13>());
+  v.push_back(kernel_info_mixed<256, 32, 512, 1>());
+  v.push_back(kernel_info_mixed<64, 128, 512, 1>());
+  v.push_back(kernel_info_mixed<16, 512, 512, 1>());
+  v.push_back(kernel_info_mixed<8, 1024, 512, 1>());
+  v.push_back(kernel_info_mixed<4, 2048, 512, 1>());
+  v.push_back(kernel_info_mixed<2, 4096, 512, 1>());
+  v.push_back(kernel_info_mixed<256, 32, 256, 2>());
+  v.push_back(kernel_info_mixed<64, 128, 256, 2>());
+  v.push_back(kernel_info_mixed<16, 512, 256, 2>());
+  v.push_back(kernel_info_mixed<8, 1024, 256, 2>());
+  v.push_back(kernel_info_mixed<4, 2048, 256, 2>());
+  v.push_back(kernel_info_mixed<2, 4096, 256, 2>());
 }
 }  // namespace dft3d

@@ -1,6 +1,6 @@
 // Lengths whose prime factors are all at most 13: one rotate-on-write
 // pencil pass whose radix stages run in LDS (the Stockham factorisation of
-// eq. (3) with mixed radices 2, 3, 4, 5, 7, 8, 11, 13).
+// eq. (3) with mixed radices 2, 3, 4, 5, 7, 8, 10, 11, 13, 16).
 //
 // A workgroup of TH threads takes a tile of T pencils (T * NMAX points fit
 // in 64 KB of LDS, so two workgroups share a CU; the twiddle table is
@@ -21,8 +21,8 @@
 // consecutive entries (conflict-free in LDS).
 //
 // PassArgs fields used: pencil fields and element strides as for every
-// pass, res_mask = n, twp_mask = the radices of the stages, 4 bits each,
-// the first stage in the lowest bits (a zero nibble ends the list).
+// pass, res_mask = n, twp_mask = the radices of the stages, 8 bits each,
+// the first stage in the lowest bits (a zero byte ends the list).
 #pragma once
 
 #include "pass_kernel.h"
@@ -63,12 +63,75 @@ __device__ __forceinline__ void dft_odd(float2* x) {
   x[0] = y0;
 }
 
+constexpr int smallest_factor(int r) {
+  for (int f = 2; f * f <= r; ++f)
+    if (r % f == 0) return f;
+  return r;
+}
+
+// Forward DFT of length R in registers: powers of two and odd primes
+// directly; other R = A B (A its smallest prime factor) by the four-step
+// identity of eq. (3) in registers: DFT_A over a for every b (input index
+// b + B a), twiddle w_R^{b a'}, DFT_B over b (output index a' + A b').
 template <int R>
 __device__ __forceinline__ void dft_mixed(float2* x) {
   if constexpr ((R & (R - 1)) == 0) {
     dft<R>(x);
-  } else {
+  } else if constexpr (smallest_factor(R) == R) {
     dft_odd<R>(x);
+  } else {
+    constexpr int A = smallest_factor(R), B = R / A;
+    float2 z[R];
+    static_for<B>([&](auto bi) {
+      constexpr int b = decltype(bi)::value;
+      float2 s[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) s[a] = x[b + B * a];
+      dft_mixed<A>(s);
+      static_for<A>([&](auto ai) {
+        constexpr int a = decltype(ai)::value;
+        z[b + B * a] = mul_root<b * a, R>(s[a]);
+      });
+    });
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      float2 s[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) s[b] = z[b + B * a];
+      dft_mixed<B>(s);
+#pragma unroll
+      for (int b = 0; b < B; ++b) x[a + A * b] = s[b];
+    }
+  }
+}
+
+// Calls f(std::integral_constant<int, R>) for a stage radix R the kernel
+// variant runs: the primes 2, 3, 5, 7 and 4, 8 always; with COMP also the
+// composites 10 and 16 (variant 1 up to NMAX = 2048, where they keep the
+// kernel at 128 VGPRs or fewer); with VAR 2 also 11 and 13.  The host
+// encodes no other radix for the kernel it picks.
+template <int VAR, bool COMP, class F>
+__device__ __forceinline__ void with_radix(int R, F&& f) {
+  switch (R) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 10:
+      if constexpr (COMP) f(std::integral_constant<int, 10>{});
+      break;
+    case 16:
+      if constexpr (COMP) f(std::integral_constant<int, 16>{});
+      break;
+    case 11:
+      if constexpr (VAR >= 2) f(std::integral_constant<int, 11>{});
+      break;
+    case 13:
+      if constexpr (VAR >= 2) f(std::integral_constant<int, 13>{});
+      break;
+    default: break;
   }
 }
 
@@ -149,14 +212,15 @@ __device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, 
   __syncthreads();  // every output of the stage is written
 }
 
-// RMAX: the largest radix compiled in (8, or 13 with the 11 and 13 stages,
-// whose registers lower the occupancy of every other stage too).
-template <int T, int NMAX, int TH, int RMAX>
+// VAR: 1 without the radix-11 and radix-13 stages (whose registers would
+// lower the occupancy of every other stage too), 2 with them.
+template <int T, int NMAX, int TH, int VAR>
 __global__ void __launch_bounds__(TH)
 fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
                  const float2* __restrict__ twp, const PassArgs a) {
   constexpr int P = TH / T;             // threads per pencil
   constexpr int V = NMAX / P;           // points per thread
+  constexpr bool COMP = VAR == 1 && NMAX <= 2048;  // radices 10 and 16
   // twiddle table in LDS where two workgroups per CU still fit
   constexpr bool TWL = 2 * (T * NMAX + NMAX) * 8 <= 160 * 1024;
   __shared__ float2 buf[T * NMAX + (TWL ? NMAX : 0)];
@@ -182,43 +246,19 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
     const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
-    const int R = (int)(code & 15);
-    code >>= 4;
-    switch (R) {
-      case 2: mixed_first_stage<2, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
-      case 3: mixed_first_stage<3, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
-      case 4: mixed_first_stage<4, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
-      case 5: mixed_first_stage<5, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
-      case 7: mixed_first_stage<7, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
-      case 8: mixed_first_stage<8, V>(s, a.ijs, a.conj_in, pen, n, p, P); break;
-      case 11:
-        if constexpr (RMAX >= 11) mixed_first_stage<11, V>(s, a.ijs, a.conj_in, pen, n, p, P);
-        break;
-      case 13:
-        if constexpr (RMAX >= 13) mixed_first_stage<13, V>(s, a.ijs, a.conj_in, pen, n, p, P);
-        break;
-      default: break;  // the host never encodes other radices
-    }
+    const int R = (int)(code & 255);
+    code >>= 8;
+    with_radix<VAR, COMP>(R, [&](auto rc) {
+      mixed_first_stage<decltype(rc)::value, V>(s, a.ijs, a.conj_in, pen, n, p, P);
+    });
     ns = R;
   }
   while (code) {
-    const int R = (int)(code & 15);
-    code >>= 4;
-    switch (R) {
-      case 2: mixed_stage<2, V>(pen, n, ns, twv, p, P); break;
-      case 3: mixed_stage<3, V>(pen, n, ns, twv, p, P); break;
-      case 4: mixed_stage<4, V>(pen, n, ns, twv, p, P); break;
-      case 5: mixed_stage<5, V>(pen, n, ns, twv, p, P); break;
-      case 7: mixed_stage<7, V>(pen, n, ns, twv, p, P); break;
-      case 8: mixed_stage<8, V>(pen, n, ns, twv, p, P); break;
-      case 11:
-        if constexpr (RMAX >= 11) mixed_stage<11, V>(pen, n, ns, twv, p, P);
-        break;
-      case 13:
-        if constexpr (RMAX >= 13) mixed_stage<13, V>(pen, n, ns, twv, p, P);
-        break;
-      default: break;  // the host never encodes other radices
-    }
+    const int R = (int)(code & 255);
+    code >>= 8;
+    with_radix<VAR, COMP>(R, [&](auto rc) {
+      mixed_stage<decltype(rc)::value, V>(pen, n, ns, twv, p, P);
+    });
     ns *= R;
   }
   {
@@ -248,26 +288,26 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
   }
 }
 
-template <int T, int NMAX, int TH, int RMAX>
+template <int T, int NMAX, int TH, int VAR>
 hipError_t launch_mixed(const PassArgs& a, const float2* src, float2* dst, const float2* tw,
                         const float2* twp, hipStream_t stream) {
   const int64_t blocks = (a.B + T - 1) / T;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   if (a.res_mask < 2 || a.res_mask >= NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fft_mixed_kernel<T, NMAX, TH, RMAX>), dim3((unsigned)blocks), dim3(TH), 0,
+  hipLaunchKernelGGL((fft_mixed_kernel<T, NMAX, TH, VAR>), dim3((unsigned)blocks), dim3(TH), 0,
                      stream, src, dst, tw, twp, a);
   return hipGetLastError();
 }
 
-template <int T, int NMAX, int TH, int RMAX>
+template <int T, int NMAX, int TH, int VAR>
 KernelInfo kernel_info_mixed() {
   constexpr int LDS = (T * NMAX + (2 * (T * NMAX + NMAX) * 8 <= 160 * 1024 ? NMAX : 0)) * 8;
   static_assert(2 * LDS <= 160 * 1024, "two workgroups per CU");
   static_assert(TH % T == 0 && NMAX % (TH / T) == 0 && TH <= 1024, "tile shape");
-  KernelInfo k{NMAX, T, MODE_ROW, MODE_COL, 0, TH, LDS, &launch_mixed<T, NMAX, TH, RMAX>, 0,
+  KernelInfo k{NMAX, T, MODE_ROW, MODE_COL, 0, TH, LDS, &launch_mixed<T, NMAX, TH, VAR>, 0,
                0};
-  k.mixed = RMAX;
+  k.mixed = VAR;
   return k;
 }
 

@@ -207,9 +207,7 @@ struct Builder {
   void add_mixed(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
                  const std::string& label) {
     const uint64_t code = mixed_radix_code(n);
-    int max_radix = 0;
-    for (uint64_t c = code; c; c >>= 4) max_radix = std::max(max_radix, (int)(c & 15));
-    const KernelInfo* k = find_mixed_kernel(n, max_radix);
+    const KernelInfo* k = find_mixed_kernel(n, mixed_variant(code));
     if (!k || !code) {
       status = DFT3D_ERR_UNSUPPORTED_SIZE;
       return;
@@ -606,8 +604,8 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << ",\"mixed\":" << p.k->mixed << ",\"radices\":[";
     if (p.k->mixed) {  // the stage radices, first stage first
       bool first = true;
-      for (uint64_t c = (uint64_t)p.args.twp_mask; c; c >>= 4, first = false)
-        os << (first ? "" : ",") << (c & 15);
+      for (uint64_t c = (uint64_t)p.args.twp_mask; c; c >>= 8, first = false)
+        os << (first ? "" : ",") << (c & 255);
     }
     os << "]"
        << ",\"threads\":" << p.k->threads

@@ -1,4 +1,6 @@
 // Registry of the compiled pass kernels.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace dft3d {
@@ -45,17 +47,16 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   return nullptr;
 }
 
-const KernelInfo* find_mixed_kernel(int64_t n, int max_radix) {
+const KernelInfo* find_mixed_kernel(int64_t n, int variant) {
   const KernelInfo* best = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.mixed >= max_radix && k.n >= n &&
-        (!best || k.n < best->n || (k.n == best->n && k.mixed < best->mixed)))
-      best = &k;
+    if (k.mixed == variant && k.n >= n && (!best || k.n < best->n)) best = &k;
   return best;
 }
 
 uint64_t mixed_radix_code(int64_t n) {
   if (n < 2) return 0;
+  const int64_t n0 = n;
   int count[14] = {0};
   for (int f : {2, 3, 5, 7, 11, 13})
     while (n % f == 0) {
@@ -63,20 +64,39 @@ uint64_t mixed_radix_code(int64_t n) {
       ++count[f];
     }
   if (n != 1) return 0;
-  // Odd radices first, then 2 or 4, then the 8s: the first stage writes
+  // Composite radices (10 = 5 * 2, 16) only where the kernel without the
+  // 11 and 13 stages runs them (lengths below 2048): fewer stages, each an
+  // LDS round trip.
+  const bool comp = count[11] == 0 && count[13] == 0 && n0 < 2048;
+  // Odd radices first, then 10s, then powers of two: the first stage writes
   // its outputs at stride R in LDS, which an odd R spreads over every bank
-  // (measured with SQ_LDS_BANK_CONFLICT at 1000^3: stride 8 first stalls
-  // on conflicts); later stages write runs of ns consecutive points.
+  // (measured with SQ_LDS_BANK_CONFLICT at 1000^3); later stages write runs
+  // of ns consecutive points.
   std::vector<int> radices;
-  for (int f : {3, 5, 7, 11, 13})
-    for (int i = 0; i < count[f]; ++i) radices.push_back(f);
-  if (count[2] % 3 == 2) radices.push_back(4);
-  if (count[2] % 3 == 1) radices.push_back(2);
-  for (int i = 0; i < count[2] / 3; ++i) radices.push_back(8);
-  if (radices.size() > 16) return 0;
+  const int tens = comp ? std::min(count[5], count[2]) : 0;
+  for (int f : {13, 11, 7, 5, 3})
+    for (int i = 0; i < count[f] - (f == 5 ? tens : 0); ++i) radices.push_back(f);
+  for (int i = 0; i < tens; ++i) radices.push_back(10);
+  // the remaining power of two in as few stages as allowed (radix <= 16
+  // with composites, else <= 8), the exponents spread evenly
+  const int e = count[2] - tens, emax = comp ? 4 : 3;
+  if (e > 0) {
+    const int stages = (e + emax - 1) / emax;
+    std::vector<int> ex(stages, e / stages);
+    for (int i = 0; i < e % stages; ++i) ++ex[i];
+    std::sort(ex.begin(), ex.end());
+    for (int x : ex) radices.push_back(1 << x);
+  }
+  if (radices.size() > 8) return 0;
   uint64_t code = 0;
-  for (size_t i = 0; i < radices.size(); ++i) code |= (uint64_t)radices[i] << (4 * i);
+  for (size_t i = 0; i < radices.size(); ++i) code |= (uint64_t)radices[i] << (8 * i);
   return code;
+}
+
+int mixed_variant(uint64_t code) {
+  for (uint64_t c = code; c; c >>= 8)
+    if ((c & 255) == 11 || (c & 255) == 13) return 2;
+  return 1;
 }
 
 bool length_supported(int64_t n) {

@@ -148,8 +148,8 @@ void make_bluestein_filter(int64_t n, float2* out) {
 
 void make_mixed_twiddles(int64_t n, uint64_t code, float2* out) {
   int64_t ns = 1;
-  for (uint64_t c = code; c; c >>= 4) {
-    const int64_t R = (int64_t)(c & 15);
+  for (uint64_t c = code; c; c >>= 8) {
+    const int64_t R = (int64_t)(c & 255);
     for (int64_t r = 1; r < R; ++r)
       for (int64_t tm = 0; tm < ns; ++tm) {
         double cr, sr;

@@ -365,7 +365,10 @@ def test_bluestein_axis_passes(shape):
             assert bool(p["mixed"]) == is_smooth13(n) and bool(p["bluestein"]) != is_smooth13(n)
         if p["mixed"]:
             assert int(np.prod(p["radices"])) == n and p["n"] >= n
-            assert set(p["radices"]) <= {2, 3, 4, 5, 7, 8, 11, 13}
+            # composite radices only in the kernel without 11 and 13, below 2048
+            if {10, 16} & set(p["radices"]):
+                assert n < 2048 and not {11, 13} & set(p["radices"]), n
+            assert set(p["radices"]) <= {2, 3, 4, 5, 7, 8, 10, 11, 13, 16}
         if p["bluestein"]:
             m = p["n"]
             assert m & (m - 1) == 0 and 2 * n - 1 <= m < 4 * n - 2
@@ -405,6 +408,9 @@ def test_every_length_up_to_4096():
         assert bool(p["bluestein"]) == (not pow2 and not is_smooth13(n)), n
         if p["mixed"]:
             assert int(np.prod(p["radices"])) == n and p["n"] >= n
+            # composite radices only in the kernel without 11 and 13, below 2048
+            if {10, 16} & set(p["radices"]):
+                assert n < 2048 and not {11, 13} & set(p["radices"]), n
 
 
 def stockham_mixed(x, radices):
@@ -430,7 +436,8 @@ def stockham_mixed(x, radices):
 
 
 @pytest.mark.parametrize("n", [3, 5, 6, 7, 9, 11, 12, 13, 15, 24, 45, 96, 100, 120, 143,
-                               169, 243, 384, 1000, 1001, 1144, 2310, 3000, 4095])
+                               169, 243, 384, 768, 1000, 1001, 1144, 1250, 1920, 2000,
+                               2310, 3000, 3072, 4095])
 def test_mixed_stage_formulas(n):
     """The stage indexing and twiddles of the mixed-radix pass, with the
     radices the planner encodes, give the DFT of the pencil."""
