@@ -128,7 +128,7 @@ const char* dft3d_status_string(int status);
  * paper's experiments use powers of two) run on the pencil schedule (or AUTO,
  * which then picks it) with FP32 precision and the natural layout, one
  * rotate-on-write pass per axis: a mixed-radix pass (radices 2, 3, 4, 5,
- * 7, 8, 11, 13) when every prime factor of n_d is at most 13, else, for
+ * 7, 8, 10, 11, 13, 16) when every prime factor of n_d is at most 13, else, for
  * n_d <= 2048, a Bluestein pass (the DFT of length n as a circular
  * convolution of length m, the power of two >= 2n - 1, done with two
  * power-of-two FFTs in the same workgroup).  Other schedules, precisions
