@@ -34,6 +34,8 @@ def say(*a):
     ((32, 64, 128), "slab", "natural"),
     ((64, 32, 16), "volumetric", "shuffled"),
     ((512, 512, 512), "auto", "natural"),   # persistent streaming kernels
+    ((100, 30, 17), "pencil", "natural"),   # mixed-radix and Bluestein passes
+    ((1000, 96, 12), "auto", "natural"),    # mixed radix with radices 10 and 16
 ])
 def test_graph_replay_matches_eager(shape, schedule, layout):
     say("case graph", shape, schedule, layout)
@@ -67,13 +69,16 @@ def test_graph_replay_matches_eager(shape, schedule, layout):
         torch.cuda.synchronize()
         if x.numel() <= (1 << 21):
             sign = 1 if inverse else -1
-            ref = oracle.dft3d(x2.astype(np.complex128), sign, "fft")
+            pow2 = all(n & (n - 1) == 0 for n in shape)
+            # other lengths: direct sums, and twice the bar (a Bluestein axis
+            # carries about twice the rounding levels of its length)
+            ref = oracle.dft3d(x2.astype(np.complex128), sign, "fft" if pow2 else "direct")
             got = y.cpu().numpy()
             if layout == "shuffled":
                 f = dft3d.shuffle_factors(shape)
                 ref = oracle.to_shuffled(ref, f) if not inverse else oracle.dft3d(
                     oracle.from_shuffled(x2.astype(np.complex128), f), +1, "fft")
-            assert oracle.rel_l2(got, ref) <= oracle.tol(x.numel())
+            assert oracle.rel_l2(got, ref) <= oracle.tol(x.numel()) * (1 if pow2 else 2)
         else:
             eager2 = torch.empty_like(x)
             p.execute(x, eager2, inverse=inverse)

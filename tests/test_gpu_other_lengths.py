@@ -169,3 +169,16 @@ def test_other_lengths_rejected_by_other_schedules():
             dft3d.fftn(x, schedule=sched)
     with pytest.raises(dft3d.Dft3dError):
         dft3d.fftn(x, schedule="pencil", precision="bf16x6")
+
+
+@pytest.mark.parametrize("tile", [1, 2, 4, 8])
+def test_bluestein_tile_variants(tile):
+    """The Bluestein pass's tile variants (the tile option; lengths without a
+    variant of that tile keep their default) give the same transform."""
+    shape = (2039, 6, 20)  # m = 4096 on the first axis, 32 on the last
+    say("case bluestein tile", tile)
+    x = inputs.uniform_c64(shape, 50)
+    y = dft3d.fftn(torch.from_numpy(x).cuda(), schedule="pencil", tile=tile)
+    torch.cuda.synchronize()
+    ref = oracle.dft3d(x.astype(np.complex128), -1, "direct")
+    assert oracle.rel_l2(y.cpu().numpy(), ref) <= tol_bl(shape)
