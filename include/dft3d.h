@@ -83,8 +83,7 @@ enum dft3d_precision {
 enum dft3d_status {
   DFT3D_OK = 0,
   DFT3D_ERR_INVALID_ARG = -1,          /* null pointer, bad enum, bad sign */
-  DFT3D_ERR_UNSUPPORTED_SIZE = -2,     /* n_d outside [1, 4096], or above 2048
-                                          with a prime factor above 13 */
+  DFT3D_ERR_UNSUPPORTED_SIZE = -2,     /* n_d outside [1, 4096] */
   DFT3D_ERR_UNSUPPORTED_SCHEDULE = -3, /* schedule/layout/precision combination */
   DFT3D_ERR_NO_DEVICE = -4,            /* no HIP device visible */
   DFT3D_ERR_OUT_OF_MEMORY = -5,        /* device allocation failed */
@@ -128,13 +127,12 @@ const char* dft3d_status_string(int status);
  * paper's experiments use powers of two) run on the pencil schedule (or AUTO,
  * which then picks it) with FP32 precision and the natural layout, one
  * rotate-on-write pass per axis: a mixed-radix pass (radices 2, 3, 4, 5,
- * 7, 8, 10, 11, 13, 16) when every prime factor of n_d is at most 13, else, for
- * n_d <= 2048, a Bluestein pass (the DFT of length n as a circular
- * convolution of length m, the power of two >= 2n - 1, done with two
- * power-of-two FFTs in the same workgroup).  Other schedules, precisions
- * or layouts with such lengths return UNSUPPORTED_SCHEDULE; lengths above
- * 2048 with a prime factor above 13 return UNSUPPORTED_SIZE.  The
- * workspace is N * 8 bytes as for powers of two.  Validates the arguments first
+ * 7, 8, 10, 11, 13, 16) when every prime factor of n_d is at most 13, else
+ * a Bluestein pass (the DFT of length n as a circular convolution of length
+ * m, the power of two >= 2n - 1, up to 8192, done with two power-of-two FFTs
+ * in the same workgroup).  Other schedules, precisions or layouts with such
+ * lengths return UNSUPPORTED_SCHEDULE.  The workspace is N * 8 bytes as for
+ * powers of two.  Validates the arguments first
  * (INVALID_ARG / UNSUPPORTED_SIZE / UNSUPPORTED_SCHEDULE), then needs a HIP
  * device (NO_DEVICE), then allocates and uploads the twiddle tables on the
  * current device (OUT_OF_MEMORY / HIP_ERROR).  *out receives the handle, or

@@ -28,6 +28,12 @@
 
 namespace dft3d {
 
+// Convolution length 8192 (lengths 2049..4096): 32 elements per thread,
+// radices 32, 16, 16; two pencils per workgroup fill 135 KB of LDS.
+template <> struct Blocking<8192> {
+  static constexpr int E = 32, R0 = 32, R1 = 16, R2 = 16;
+};
+
 // One FFT of length M over the tile held in v (thread (q, p) has elements
 // p + P e), ending in LAST_MODE; on return v[e] is output p + P e of
 // pencil q under that mapping.  The caller makes sure no thread still reads

@@ -274,8 +274,7 @@ const char* dft3d_status_string(int status) {
     case DFT3D_OK: return "ok";
     case DFT3D_ERR_INVALID_ARG: return "invalid argument";
     case DFT3D_ERR_UNSUPPORTED_SIZE:
-      return "unsupported size (each n_d in [1, 4096]; lengths with a prime factor above 13 at "
-             "most 2048)";
+      return "unsupported size (each n_d must be in [1, 4096])";
     case DFT3D_ERR_UNSUPPORTED_SCHEDULE: return "unsupported schedule/layout/precision combination";
     case DFT3D_ERR_NO_DEVICE: return "no HIP device";
     case DFT3D_ERR_OUT_OF_MEMORY: return "device out of memory";

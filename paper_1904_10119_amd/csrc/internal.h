@@ -72,9 +72,9 @@ const KernelInfo* find_mixed_kernel(int64_t n, int variant);
 uint64_t mixed_radix_code(int64_t n);
 // The kernel variant a radix code needs.
 int mixed_variant(uint64_t code);
-// Whether a length is supported: powers of two up to 4096; lengths whose
-// prime factors are at most 13 up to 4096 (mixed radix); others up to 2048
-// (Bluestein).
+// Whether a length is supported: every length 1..4096 (powers of two,
+// mixed radix when the prime factors are at most 13, else Bluestein with a
+// convolution length up to 8192).
 bool length_supported(int64_t n);
 // The one-pass Bluestein axis kernel of convolution length m with the given
 // tile, else the length's default tile; null if none is compiled.

@@ -1,5 +1,5 @@
 // One-pass Bluestein axis kernels (lengths that are not powers of two), one
-// per convolution length m = 8 .. 4096 and tile.
+// per convolution length m = 8 .. 8192 and tile.
 #include "bluestein.h"
 
 namespace dft3d {
@@ -32,5 +32,7 @@ void register_kernels_bluestein(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info_bluestein<4096, 4>());
   v.push_back(kernel_info_bluestein<4096, 2>());
   v.push_back(kernel_info_bluestein<4096, 1>());
+  v.push_back(kernel_info_bluestein<8192, 2>());
+  v.push_back(kernel_info_bluestein<8192, 1>());
 }
 }  // namespace dft3d

@@ -99,11 +99,7 @@ int mixed_variant(uint64_t code) {
   return 1;
 }
 
-bool length_supported(int64_t n) {
-  if (n < 1 || n > 4096) return false;
-  if ((n & (n - 1)) == 0) return true;
-  return mixed_radix_code(n) != 0 || n <= 2048;
-}
+bool length_supported(int64_t n) { return n >= 1 && n <= 4096; }
 
 const KernelInfo* find_bluestein_kernel(int m, int tile) {
   const KernelInfo* first = nullptr;

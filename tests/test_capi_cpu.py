@@ -35,8 +35,8 @@ def test_status_strings():
     assert L.dft3d_status_string(-99) == b"unknown status"
 
 
-@pytest.mark.parametrize("shape", [(2049, 4, 4), (4, 0, 4), (8192, 2, 2), (4, 4, -2),
-                                   (4, 3001, 4), (4097, 1, 1), (2062, 2, 2)])
+@pytest.mark.parametrize("shape", [(4, 0, 4), (8192, 2, 2), (4, 4, -2), (4097, 1, 1),
+                                   (2, 5000, 3), (3, 3, 4099)])
 def test_bad_sizes_rejected(shape):
     h = ctypes.c_void_p(1)
     st = dft3d.lib().dft3d_plan(*shape, 0, 0, ctypes.byref(h))

@@ -1,6 +1,7 @@
 """GPU parity for lengths that are not powers of two, through the C ABI,
 against the FP64 oracle's direct sums: the mixed-radix pass (prime factors
-at most 13) and the Bluestein pass (other lengths up to 2048).
+at most 13) and the Bluestein pass (other lengths, convolution length up
+to 8192).
 
 Tolerance: each power-of-two axis of length n contributes log2(n) rounding
 levels, as in tol(N); a mixed-radix axis log2(n) + 1 (its odd radices are
@@ -72,6 +73,8 @@ SHAPES = [
     # Bluestein (a prime factor above 13), with mixed and power-of-two axes
     (1, 17, 1), (100, 30, 17), (2047, 5, 3), (5, 3, 1025), (19, 23, 31),
     (1009, 2, 6), (2039, 3, 1), (34, 37, 8),
+    # Bluestein with convolution length 8192 (lengths above 2048)
+    (4093, 2, 3), (3, 2062, 2),
 ]
 
 

@@ -322,7 +322,7 @@ def test_volumetric_1024_cubed_has_four_passes():
 
 OTHER_SHAPES = [(3, 5, 7), (6, 10, 12), (1, 1, 3), (9, 1, 1), (2, 3, 4), (100, 30, 17),
                 (64, 100, 64), (15, 8, 2048), (12, 7, 16), (19, 23, 4), (1009, 2, 3),
-                (11, 13, 26), (2039, 3, 1), (4095, 2, 1)]
+                (11, 13, 26), (2039, 3, 1), (4095, 2, 1), (4093, 2, 1), (2, 2062, 1)]
 
 
 def is_smooth13(n):
@@ -386,22 +386,22 @@ def test_bluestein_limits(schedule, opts):
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((3, 4, 4), schedule, **opts)
     with pytest.raises(dft3d.Dft3dError):
-        dft3d.describe((2049, 4, 4), "pencil")
+        dft3d.describe((4097, 4, 4), "pencil")
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((3, 4, 4), "auto", "shuffled")
 
 
 def test_every_length_up_to_4096():
     """Each length 1..4096 is planned as a power-of-two pass, a mixed-radix
-    pass (prime factors <= 13) or a Bluestein pass (other lengths up to
-    2048), or rejected (other lengths above 2048)."""
+    pass (prime factors <= 13) or a Bluestein pass (other lengths, with a
+    convolution length up to 8192); 4097 is rejected."""
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((4097, 1, 1), "pencil")
     for n in range(1, 4097):
         pow2 = n & (n - 1) == 0
-        if not pow2 and not is_smooth13(n) and n > 2048:
-            with pytest.raises(dft3d.Dft3dError):
-                dft3d.describe((n, 1, 1), "pencil")
-            continue
         p = dft3d.describe((1, 1, n), "pencil")["passes"][0]
+        if p["bluestein"]:
+            assert p["n"] <= 8192 and p["n"] >= 2 * n - 1, n
         if n == 1:
             continue
         assert bool(p["mixed"]) == (not pow2 and is_smooth13(n)), n
