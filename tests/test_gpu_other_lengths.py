@@ -185,3 +185,30 @@ def test_bluestein_tile_variants(tile):
     torch.cuda.synchronize()
     ref = oracle.dft3d(x.astype(np.complex128), -1, "direct")
     assert oracle.rel_l2(y.cpu().numpy(), ref) <= tol_bl(shape)
+
+
+def test_every_length_up_to_300():
+    """Every length 1..300 along the contiguous axis (powers of two, every
+    radix packing of the mixed-radix pass, Bluestein lengths with m = 8..1024)
+    against the oracle's direct sums, forward and inverse."""
+    worst = 0.0
+    for n in range(1, 301):
+        shape = (3, 4, n)
+        x = inputs.uniform_c64(shape, 1000 + n)
+        for sign, inv in ((-1, False), (1, True)):
+            y = gpu_fftn(x, inv)
+            err = oracle.rel_l2(y, oracle.dft3d(x.astype(np.complex128), sign, "direct"))
+            assert err <= tol_bl(shape), (n, sign, err)
+            worst = max(worst, err / tol_bl(shape))
+    say("  worst error / bar over lengths 1..300:", worst)
+
+
+@pytest.mark.parametrize("n", [2047, 2049, 2050, 2053, 2187, 3001, 3003, 3125, 4093, 4095])
+def test_lengths_near_the_limits(n):
+    """Lengths around 2048 and up to 4095 along the outermost axis."""
+    shape = (n, 2, 3)
+    x = inputs.uniform_c64(shape, 2000 + n)
+    y = gpu_fftn(x)
+    err = oracle.rel_l2(y, oracle.dft3d(x.astype(np.complex128), -1, "direct"))
+    say("  n", n, "rel_l2", err)
+    assert err <= tol_bl(shape), (n, err)
