@@ -19,8 +19,10 @@ The JSON line also carries:
                 inverse (latency), every schedule at 1024^3, every leaf
                 precision at 256^3 and 1024^3, 96 uneven problems batched
                 per pass level against one plan at a time,
-                2048 x 1024 x 512 auto vs pencil, FP32 vs bf16x6 leaves, and
-                lengths that are not powers of two (1000^3, 1009^3, 96^3).
+                2048 x 1024 x 512 auto vs pencil, FP32 vs bf16x6 leaves,
+                lengths that are not powers of two (1000^3, 1009^3, 96^3), and
+                rocFFT through torch.fft.fftn on the same shapes as a timed
+                vendor-library context (never a correctness reference).
 """
 import argparse
 import json
@@ -290,6 +292,30 @@ def extras(x1024_host, args):
         torch.cuda.empty_cache()
     out["other lengths"] = bl
     log(f"bench: other lengths {bl}")
+
+    # vendor-library context (timing only, never a correctness reference):
+    # rocFFT through torch.fft.fftn on the same shapes, beside this library
+    ctx = {}
+    for shape, reps in (((1024, 1024, 1024), 5), ((2048, 1024, 512), 5),
+                        ((1000, 1000, 1000), 3), ((256, 256, 256), 20), ((64, 64, 64), 100)):
+        g = torch.Generator(device="cuda").manual_seed(7)
+        x = torch.complex(torch.rand(shape, device="cuda", generator=g) * 2 - 1,
+                          torch.rand(shape, device="cuda", generator=g) * 2 - 1)
+        y = torch.empty_like(x)
+        try:
+            vendor = timed(lambda: torch.fft.fftn(x), reps)
+        except RuntimeError as e:  # no vendor FFT in this torch build
+            vendor = None
+            log(f"bench: torch.fft.fftn unavailable: {e}")
+        mine, _ = plan_ms(shape, x, y, reps, schedule="auto")
+        ctx["x".join(map(str, shape))] = {
+            "rocfft_torch_fftn_ms": None if vendor is None else round(vendor, 4),
+            "dft3d_ms": round(mine, 4),
+            "speedup": None if vendor is None else round(vendor / mine, 2)}
+        del x, y
+        torch.cuda.empty_cache()
+    out["vendor context (rocFFT via torch.fft.fftn, timing only)"] = ctx
+    log(f"bench: vendor context {ctx}")
     return out
 
 
