@@ -65,8 +65,10 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
 // The mixed-radix pass kernel of a variant (1: radices without 11 and 13,
-// 2: all) with the smallest tile length >= n, if any.
-const KernelInfo* find_mixed_kernel(int64_t n, int variant);
+// 2: all) for length n: the one with the given tile (pencils per workgroup)
+// if compiled, else the first registered with the smallest tile length
+// >= n; null if none.
+const KernelInfo* find_mixed_kernel(int64_t n, int variant, int tile);
 // Stage radices of a mixed-radix pass of length n, 8 bits per stage, first
 // stage lowest; 0 if n has a prime factor above 13 or is 1.
 uint64_t mixed_radix_code(int64_t n);

@@ -47,10 +47,13 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   return nullptr;
 }
 
-const KernelInfo* find_mixed_kernel(int64_t n, int variant) {
+const KernelInfo* find_mixed_kernel(int64_t n, int variant, int tile) {
   const KernelInfo* best = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.mixed == variant && k.n >= n && (!best || k.n < best->n)) best = &k;
+    if (k.mixed == variant && k.n >= n) {
+      if (tile > 0 && k.tile == tile) return &k;  // the asked-for tile, if any
+      if (!best || k.n < best->n) best = &k;      // else the first, smallest
+    }
   return best;
 }
 
