@@ -11,8 +11,9 @@
 // which recovers FP32-level accuracy from 8- or 11-bit significands.  A
 // leftover radix-2/4/8 stage and every twiddle run in FP32 on the vector
 // ALUs.  The first stage takes its operands straight from the registers
-// the tile was loaded into, later stages run in place in LDS, and a
-// leftover radix writes straight to global memory; the persistent form
+// the tile was loaded into, later stages run in LDS (in place in the
+// one-tile form, ping-pong between two buffers in the persistent form), and
+// a leftover radix writes straight to global memory; the persistent form
 // loads the next tile into registers meanwhile.
 //
 // Operand lane layout of the 16x16x32 MFMA (checked on gfx950): lane l
@@ -288,11 +289,11 @@ __device__ __forceinline__ void mfma_first_stage(const float2 (&v)[kMfmaRegs], f
   }
 }
 
-// The remaining radix-16 stages, in place in the LDS tile: every lane reads
-// the inputs of its four 16-vector groups (twiddled) into registers, the
-// workgroup waits, and the leaves write their outputs back to their
-// Stockham places.  One buffer (not two) leaves room for two workgroups per
-// CU.
+// The one-tile form's later radix-16 stages, in place in the LDS tile:
+// every lane reads the inputs of its four 16-vector groups (twiddled) into
+// registers, the workgroup waits, and the leaves write their outputs back to
+// their Stockham places.  One buffer (not two) leaves room for two
+// workgroups per CU.
 template <int N, int PREC>
 __device__ __forceinline__ void mfma_later_stages(float2* io, const float2* ltw,
                                                   const LeafA<PREC>& A, int tid) {
@@ -326,6 +327,45 @@ __device__ __forceinline__ void mfma_later_stages(float2* io, const float2* ltw,
     __syncthreads();  // every output of the stage is written
     NS *= 16;
   }
+}
+
+// The persistent form's later stages: ping-pong between two LDS buffers
+// (starting from buffer 0; no wait between a stage's reads and its writes,
+// and fewer registers held across the waits than in place); returns the
+// buffer index holding the result.
+template <int N, int PREC>
+__device__ __forceinline__ int mfma_later_stages_pingpong(float2 (*buf)[mfma_buf_elems<N>()],
+                                                 const float2* ltw, const LeafA<PREC>& A,
+                                                 int tid) {
+  constexpr int S16 = mfma_stages<N>();
+  constexpr int stride = N / 16;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rb = 8 * ((lane >> 4) & 1) + 4 * (lane >> 5);
+  int cur = 0;
+  int NS = 16;
+#pragma unroll
+  for (int st = 1; st < S16; ++st) {
+    const float2* in = buf[cur];
+    float2* out = buf[cur ^ 1];
+    const int twstep = N / (NS * 16);
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+      int q, t;
+      mfma_vec<N, MODE_ROW>(wave * 64 + g4 * 16 + (lane & 15), q, t);
+      const int tm = t & (NS - 1);
+      float2 x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = rb + k;
+        x[k] = cmul(in[mfma_lds<N>(q, t + r * stride)], ltw[tm * r * twstep]);
+      }
+      mfma_leaf_store<N, PREC>(x, A, out, q, t, NS, lane);
+    }
+    __syncthreads();
+    cur ^= 1;
+    NS *= 16;
+  }
+  return cur;
 }
 
 // Last step: with a leftover radix, its butterflies read LDS and write
@@ -411,7 +451,7 @@ __global__ void __launch_bounds__(mfma_threads<N>())
 fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restrict__ tw,
                          const unsigned short* __restrict__ leaf, const PassArgs a) {
   constexpr int T = mfma_tile_elems<N>() / N;
-  __shared__ float2 buf[mfma_buf_elems<N>()];
+  __shared__ float2 buf[2][mfma_buf_elems<N>()];
   __shared__ float2 ltw[N];
   const int tid = threadIdx.x;
   const int64_t ntiles = (a.B + T - 1) / T;
@@ -426,13 +466,13 @@ fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restric
   A.load(leaf, tid & 63);
   __syncthreads();  // twiddles in LDS
   while (true) {
-    mfma_first_stage<N, LM, PREC>(v, buf, A, a.conj_in, tid);
+    mfma_first_stage<N, LM, PREC>(v, buf[0], A, a.conj_in, tid);
     __syncthreads();
     const int64_t wn = w + G;
     // prefetch the next tile (past the end: the last tile again, in bounds)
     mfma_load<N, LM>(v, src, a, tile_index(wn < last ? wn : last, ntiles, a.xcd_remap), tid);
-    mfma_later_stages<N, PREC>(buf, ltw, A, tid);
-    mfma_finish<N, SM>(buf, dst, ltw, a, tile_index(w, ntiles, a.xcd_remap), tid);
+    const int cur = mfma_later_stages_pingpong<N, PREC>(buf, ltw, A, tid);
+    mfma_finish<N, SM>(buf[cur], dst, ltw, a, tile_index(w, ntiles, a.xcd_remap), tid);
     __syncthreads();  // every read of the result buffer is done
     w = wn;
     if (w >= ntiles) break;
@@ -477,7 +517,7 @@ hipError_t launch_mfma_persistent(const PassArgs& a, const float2* src, float2* 
 template <int N, int LM, int SM, int PREC, int PERS>
 KernelInfo kernel_info_mfma() {
   constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int LDS = (mfma_buf_elems<N>() + N) * 8;
+  constexpr int LDS = ((PERS ? 2 : 1) * mfma_buf_elems<N>() + N) * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(mfma_tile_elems<N>() % (16 * mfma_threads<N>()) == 0, "whole rounds");
   return KernelInfo{N, T, LM, SM, 0, mfma_threads<N>(), LDS,
