@@ -182,12 +182,12 @@ __device__ __forceinline__ void mixed_stage(float2* pen, int n, int ns,
 // the pencil's points t + r n / R (consecutive t on consecutive lanes),
 // all of the thread's loads in flight before the transforms, and writes
 // its outputs to t R + r in LDS; no twiddles.
-template <int R, int V>
-__device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, int conj,
-                                                  float2* pen, int n, int p, int P) {
-  constexpr int K = (V + R - 1) / R;
+template <int R, int V> constexpr int mixed_first_count() { return (V + R - 1) / R; }
+
+template <int R, int V, int K = (V + R - 1) / R>
+__device__ __forceinline__ void mixed_first_load(float2 (&a)[K][R], const float2* s,
+                                                 int64_t ijs, int n, int p, int P) {
   const int nr = n / R;
-  float2 a[K][R];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     const int t = p + P * i;
@@ -196,6 +196,12 @@ __device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, 
       for (int r = 0; r < R; ++r) a[i][r] = s[(int64_t)(t + r * nr) * ijs];
     }
   }
+}
+
+template <int R, int V, int K = (V + R - 1) / R>
+__device__ __forceinline__ void mixed_first_compute(float2 (&a)[K][R], int conj, float2* pen,
+                                                    int n, int p, int P) {
+  const int nr = n / R;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     const int t = p + P * i;
@@ -210,6 +216,56 @@ __device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, 
     }
   }
   __syncthreads();  // every output of the stage is written
+}
+
+template <int R, int V>
+__device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, int conj,
+                                                  float2* pen, int n, int p, int P) {
+  float2 a[mixed_first_count<R, V>()][R];
+  mixed_first_load<R, V>(a, s, ijs, n, p, P);
+  mixed_first_compute<R, V>(a, conj, pen, n, p, P);
+}
+
+// The later stages (radices in code, ns = the first radix) and the rotated
+// store of the tile's pencils (thread covers pencil tid mod T, outputs
+// k = tid / T + (TH / T) i).
+template <int T, int NMAX, int TH, int VAR>
+__device__ __forceinline__ void mixed_rest(uint64_t code, int ns, float2* buf, float2* pen,
+                                           const float2* twv, float2* dst, const PassArgs& a,
+                                           int64_t tile, int n, int sq, int tid, int p) {
+  constexpr int P = TH / T;
+  constexpr int V = NMAX / P;
+  constexpr bool COMP = VAR == 1 && NMAX <= 2048;  // radices 10 and 16
+  while (code) {
+    const int R = (int)(code & 255);
+    code >>= 8;
+    with_radix<VAR, COMP>(R, [&](auto rc) {
+      mixed_stage<decltype(rc)::value, V>(pen, n, ns, twv, p, P);
+    });
+    ns *= R;
+  }
+  const int qs = tid % T;
+  const int64_t b = tile * T + qs;
+  if (b < a.B) {
+    float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+    const float2* ps = buf + qs * sq;
+    constexpr int S = T * NMAX / TH;  // outputs per thread, at most
+    constexpr int KS = TH / T;
+    float2 w[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const int k = tid / T + KS * i;
+      if (k < n) w[i] = ps[k];
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const int k = tid / T + KS * i;
+      if (k < n) {
+        if (a.conj_out) w[i].y = -w[i].y;
+        d[k * a.oks] = w[i];
+      }
+    }
+  }
 }
 
 // VAR: 1 without the radix-11 and radix-13 stages (whose registers would
@@ -253,39 +309,7 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
     });
     ns = R;
   }
-  while (code) {
-    const int R = (int)(code & 255);
-    code >>= 8;
-    with_radix<VAR, COMP>(R, [&](auto rc) {
-      mixed_stage<decltype(rc)::value, V>(pen, n, ns, twv, p, P);
-    });
-    ns *= R;
-  }
-  {
-    // rotated store: thread covers pencil tid mod T, outputs k = tid / T + ...
-    const int qs = tid % T;
-    const int64_t b = tile * T + qs;
-    if (b < a.B) {
-      float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
-      const float2* ps = buf + qs * sq;
-      constexpr int S = T * NMAX / TH;  // outputs per thread, at most
-      constexpr int KS = TH / T;
-      float2 w[S];
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const int k = tid / T + KS * i;
-        if (k < n) w[i] = ps[k];
-      }
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const int k = tid / T + KS * i;
-        if (k < n) {
-          if (a.conj_out) w[i].y = -w[i].y;
-          d[k * a.oks] = w[i];
-        }
-      }
-    }
-  }
+  mixed_rest<T, NMAX, TH, VAR>(code, ns, buf, pen, twv, dst, a, tile, n, sq, tid, p);
 }
 
 template <int T, int NMAX, int TH, int VAR>
@@ -294,7 +318,8 @@ hipError_t launch_mixed(const PassArgs& a, const float2* src, float2* dst, const
   const int64_t blocks = (a.B + T - 1) / T;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  if (a.res_mask < 2 || a.res_mask >= NMAX) return hipErrorInvalidValue;
+  if (a.res_mask < 2 || a.res_mask >= NMAX || !mixed_kernel_runs(VAR, NMAX, (uint64_t)a.twp_mask))
+    return hipErrorInvalidValue;  // a stage radix this kernel does not run
   hipLaunchKernelGGL((fft_mixed_kernel<T, NMAX, TH, VAR>), dim3((unsigned)blocks), dim3(TH), 0,
                      stream, src, dst, tw, twp, a);
   return hipGetLastError();

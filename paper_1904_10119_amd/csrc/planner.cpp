@@ -212,7 +212,7 @@ struct Builder {
   void add_mixed(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
                  const std::string& label) {
     const uint64_t code = mixed_radix_code(n);
-    const KernelInfo* k = find_mixed_kernel(n, mixed_variant(code), opt.tile);
+    const KernelInfo* k = find_mixed_kernel(n, code, opt.tile);
     if (!k || !code) {
       status = DFT3D_ERR_UNSUPPORTED_SIZE;
       return;

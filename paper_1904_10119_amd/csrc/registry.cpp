@@ -47,10 +47,25 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   return nullptr;
 }
 
-const KernelInfo* find_mixed_kernel(int64_t n, int variant, int tile) {
+bool mixed_kernel_runs(int variant, int nmax, uint64_t code) {
+  for (uint64_t c = code; c; c >>= 8) {
+    const int r = (int)(c & 255);
+    if (r == 11 || r == 13) {
+      if (variant < 2) return false;
+    } else if (r == 10 || r == 16) {  // composites: variant 1 up to 2048 only
+      if (variant != 1 || nmax > 2048) return false;
+    } else if (r != 2 && r != 3 && r != 4 && r != 5 && r != 7 && r != 8) {
+      return false;
+    }
+  }
+  return true;
+}
+
+const KernelInfo* find_mixed_kernel(int64_t n, uint64_t code, int tile) {
+  const int variant = mixed_variant(code);
   const KernelInfo* best = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.mixed == variant && k.n >= n) {
+    if (k.mixed == variant && k.n >= n && mixed_kernel_runs(k.mixed, k.n, code)) {
       if (tile > 0 && k.tile == tile) return &k;  // the asked-for tile, if any
       if (!best || k.n < best->n) best = &k;      // else the first, smallest
     }

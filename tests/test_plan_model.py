@@ -470,3 +470,23 @@ if given is not None:
         x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
         got = run_model(x, d, sign)
         assert oracle.rel_l2(got, oracle.dft3d(x, sign, "direct")) < 1e-12
+
+
+@pytest.mark.parametrize("tile", [0, 2, 4, 8, 16, 32, 64, 256])
+def test_mixed_kernel_runs_its_radices(tile):
+    """Whatever the tile option, the mixed-radix kernel a plan picks runs
+    every stage radix of its length: composites (10, 16) only in the
+    variant without 11 and 13 with a tile length of at most 2048; 11 and 13
+    only in the other variant."""
+    for n in list(range(3, 300)) + [500, 768, 1000, 1001, 1536, 2000, 2187, 3000, 4095]:
+        if n & (n - 1) == 0 or not is_smooth13(n):
+            continue
+        kw = {"tile": tile} if tile else {}
+        p = dft3d.describe((1, 1, n), "pencil", **kw)["passes"][0]
+        assert p["mixed"], n
+        r = set(p["radices"])
+        if r & {10, 16}:
+            assert p["mixed"] == 1 and p["n"] <= 2048, (n, tile, p["n"])
+        if r & {11, 13}:
+            assert p["mixed"] == 2, (n, tile)
+        assert p["n"] > n
