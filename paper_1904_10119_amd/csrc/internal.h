@@ -56,6 +56,8 @@ struct KernelInfo {
   int fused_axes = 0; // 1: volumetric V2 of one axis fused with V1 of the next (n = a)
   int bluestein = 0;  // 1: one-pass Bluestein axis (length not a power of two, n = m)
   int mixed = 0;      // > 0: mixed-radix pass in LDS for lengths up to n (the variant)
+  int fixed_n = 0;              // mixed-radix pass compiled for this one length, 0: any
+  uint64_t fixed_code = 0;      // and its radix code
 };
 
 // All compiled pass kernels.

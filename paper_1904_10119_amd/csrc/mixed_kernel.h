@@ -312,6 +312,76 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
   mixed_rest<T, NMAX, TH, VAR>(code, ns, buf, pen, twv, dst, a, tile, n, sq, tid, p);
 }
 
+// Stages of a compile-time radix code (the first stage done, NS = its radix).
+template <uint64_t CODE, int NS, int V, int N>
+__device__ __forceinline__ void mixed_stages_fixed(float2* pen, const float2* twv, int p,
+                                                   int P) {
+  if constexpr (CODE != 0) {
+    constexpr int R = (int)(CODE & 255);
+    mixed_stage<R, V>(pen, N, NS, twv, p, P);
+    mixed_stages_fixed<(CODE >> 8), NS * R, V, N>(pen, twv, p, P);
+  }
+}
+
+// The same pass for one length N known at compile time, with its radix code
+// CODE (variant 1 radices): the stage sizes, the butterfly index arithmetic
+// and the LDS offsets fold into constants and the radix switch disappears.
+template <int T, int NMAX, int TH, int N, uint64_t CODE>
+__global__ void __launch_bounds__(TH)
+fft_mixed_fixed(const float2* src, float2* dst, const float2* __restrict__ tw,
+                const float2* __restrict__ twp, const PassArgs a) {
+  constexpr int P = TH / T;
+  constexpr int V = NMAX / P;
+  constexpr bool TWL = 2 * (T * NMAX + NMAX) * 8 <= 160 * 1024;
+  static_assert(N < NMAX, "length fits the tile");
+  __shared__ float2 buf[T * NMAX + (TWL ? NMAX : 0)];
+  constexpr int sq = N + 1;
+  const int tid = threadIdx.x;
+  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int q = tid / P, p = tid % P;
+  float2* pen = buf + q * sq;
+  const float2* twv = TWL ? buf + T * NMAX : tw;
+  if constexpr (TWL) {
+    float2* tl = buf + T * NMAX;
+#pragma unroll
+    for (int i = 0; i < (NMAX + TH - 1) / TH; ++i) {
+      const int j = tid + TH * i;
+      if (j < N - 1) tl[j] = tw[j];
+    }
+  }
+  int64_t b = tile * T + q;
+  b = b < a.B ? b : a.B - 1;
+  const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+  constexpr int R1 = (int)(CODE & 255);
+  mixed_first_stage<R1, V>(s, a.ijs, a.conj_in, pen, N, p, P);
+  mixed_stages_fixed<(CODE >> 8), R1, V, N>(pen, twv, p, P);
+  mixed_rest<T, NMAX, TH, 1>(0, N, buf, pen, twv, dst, a, tile, N, sq, tid, p);  // store
+}
+
+template <int T, int NMAX, int TH, int N, uint64_t CODE>
+hipError_t launch_mixed_fixed(const PassArgs& a, const float2* src, float2* dst,
+                              const float2* tw, const float2* twp, hipStream_t stream) {
+  const int64_t blocks = (a.B + T - 1) / T;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (a.res_mask != N || (uint64_t)a.twp_mask != CODE) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fft_mixed_fixed<T, NMAX, TH, N, CODE>), dim3((unsigned)blocks), dim3(TH),
+                     0, stream, src, dst, tw, twp, a);
+  return hipGetLastError();
+}
+
+template <int T, int NMAX, int TH, int N, uint64_t CODE>
+KernelInfo kernel_info_mixed_fixed() {
+  constexpr int LDS = (T * NMAX + (2 * (T * NMAX + NMAX) * 8 <= 160 * 1024 ? NMAX : 0)) * 8;
+  static_assert(2 * LDS <= 160 * 1024, "two workgroups per CU");
+  KernelInfo k{NMAX, T, MODE_ROW, MODE_COL, 0, TH, LDS, &launch_mixed_fixed<T, NMAX, TH, N, CODE>,
+               0, 0};
+  k.mixed = 1;
+  k.fixed_n = N;
+  k.fixed_code = CODE;
+  return k;
+}
+
 template <int T, int NMAX, int TH, int VAR>
 hipError_t launch_mixed(const PassArgs& a, const float2* src, float2* dst, const float2* tw,
                         const float2* twp, hipStream_t stream) {

@@ -606,7 +606,7 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << ",\"nontemporal\":" << p.k->nontemporal << ",\"precision\":" << p.k->precision
        << ",\"plane_rows\":" << p.k->plane_rows << ",\"fused_axes\":" << p.k->fused_axes
        << ",\"bluestein\":" << p.k->bluestein << ",\"bl_n\":" << p.bl_n
-       << ",\"mixed\":" << p.k->mixed << ",\"radices\":[";
+       << ",\"mixed\":" << p.k->mixed << ",\"fixed_n\":" << p.k->fixed_n << ",\"radices\":[";
     if (p.k->mixed) {  // the stage radices, first stage first
       bool first = true;
       for (uint64_t c = (uint64_t)p.args.twp_mask; c; c >>= 8, first = false)

@@ -212,3 +212,15 @@ def test_lengths_near_the_limits(n):
     err = oracle.rel_l2(y, oracle.dft3d(x.astype(np.complex128), -1, "direct"))
     say("  n", n, "rel_l2", err)
     assert err <= tol_bl(shape), (n, err)
+
+
+@pytest.mark.parametrize("n", [96, 100, 120, 125, 200, 250, 384, 500, 768, 1000, 1536, 2000])
+def test_fixed_length_kernels(n):
+    """The lengths with a kernel compiled for them, on the innermost and the
+    outermost axis, forward and inverse, against direct sums."""
+    for shape in ((2, 3, n), (n, 3, 2)):
+        x = inputs.uniform_c64(shape, 3000 + n)
+        for sign, inv in ((-1, False), (1, True)):
+            y = gpu_fftn(x, inv)
+            err = oracle.rel_l2(y, oracle.dft3d(x.astype(np.complex128), sign, "direct"))
+            assert err <= tol_bl(shape), (shape, sign, err)

@@ -490,3 +490,19 @@ def test_mixed_kernel_runs_its_radices(tile):
         if r & {11, 13}:
             assert p["mixed"] == 2, (n, tile)
         assert p["n"] > n
+
+
+FIXED_LENGTHS = [96, 100, 120, 125, 200, 250, 384, 500, 768, 1000, 1536, 2000]
+
+
+@pytest.mark.parametrize("n", FIXED_LENGTHS)
+def test_fixed_length_kernels_are_picked(n):
+    """Each length with a kernel compiled for it gets that kernel (its radix
+    code matches the planner's packing), on every axis; the tile option
+    falls back to the generic kernels."""
+    d = dft3d.describe((n, n, n) if n <= 128 else (n, 4, 2), "pencil")
+    picked = [p for p in d["passes"] if p.get("bl_n", 0) == 0 and p["mixed"]
+              and pass_points(p) == n]
+    assert picked and all(p["fixed_n"] == n for p in picked)
+    p = dft3d.describe((1, 1, n), "pencil", tile=16)["passes"][0]
+    assert p["fixed_n"] == 0
