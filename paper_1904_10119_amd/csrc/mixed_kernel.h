@@ -182,8 +182,6 @@ __device__ __forceinline__ void mixed_stage(float2* pen, int n, int ns,
 // the pencil's points t + r n / R (consecutive t on consecutive lanes),
 // all of the thread's loads in flight before the transforms, and writes
 // its outputs to t R + r in LDS; no twiddles.
-template <int R, int V> constexpr int mixed_first_count() { return (V + R - 1) / R; }
-
 template <int R, int V, int K = (V + R - 1) / R>
 __device__ __forceinline__ void mixed_first_load(float2 (&a)[K][R], const float2* s,
                                                  int64_t ijs, int n, int p, int P) {
