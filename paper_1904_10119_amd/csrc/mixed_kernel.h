@@ -219,7 +219,7 @@ __device__ __forceinline__ void mixed_first_compute(float2 (&a)[K][R], int conj,
 template <int R, int V>
 __device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, int conj,
                                                   float2* pen, int n, int p, int P) {
-  float2 a[mixed_first_count<R, V>()][R];
+  float2 a[(V + R - 1) / R][R];
   mixed_first_load<R, V>(a, s, ijs, n, p, P);
   mixed_first_compute<R, V>(a, conj, pen, n, p, P);
 }
