@@ -16,6 +16,7 @@ void register_kernels_plane(std::vector<KernelInfo>& v);
 void register_kernels_fused(std::vector<KernelInfo>& v);
 void register_kernels_bluestein(std::vector<KernelInfo>& v);
 void register_kernels_mixed(std::vector<KernelInfo>& v);
+void register_kernels_mixed_fixed(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -31,6 +32,7 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_fused(v);
     register_kernels_bluestein(v);
     register_kernels_mixed(v);
+    register_kernels_mixed_fixed(v);
     return v;
   }();
   return table;

@@ -214,7 +214,9 @@ def test_lengths_near_the_limits(n):
     assert err <= tol_bl(shape), (n, err)
 
 
-@pytest.mark.parametrize("n", [96, 100, 120, 125, 200, 250, 384, 500, 768, 1000, 1536, 2000])
+@pytest.mark.parametrize("n", [48, 60, 72, 80, 96, 100, 120, 125, 144, 160, 192, 200, 240, 250,
+                               300, 320, 384, 400, 480, 500, 600, 640, 768, 800, 960, 1000,
+                               1200, 1536, 2000])
 def test_fixed_length_kernels(n):
     """The lengths with a kernel compiled for them, on the innermost and the
     outermost axis, forward and inverse, against direct sums."""
