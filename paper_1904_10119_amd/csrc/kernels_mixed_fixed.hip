@@ -34,5 +34,12 @@ void register_kernels_mixed_fixed(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info_mixed_fixed<4, 2048, 512, 1200, 0x40A0A03>());  // 3*10*10*4
   v.push_back(kernel_info_mixed_fixed<4, 2048, 512, 1536, 0x8080803>());  // 3*8*8*8
   v.push_back(kernel_info_mixed_fixed<4, 2048, 512, 2000, 0x20A0A0A>());  // 10*10*10*2
+  v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 2400, 0x804030505>());  // 5*5*3*4*8
+  v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 2500, 0x405050505>());  // 5*5*5*5*4
+  v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 3000, 0x803050505>());  // 5*5*5*3*8
+  v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 3072, 0x808040403>());  // 3*4*4*8*8
+  v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 3200, 0x804040505>());  // 5*5*4*4*8
+  v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 3600, 0x40403030505>());  // 5*5*3*3*4*4
+  v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 4000, 0x804050505>());  // 5*5*5*4*8
 }
 }  // namespace dft3d

@@ -216,7 +216,7 @@ def test_lengths_near_the_limits(n):
 
 @pytest.mark.parametrize("n", [48, 60, 72, 80, 96, 100, 120, 125, 144, 160, 192, 200, 240, 250,
                                300, 320, 384, 400, 480, 500, 600, 640, 768, 800, 960, 1000,
-                               1200, 1536, 2000])
+                               1200, 1536, 2000, 2400, 2500, 3000, 3072, 3200, 3600, 4000])
 def test_fixed_length_kernels(n):
     """The lengths with a kernel compiled for them, on the innermost and the
     outermost axis, forward and inverse, against direct sums."""
