@@ -116,6 +116,16 @@ enum dft3d_option {
                                 of the next in one pass where the split
                                 factors match (a_d = b_{d-1} = 16 or 32:
                                 256^3, 1024^3); default 1 */
+  DFT3D_OPT_PENCIL_GROUP = 10, /* pencil, FP32, powers of two: planes of
+                                axis 0 per group of the first two passes
+                                (rounded down to a power of two), so a
+                                group's intermediate can stay in the
+                                Infinity Cache; 0 = all planes at once
+                                (default), -1 = groups of up to 256 MB for
+                                arrays of 256 MiB or more where the
+                                one-sided streaming kernels exist (length
+                                1024); slower than 0 at 1024^3 as measured,
+                                offered to the autotuner */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

@@ -4,7 +4,7 @@
 // architecture name and the shape, optionally mirrored to a text file
 // (DFT3D_TUNE_CACHE): one line per entry,
 //   arch n0 n1 n2 schedule tile xcd_remap split_max nontemporal persistent
-//   slab_group milliseconds
+//   slab_group pencil_group milliseconds
 // Lines whose architecture differs from the current device are ignored.
 #include <cstdio>
 #include <cstdlib>
@@ -58,10 +58,11 @@ void load_file_locked() {
   if (!f) return;
   char arch[64];
   long long n0, n1, n2;
-  int sched, tile, xcd, split, nt, pers, group;
+  int sched, tile, xcd, split, nt, pers, group, pgroup;
   double ms;
-  while (std::fscanf(f, "%63s %lld %lld %lld %d %d %d %d %d %d %d %lf", arch, &n0, &n1, &n2,
-                     &sched, &tile, &xcd, &split, &nt, &pers, &group, &ms) == 12) {
+  while (std::fscanf(f, "%63s %lld %lld %lld %d %d %d %d %d %d %d %d %lf", arch, &n0, &n1,
+                     &n2, &sched, &tile, &xcd, &split, &nt, &pers, &group, &pgroup,
+                     &ms) == 13) {
     const int64_t n[3] = {n0, n1, n2};
     TuneEntry e;
     e.schedule = sched;
@@ -71,6 +72,7 @@ void load_file_locked() {
     e.opt.nontemporal = nt;
     e.opt.persistent = pers;
     e.opt.slab_group = group;
+    e.opt.pencil_group = pgroup;
     e.ms = ms;
     g_tune[key_of(arch, n)] = e;
   }
@@ -85,9 +87,9 @@ void save_file_locked() {
   if (!f) return;
   for (const auto& kv : g_tune) {
     const TuneEntry& e = kv.second;
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %.6f\n", kv.first.c_str(), e.schedule, e.opt.tile,
-                 e.opt.xcd_remap, e.opt.split_max, e.opt.nontemporal, e.opt.persistent,
-                 e.opt.slab_group, e.ms);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.6f\n", kv.first.c_str(), e.schedule,
+                 e.opt.tile, e.opt.xcd_remap, e.opt.split_max, e.opt.nontemporal,
+                 e.opt.persistent, e.opt.slab_group, e.opt.pencil_group, e.ms);
   }
   std::fclose(f);
   std::rename(tmp.c_str(), path);
@@ -120,6 +122,7 @@ extern "C" int dft3d_autotune(int64_t n0, int64_t n1, int64_t n2, const void* in
   static const Cand cands[] = {
       {DFT3D_SCHED_PENCIL, 0, 0},
       {DFT3D_SCHED_PENCIL, DFT3D_OPT_PERSISTENT, 0},
+      {DFT3D_SCHED_PENCIL, DFT3D_OPT_PENCIL_GROUP, -1},
       {DFT3D_SCHED_PENCIL, DFT3D_OPT_SPLIT_MAX, 1024},
       {DFT3D_SCHED_PENCIL, DFT3D_OPT_SPLIT_MAX, 512},
       {DFT3D_SCHED_PENCIL, DFT3D_OPT_TILE, 8},

@@ -209,6 +209,10 @@ int apply_option(Options& o, int key, int64_t value) {
       if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
       o.fused_axes = (int)value;
       return DFT3D_OK;
+    case DFT3D_OPT_PENCIL_GROUP:
+      if (value < -1 || value > 4096) return DFT3D_ERR_INVALID_ARG;
+      o.pencil_group = (int)value;
+      return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
   }
@@ -381,6 +385,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_SLAB_GROUP: *value = p->opt.slab_group; break;
     case DFT3D_OPT_FUSED_PLANE: *value = p->opt.fused_plane; break;
     case DFT3D_OPT_FUSED_AXES: *value = p->opt.fused_axes; break;
+    case DFT3D_OPT_PENCIL_GROUP: *value = p->opt.pencil_group; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }

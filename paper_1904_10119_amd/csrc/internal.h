@@ -50,7 +50,7 @@ struct KernelInfo {
   int lds_bytes;     // static LDS per workgroup
   LaunchFn launch;
   int persistent;    // 1: grid of resident workgroups walking all tiles
-  int nontemporal;   // 1: streaming (non-temporal) loads and stores
+  int nontemporal;   // streaming accesses: 0 none, 1 loads and stores, 2 loads, 3 stores
   int precision = 0; // DFT3D_PREC_*: FP32 butterflies or split MFMA leaves
   int plane_rows = 0; // > 0: fused 2D DFT of (plane_rows, n) planes, one per workgroup
   int fused_axes = 0; // 1: volumetric V2 of one axis fused with V1 of the next (n = a)
@@ -141,6 +141,7 @@ struct Options {
   int slab_group = -1; // slab: planes per row/column group (0 = all, -1 = auto)
   int fused_plane = 1; // slab: one fused 2D pass for planes that fit in LDS
   int fused_axes = 1;  // volumetric: V2 of an axis and V1 of the next in one pass
+  int pencil_group = 0; // pencil: planes per group of the first two passes (0 = all, -1 = auto)
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

@@ -165,6 +165,12 @@ __device__ __forceinline__ void lds_exchange(float2 (&v)[E], float2* lds, int ti
 // past the end of a ragged last tile read the last pencil instead (always in
 // bounds; their results are never stored), so the loads carry no branch.
 // Inputs are conjugated (inverse transform) later, in transform_store_tile.
+// Streaming (non-temporal) accesses of a pass kernel, by its NT parameter:
+// 0 none, 1 loads and stores, 2 loads only, 3 stores only.  The one-sided
+// forms serve passes whose other side is meant to stay in the caches.
+constexpr bool nt_loads(int nt) { return nt == 1 || nt == 2; }
+constexpr bool nt_stores(int nt) { return nt == 1 || nt == 3; }
+
 template <int N, int T, int E, int P, int LM, int NT>
 __device__ __forceinline__ void load_tile(float2 (&v)[E], const float2* src, const PassArgs& a,
                                           int64_t tile, int q, int p) {
@@ -174,7 +180,7 @@ __device__ __forceinline__ void load_tile(float2 (&v)[E], const float2* src, con
   const int64_t step = LM == MODE_ROW ? P : (int64_t)P * a.ijs;
   s += LM == MODE_ROW ? (int64_t)p : (int64_t)p * a.ijs;
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = load_c64(s + e * step, NT != 0);
+  for (int e = 0; e < E; ++e) v[e] = load_c64(s + e * step, nt_loads(NT));
 }
 
 // Radix stages, LDS exchanges and the store of one tile whose elements are
@@ -217,7 +223,7 @@ __device__ __forceinline__ void transform_store_tile(float2 (&v)[E], float2* dst
       if (a.conj_out) v[e].y = -v[e].y;
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) store_c64(d + e * step, v[e], NT != 0);
+    for (int e = 0; e < E; ++e) store_c64(d + e * step, v[e], nt_stores(NT));
   }
 }
 
@@ -399,6 +405,15 @@ template <int N, int T, class BL = Blocking<N>>
 void add_persistent_kernels(std::vector<KernelInfo>& v) {
   add_persistent_kernels_nt<N, T, 0, BL>(v);
   add_persistent_kernels_nt<N, T, 1, BL>(v);
+}
+
+// Rotate-on-write passes with one streaming side: the first two passes of
+// the grouped pencil schedule, whose intermediate (one group of planes)
+// stays in the Infinity Cache between them.
+template <int N, int T, class BL = Blocking<N>>
+void add_group_kernels(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_COL, 0, 2, BL>());
+  v.push_back(kernel_info_persistent<N, T, MODE_ROW, MODE_COL, 0, 3, BL>());
 }
 
 }  // namespace dft3d

@@ -61,6 +61,9 @@ int default_tile(int n) {
 // Arrays at least this large stream through HBM on every pass; below it the
 // data may stay in the 256 MB Infinity Cache between passes.
 constexpr int64_t kStreamBytes = int64_t(256) << 20;
+// Largest group of planes the grouped pencil schedule keeps in the
+// Infinity Cache between its first two passes.
+constexpr int64_t kGroupBytes = int64_t(256) << 20;
 
 // Kernel choice for one pass.  Measured on MI355X at 1024^3: the persistent
 // prefetching kernels run best with streaming (non-temporal) accesses, the
@@ -127,13 +130,17 @@ struct Builder {
   std::vector<Pass>& passes;
   int64_t total_points;
   int status = DFT3D_OK;
+  int nt_side = 0;  // > 0: prefer the persistent kernel with this one-sided NT form
 
   void add(int n, int lmode, int smode, int tw, const Field* f, int nf, int64_t ijs,
            int64_t oks, int64_t twp_len, int res_shift, int64_t res_mask,
            const std::string& label) {
     const KernelInfo* k = nullptr;
     int leaf = 0;
-    if (opt.precision != DFT3D_PREC_FP32 && !tw) {
+    if (nt_side && opt.precision == DFT3D_PREC_FP32 && !tw)
+      k = find_kernel(n, opt.tile > 0 ? opt.tile : default_tile(n), lmode, smode, 0, 1,
+                      nt_side);
+    if (!k && opt.precision != DFT3D_PREC_FP32 && !tw) {
       // split-precision leaves on the matrix cores where a kernel exists;
       // the persistent form under the same rule as the FP32 kernels (in
       // automatic mode only for arrays that stream through HBM: measured at
@@ -401,6 +408,96 @@ void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
   }
 }
 
+// Grouped pencil schedule: planes of axis 0 taken G at a time through the
+// first two passes, so that a group's intermediate (G n1 n2 points, about
+// 256 MB) is read back by the second pass while it is still in the
+// Infinity Cache; only the input read and the second pass's output write go
+// to HBM.  For each group g (i0 = g G + i, i < G):
+//   A_g: DFT along axis 2 of the (G, n1, n2) block of IN, rotated into the
+//        group's own region of OUT as W[k2][i][i1];
+//   B_g: DFT along axis 1 of W (pencils (i fastest, k2)), written to WS at
+//        the full-array rotated place [k1][k2][g G + i];
+// then one ordinary pencil pass along axis 0 from WS to OUT.  The passes of
+// the two orders compute the same sums (eq. (8)); only the order in which
+// the batches of 1D DFTs run differs.  Returns the group size, 0 if the
+// shape does not take this form.
+int64_t pencil_group_size(const int64_t n[3], const Options& opt, int64_t split_max) {
+  if (opt.pencil_group == 0 || opt.precision != DFT3D_PREC_FP32) return 0;
+  for (int d = 0; d < 3; ++d)
+    if (!is_pow2(n[d])) return 0;
+  if (n[0] < 2 || n[0] > split_max || n[1] > split_max || n[2] > split_max) return 0;
+  const int64_t plane = n[1] * n[2];
+  int64_t g;
+  if (opt.pencil_group > 0) {
+    g = std::min<int64_t>(opt.pencil_group, n[0]);
+  } else {
+    // automatic size: arrays that stream through HBM, groups of at most
+    // 256 MB, and only where the one-sided streaming kernels exist for both
+    // lengths.  Measured at 1024^3 on MI355X: 11.4 ms against 10.3 ms for
+    // the ordinary schedule; a group's launch is eight tiles per workgroup
+    // deep, and the unhidden first load and last store of each launch cost
+    // more than the cache saves, so the option is off by default.
+    if (n[0] * plane * 8 < kStreamBytes || opt.nontemporal != 2 || !opt.persistent) return 0;
+    const int t2 = opt.tile > 0 ? opt.tile : default_tile((int)n[2]);
+    const int t1 = opt.tile > 0 ? opt.tile : default_tile((int)n[1]);
+    if (!find_kernel((int)n[2], t2, MODE_ROW, MODE_COL, 0, 1, 2) ||
+        !find_kernel((int)n[1], t1, MODE_ROW, MODE_COL, 0, 1, 3))
+      return 0;
+    g = kGroupBytes / (plane * 8);
+    if (g < 1) return 0;
+  }
+  int64_t p2 = 1;
+  while (p2 * 2 <= g) p2 *= 2;
+  return p2 < n[0] ? p2 : 0;  // one group is the ordinary schedule
+}
+
+void pencil_grouped(Builder& b, const int64_t n[3], int64_t G) {
+  const int64_t n0 = n[0], n1 = n[1], n2 = n[2];
+  char lab[80];
+  for (int64_t g = 0; g < n0 / G && b.status == DFT3D_OK; ++g) {
+    const int64_t base = g * G * n1 * n2;
+    {  // A_g: pencils b = i n1 + i1 of the block; element k2 -> W[k2 (G n1) + b]
+      Field f[1] = {{G * n1, n2, 1}};
+      std::snprintf(lab, sizeof lab, "pencil2 DFT%lld x%lld rot group %lld", (long long)n2,
+                    (long long)(G * n1), (long long)g);
+      b.nt_side = 2;
+      b.add((int)n2, MODE_ROW, MODE_COL, 0, f, 1, 1, G * n1, 0, 0, 0, lab);
+      if (b.status != DFT3D_OK) break;
+      Pass& p = b.passes.back();
+      p.src = BUF_IN;
+      p.dst = BUF_OUT;
+      p.in_off = base;
+      p.out_off = base;
+      p.chain_src = p.chain_dst = false;
+    }
+    {  // B_g: pencils (i fastest, k2) of W; element k1 -> WS[k1 (n2 n0) + k2 n0 + g G + i]
+      Field f[2] = {{G, n1, 1}, {n2, G * n1, n0}};
+      std::snprintf(lab, sizeof lab, "pencil1 DFT%lld x%lld rot group %lld", (long long)n1,
+                    (long long)(G * n2), (long long)g);
+      b.nt_side = 3;
+      b.add((int)n1, MODE_ROW, MODE_COL, 0, f, 2, 1, n2 * n0, 0, 0, 0, lab);
+      if (b.status != DFT3D_OK) break;
+      Pass& p = b.passes.back();
+      p.src = BUF_OUT;
+      p.dst = BUF_WS;
+      p.in_off = base;
+      p.out_off = g * G;
+      p.chain_src = p.chain_dst = false;
+    }
+  }
+  b.nt_side = 0;
+  if (b.status != DFT3D_OK) return;
+  Field f[1] = {{n1 * n2, n0, 1}};
+  std::snprintf(lab, sizeof lab, "pencil0 DFT%lld x%lld rot", (long long)n0,
+                (long long)(n1 * n2));
+  b.add((int)n0, MODE_ROW, MODE_COL, 0, f, 1, 1, n1 * n2, 0, 0, 0, lab);
+  if (b.status != DFT3D_OK) return;
+  Pass& p = b.passes.back();
+  p.src = BUF_WS;
+  p.dst = BUF_OUT;
+  p.chain_src = p.chain_dst = false;
+}
+
 // Buffers for a chain of passes from IN to OUT that never writes IN and
 // never reads and writes the same buffer in one (not in-place-safe) pass.
 void assign_chain(std::vector<Pass>& passes, size_t first, size_t& ws_needed_flag) {
@@ -459,7 +556,13 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
                         : (schedule == DFT3D_SCHED_AUTO ? 2048 : int64_t(1) << 20);
 
   size_t need_ws = 0;
-  if (resolved == DFT3D_SCHED_PENCIL) {
+  const int64_t group = resolved == DFT3D_SCHED_PENCIL && !shuffled
+                            ? pencil_group_size(n, opt, split_max)
+                            : 0;
+  if (group > 0) {
+    pencil_grouped(b, n, group);
+    need_ws = 1;
+  } else if (resolved == DFT3D_SCHED_PENCIL) {
     int64_t cur[3] = {n[0], n[1], n[2]};
     for (int step = 0; step < 3; ++step) {
       const int axis = 2 - step;

@@ -92,9 +92,16 @@ def check_chain(d, shape):
     n = shape[0] * shape[1] * shape[2]
     assert passes[0]["src"] == "in"
     assert passes[-1]["dst"] == "out"
+    grouped = [p for p in passes if " group " in p["label"]]
+    for axis in ("pencil2", "pencil1"):
+        # grouped pencil passes: one block of planes each, together every point
+        ps = [p for p in grouped if p["label"].startswith(axis)]
+        assert not grouped or sum(p["pencils"] * p["n"] for p in ps) == n
     for i, p in enumerate(passes):
         assert p["dst"] != "in"
-        if i:
+        if i and " group " in p["label"] and p["label"].startswith("pencil2"):
+            assert p["src"] == "in"      # each group starts from the input
+        elif i:
             assert p["src"] == passes[i - 1]["dst"]
         if p["src"] == p["dst"]:
             # only layout-preserving passes may run in place
@@ -104,7 +111,7 @@ def check_chain(d, shape):
         # fused two-axis volumetric pass n x n x tile points per workgroup
         if p["fused_axes"]:
             assert p["pencils"] * p["n"] * p["n"] * p["tile"] == n
-        else:
+        elif " group " not in p["label"]:
             assert p["pencils"] * p["n"] * max(1, p["plane_rows"]) == n
     uses_ws = any("ws" in (p["src"], p["dst"]) for p in passes)
     assert d["workspace_bytes"] == (8 * n if uses_ws else 0)

@@ -202,7 +202,9 @@ def test_pass_list_computes_the_dft(shape, schedule):
 
 OPTION_SETS = [dict(slab_group=1), dict(slab_group=2), dict(fused_plane=0), dict(tile=8), dict(tile=64),
                dict(split_max=4), dict(persistent=0), dict(nontemporal=1),
-               dict(xcd_remap=0), dict(precision="bf16x6"), dict(precision="fp16x3")]
+               dict(xcd_remap=0), dict(precision="bf16x6"), dict(precision="fp16x3"),
+               dict(pencil_group=1), dict(pencil_group=2), dict(pencil_group=4),
+               dict(pencil_group=3), dict(pencil_group=2, tile=8)]
 
 
 @pytest.mark.parametrize("opts", OPTION_SETS)
@@ -508,3 +510,44 @@ def test_fixed_length_kernels_are_picked(n):
     assert picked and all(p["fixed_n"] == n for p in picked)
     p = dft3d.describe((1, 1, n), "pencil", tile=16)["passes"][0]
     assert p["fixed_n"] == 0
+
+
+@pytest.mark.parametrize("shape,groups", [((1024, 1024, 1024), 32), ((64, 1024, 1024), 2),
+                                          ((2048, 512, 512), 0), ((512, 512, 512), 0),
+                                          ((128, 1024, 1024), 4), ((4096, 256, 256), 0)])
+def test_grouped_pencil_plan(shape, groups):
+    """Automatic group size for the pencil schedule's first two passes:
+    groups of planes of at most 256 MB where both one-sided streaming
+    kernels exist, the group's intermediate in OUT, the rotated second pass
+    into WS at the group's columns, one pass along axis 0; every pass in
+    bounds (sampled at full size).  Off unless asked for."""
+    assert not any(" group " in p["label"] for p in dft3d.describe(shape, "auto")["passes"])
+    d = dft3d.describe(shape, "auto", pencil_group=-1)
+    ps = d["passes"]
+    if not groups:
+        assert not any("group" in p["label"] for p in ps)
+        return
+    n0, n1, n2 = shape
+    G = n0 // groups
+    assert len(ps) == 2 * groups + 1 and G * n1 * n2 * 8 <= (256 << 20)
+    for g in range(groups):
+        a, b = ps[2 * g], ps[2 * g + 1]
+        assert (a["src"], a["dst"], a["nontemporal"]) == ("in", "out", 2)
+        assert (b["src"], b["dst"], b["nontemporal"]) == ("out", "ws", 3)
+        assert a["in_off"] == a["out_off"] == b["in_off"] == g * G * n1 * n2
+        assert b["out_off"] == g * G
+    assert (ps[-1]["src"], ps[-1]["dst"], ps[-1]["n"]) == ("ws", "out", n0)
+    check_pass_maps(d, n0 * n1 * n2)
+
+
+@pytest.mark.parametrize("shape", [(8, 16, 32), (4, 4, 4), (16, 2, 8), (2, 64, 1), (32, 8, 128)])
+@pytest.mark.parametrize("group", [1, 2, 8])
+def test_grouped_pencil_computes_the_dft(shape, group):
+    g = np.random.default_rng(sum(shape) + group)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    d = dft3d.describe(shape, "pencil", pencil_group=group)
+    if group < shape[0]:
+        assert any("group" in p["label"] for p in d["passes"])
+    check_pass_maps(d, x.size)
+    for sign in (-1, 1):
+        assert oracle.rel_l2(run_model(x, d, sign), oracle.dft3d(x, sign, "fft")) < 1e-13
