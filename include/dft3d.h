@@ -211,8 +211,9 @@ int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
                           void* const* out, int count, int sign, void* stream);
 
 /* Autotuner: time candidate schedules and kernel options (pencil with and
- * without the persistent kernels, split long axes, other tiles; slab;
- * volumetric) for a (n0, n1, n2) transform on the current device, on `in`
+ * without the persistent kernels, split long axes, other tiles, grouped
+ * first passes; slab; volumetric) for a (n0, n1, n2) transform on the
+ * current device, on `in`
  * and `out` (device buffers of n0 n1 n2 complex64; out is overwritten), in
  * stream order on `stream`, and record the fastest: DFT3D_SCHED_AUTO plans
  * of that shape created afterwards use it (their precision is kept).  The
