@@ -294,6 +294,36 @@ def test_grouped_pencil_one_sided_kernels_bitwise():
         assert abs(y[k] - ref) <= 1e-5 * np.sqrt(np.sum(np.abs(xs) ** 2)), k
 
 
+def test_grouped_pencil_plans_in_a_batch():
+    """Plans with grouped first passes in one batched call, next to an
+    ordinary plan: every result equals its single execution bit for bit,
+    forward and inverse."""
+    import ctypes
+    shapes = [(16, 32, 64), (32, 64, 16), (8, 8, 8)]
+    groups = [4, 8, 0]
+    plans = [dft3d.Plan(s, "pencil", pencil_group=g) for s, g in zip(shapes, groups)]
+    xs = [torch.from_numpy(inputs.uniform_c64(s, 70 + i)).cuda() for i, s in enumerate(shapes)]
+    for p, x in zip(plans, xs):
+        p.bind_workspace(x.device)
+    assert sum(" group " in q["label"] for q in dft3d.describe(shapes[0], "pencil",
+                                                                pencil_group=4)["passes"]) == 8
+    arr = ctypes.c_void_p * len(plans)
+    for inverse in (False, True):
+        outs = [torch.empty_like(x) for x in xs]
+        st = dft3d.lib().dft3d_execute_batched(
+            arr(*[p.handle.value for p in plans]), arr(*[x.data_ptr() for x in xs]),
+            arr(*[o.data_ptr() for o in outs]), len(plans), 1 if inverse else -1,
+            torch.cuda.current_stream().cuda_stream)
+        assert st == 0
+        for p, x, o in zip(plans, xs, outs):
+            single = torch.empty_like(x)
+            p.execute(x, single, inverse=inverse)
+            torch.cuda.synchronize()
+            assert torch.equal(o, single), (x.shape, inverse)
+    for p in plans:
+        p.close()
+
+
 def test_autotune_records_choice_for_auto_plans(tmp_path, monkeypatch):
     """The autotuner times the candidates, records the fastest, and later
     auto plans of that shape use it (and still match the oracle); the
