@@ -56,6 +56,15 @@ __device__ __forceinline__ void bluestein_fft(float2 (&v)[E], float2* lds,
   }
 }
 
+// Whether the roots of length M go to LDS beside a tile of T pencils: where
+// they fit without lowering the number of workgroups a CU holds.
+template <int M, int T, class BL>
+constexpr bool bluestein_roots_in_lds() {
+  constexpr int kLds = 160 * 1024, tile = T * lds_pencil_stride<M, T>() * 8;
+  return num_stages<BL>() > 1 && tile + M * 8 <= kLds &&
+         kLds / (tile + M * 8) == kLds / tile;
+}
+
 // BL: register blocking of the length-m FFTs (E elements per thread).
 template <int M, int T, class BL>
 __global__ void __launch_bounds__(T*(M / BL::E))
@@ -66,12 +75,27 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
   constexpr int NST = num_stages<BL>();
   constexpr int SQ = lds_pencil_stride<M, T>();
   constexpr int LDS_ELEMS = NST > 1 ? T * SQ : 1;
-  __shared__ float2 lds[LDS_ELEMS];
+  constexpr bool TWL = bluestein_roots_in_lds<M, T, BL>();
+  __shared__ float2 lds[LDS_ELEMS + (TWL ? M : 0)];
   const int64_t n = a.res_mask;
   const float2* __restrict__ chirp = twp;
   const float2* __restrict__ filt = twp + n;
 
   const int tid = threadIdx.x;
+  // The roots of length m go to LDS next to the tile where they fit: the
+  // later radix stages of both FFTs read them, and from global memory each
+  // of those stages waited on its own loads.  The first stage reads none,
+  // and the first exchange's barrier orders these writes before any read.
+  const float2* twv = tw;
+  if constexpr (TWL) {
+    float2* lt = lds + LDS_ELEMS;
+#pragma unroll
+    for (int i = 0; i < (M + T * P - 1) / (T * P); ++i) {
+      const int j = tid + T * P * i;
+      if (j < M) lt[j] = tw[j];
+    }
+    twv = lt;
+  }
   const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
   int q, p;
   thread_map<MODE_ROW, T, P>(tid, q, p);
@@ -92,11 +116,11 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
       }
       v[e] = x;
     }
-    bluestein_fft<M, BL, T, SQ, MODE_ROW, E, P>(v, lds, tw, tid, q, p);
+    bluestein_fft<M, BL, T, SQ, MODE_ROW, E, P>(v, lds, twv, tid, q, p);
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cmul(v[e], filt[p + P * e]);
     if constexpr (NST > 1) __syncthreads();  // the first FFT's exchanges are read
-    bluestein_fft<M, BL, T, SQ, MODE_COL, E, P>(v, lds, tw, tid, q, p);
+    bluestein_fft<M, BL, T, SQ, MODE_COL, E, P>(v, lds, twv, tid, q, p);
     const int64_t bo = tile * T + q;
     if (bo < a.B) {
       float2* d = dst + pencil_offset(bo, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
@@ -131,7 +155,8 @@ KernelInfo kernel_info_bluestein() {
   using BL = Blocking<M>;
   constexpr int E = BL::E;
   constexpr int SQ = lds_pencil_stride<M, T>();
-  constexpr int LDS = num_stages<BL>() > 1 ? T * SQ * 8 : 8;
+  constexpr int LDS = (num_stages<BL>() > 1 ? T * SQ : 1) * 8 +
+                      (bluestein_roots_in_lds<M, T, BL>() ? M * 8 : 0);
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(T * (M / E) <= 1024, "workgroup too large");
   KernelInfo k{M, T, MODE_ROW, MODE_COL, 0, T * (M / E), LDS,
