@@ -34,35 +34,79 @@ template <> struct Blocking<8192> {
   static constexpr int E = 32, R0 = 32, R1 = 16, R2 = 16;
 };
 
-// One FFT of length M over the tile held in v (thread (q, p) has elements
-// p + P e), ending in LAST_MODE; on return v[e] is output p + P e of
-// pencil q under that mapping.  The caller makes sure no thread still reads
-// lds when this starts.
-template <int M, class BL, int T, int SQ, int LAST_MODE, int E, int P>
-__device__ __forceinline__ void bluestein_fft(float2 (&v)[E], float2* lds,
-                                              const float2* __restrict__ tw, int tid, int& q,
-                                              int& p) {
+// Stage twiddles laid out per stage for LDS: for each twiddled radix stage
+// (ns, R) of the blocking, in order, entry (r - 1) ns + tm holds
+// w_M^{tm r M / (ns R)} (r = 1 .. R-1, tm < ns), so the lanes of a wave, whose
+// tm are consecutive, read consecutive entries.  M - R0 entries in all.
+template <int M, class BL> constexpr int stage_table_size() {
   constexpr int NST = num_stages<BL>();
-  radix_stage<M, E, P, 1, BL::R0>(v, p, tw);
-  if constexpr (NST == 2) {
-    lds_exchange<M, E, P, T, SQ, 1, BL::R0, LAST_MODE>(v, lds, tid, q, p);
-    radix_stage<M, E, P, BL::R0, BL::R1>(v, p, tw);
-  } else if constexpr (NST == 3) {
-    lds_exchange<M, E, P, T, SQ, 1, BL::R0, MODE_ROW>(v, lds, tid, q, p);
-    radix_stage<M, E, P, BL::R0, BL::R1>(v, p, tw);
-    __syncthreads();  // every read of the first exchange is done
-    lds_exchange<M, E, P, T, SQ, BL::R0, BL::R1, LAST_MODE>(v, lds, tid, q, p);
-    radix_stage<M, E, P, BL::R0 * BL::R1, BL::R2>(v, p, tw);
+  return NST == 1 ? 0 : (NST == 2 ? (BL::R1 - 1) * BL::R0
+                                  : (BL::R1 - 1) * BL::R0 + (BL::R2 - 1) * BL::R0 * BL::R1);
+}
+
+// Index into the roots of length M of stage-table entry j.
+template <int M, class BL>
+__device__ __forceinline__ int stage_table_root(int j) {
+  constexpr int R0 = BL::R0, R1 = BL::R1, R2 = BL::R2, S1 = (R1 - 1) * R0;
+  if (j < S1) return (j % R0) * (j / R0 + 1) * (M / (R0 * R1));
+  j -= S1;
+  return (j % (R0 * R1)) * (j / (R0 * R1) + 1) * (M / (R0 * R1 * R2));
+}
+
+// Radix-R stage after ns with its twiddles from a stage table (entry
+// (r - 1) ns + tm); otherwise as radix_stage.
+template <int N, int E, int P, int NS, int R>
+__device__ __forceinline__ void radix_stage_staged(float2 (&v)[E], int p, const float2* st) {
+  constexpr int U = E / R;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    float2 a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[u + r * U];
+    const int tm = (p + P * u) & (NS - 1);
+#pragma unroll
+    for (int r = 1; r < R; ++r) a[r] = cmul(a[r], st[(r - 1) * NS + tm]);
+    dft<R>(a);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[u + r * U] = a[r];
   }
 }
 
-// Whether the roots of length M go to LDS beside a tile of T pencils: where
-// they fit without lowering the number of workgroups a CU holds.
+// One FFT of length M over the tile held in v (thread (q, p) has elements
+// p + P e), ending in LAST_MODE; on return v[e] is output p + P e of
+// pencil q under that mapping.  The caller makes sure no thread still reads
+// lds when this starts.  Twiddles from the stage table st when STAGED, else
+// from the roots tw.
+template <int M, class BL, int T, int SQ, int LAST_MODE, int E, int P, bool STAGED>
+__device__ __forceinline__ void bluestein_fft(float2 (&v)[E], float2* lds,
+                                              const float2* __restrict__ tw,
+                                              const float2* st, int tid, int& q, int& p) {
+  constexpr int NST = num_stages<BL>();
+  constexpr int R0 = BL::R0, R1 = BL::R1, R2 = BL::R2;
+  radix_stage<M, E, P, 1, R0>(v, p, tw);  // no twiddles
+  if constexpr (NST == 2) {
+    lds_exchange<M, E, P, T, SQ, 1, R0, LAST_MODE>(v, lds, tid, q, p);
+    if constexpr (STAGED) radix_stage_staged<M, E, P, R0, R1>(v, p, st);
+    else radix_stage<M, E, P, R0, R1>(v, p, tw);
+  } else if constexpr (NST == 3) {
+    lds_exchange<M, E, P, T, SQ, 1, R0, MODE_ROW>(v, lds, tid, q, p);
+    if constexpr (STAGED) radix_stage_staged<M, E, P, R0, R1>(v, p, st);
+    else radix_stage<M, E, P, R0, R1>(v, p, tw);
+    __syncthreads();  // every read of the first exchange is done
+    lds_exchange<M, E, P, T, SQ, R0, R1, LAST_MODE>(v, lds, tid, q, p);
+    if constexpr (STAGED) radix_stage_staged<M, E, P, R0 * R1, R2>(v, p, st + (R1 - 1) * R0);
+    else radix_stage<M, E, P, R0 * R1, R2>(v, p, tw);
+  }
+}
+
+// Whether the stage table goes to LDS beside a tile of T pencils: where it
+// fits without lowering the number of workgroups a CU holds.
 template <int M, int T, class BL>
-constexpr bool bluestein_roots_in_lds() {
+constexpr bool bluestein_table_in_lds() {
   constexpr int kLds = 160 * 1024, tile = T * lds_pencil_stride<M, T>() * 8;
-  return num_stages<BL>() > 1 && tile + M * 8 <= kLds &&
-         kLds / (tile + M * 8) == kLds / tile;
+  constexpr int table = stage_table_size<M, BL>() * 8;
+  return num_stages<BL>() > 1 && tile + table <= kLds &&
+         kLds / (tile + table) == kLds / tile;
 }
 
 // BL: register blocking of the length-m FFTs (E elements per thread).
@@ -75,26 +119,25 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
   constexpr int NST = num_stages<BL>();
   constexpr int SQ = lds_pencil_stride<M, T>();
   constexpr int LDS_ELEMS = NST > 1 ? T * SQ : 1;
-  constexpr bool TWL = bluestein_roots_in_lds<M, T, BL>();
-  __shared__ float2 lds[LDS_ELEMS + (TWL ? M : 0)];
+  constexpr bool TWL = bluestein_table_in_lds<M, T, BL>();
+  constexpr int ST = TWL ? stage_table_size<M, BL>() : 0;
+  __shared__ float2 lds[LDS_ELEMS + ST];
   const int64_t n = a.res_mask;
   const float2* __restrict__ chirp = twp;
   const float2* __restrict__ filt = twp + n;
 
   const int tid = threadIdx.x;
-  // The roots of length m go to LDS next to the tile where they fit: the
-  // later radix stages of both FFTs read them, and from global memory each
-  // of those stages waited on its own loads.  The first stage reads none,
-  // and the first exchange's barrier orders these writes before any read.
-  const float2* twv = tw;
+  // The stage twiddles go to LDS next to the tile where they fit: the later
+  // radix stages of both FFTs read them, and from global memory each of
+  // those stages waited on its own loads.  The first stage reads none, and
+  // the first exchange's barrier orders these writes before any read.
+  float2* st = lds + LDS_ELEMS;
   if constexpr (TWL) {
-    float2* lt = lds + LDS_ELEMS;
 #pragma unroll
-    for (int i = 0; i < (M + T * P - 1) / (T * P); ++i) {
+    for (int i = 0; i < (ST + T * P - 1) / (T * P); ++i) {
       const int j = tid + T * P * i;
-      if (j < M) lt[j] = tw[j];
+      if (j < ST) st[j] = tw[stage_table_root<M, BL>(j)];
     }
-    twv = lt;
   }
   const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
   int q, p;
@@ -116,11 +159,11 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
       }
       v[e] = x;
     }
-    bluestein_fft<M, BL, T, SQ, MODE_ROW, E, P>(v, lds, twv, tid, q, p);
+    bluestein_fft<M, BL, T, SQ, MODE_ROW, E, P, TWL>(v, lds, tw, st, tid, q, p);
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cmul(v[e], filt[p + P * e]);
     if constexpr (NST > 1) __syncthreads();  // the first FFT's exchanges are read
-    bluestein_fft<M, BL, T, SQ, MODE_COL, E, P>(v, lds, twv, tid, q, p);
+    bluestein_fft<M, BL, T, SQ, MODE_COL, E, P, TWL>(v, lds, tw, st, tid, q, p);
     const int64_t bo = tile * T + q;
     if (bo < a.B) {
       float2* d = dst + pencil_offset(bo, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
@@ -156,7 +199,7 @@ KernelInfo kernel_info_bluestein() {
   constexpr int E = BL::E;
   constexpr int SQ = lds_pencil_stride<M, T>();
   constexpr int LDS = (num_stages<BL>() > 1 ? T * SQ : 1) * 8 +
-                      (bluestein_roots_in_lds<M, T, BL>() ? M * 8 : 0);
+                      (bluestein_table_in_lds<M, T, BL>() ? stage_table_size<M, BL>() * 8 : 0);
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(T * (M / E) <= 1024, "workgroup too large");
   KernelInfo k{M, T, MODE_ROW, MODE_COL, 0, T * (M / E), LDS,
