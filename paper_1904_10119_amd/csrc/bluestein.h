@@ -99,14 +99,29 @@ __device__ __forceinline__ void bluestein_fft(float2 (&v)[E], float2* lds,
   }
 }
 
-// Whether the stage table goes to LDS beside a tile of T pencils: where it
-// fits without lowering the number of workgroups a CU holds.
+// Whether `entries` more float2 fit in LDS beside a tile of T pencils
+// without lowering the number of workgroups a CU holds.
+template <int M, int T, class BL>
+constexpr bool bluestein_lds_fits(int entries) {
+  constexpr int kLds = 160 * 1024, tile = T * lds_pencil_stride<M, T>() * 8;
+  return num_stages<BL>() > 1 && tile + entries * 8 <= kLds &&
+         kLds / (tile + entries * 8) == kLds / tile;
+}
+// The stage table goes to LDS where it fits; the chirp (n <= M / 2 entries,
+// read again by the store) as well where both fit.
 template <int M, int T, class BL>
 constexpr bool bluestein_table_in_lds() {
-  constexpr int kLds = 160 * 1024, tile = T * lds_pencil_stride<M, T>() * 8;
-  constexpr int table = stage_table_size<M, BL>() * 8;
-  return num_stages<BL>() > 1 && tile + table <= kLds &&
-         kLds / (tile + table) == kLds / tile;
+  return bluestein_lds_fits<M, T, BL>(stage_table_size<M, BL>());
+}
+template <int M, int T, class BL>
+constexpr bool bluestein_chirp_in_lds() {
+  return bluestein_lds_fits<M, T, BL>(stage_table_size<M, BL>() + M / 2);
+}
+template <int M, int T, class BL>
+constexpr int bluestein_lds_tables() {
+  return bluestein_chirp_in_lds<M, T, BL>()
+             ? stage_table_size<M, BL>() + M / 2
+             : (bluestein_table_in_lds<M, T, BL>() ? stage_table_size<M, BL>() : 0);
 }
 
 // BL: register blocking of the length-m FFTs (E elements per thread).
@@ -120,8 +135,9 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
   constexpr int SQ = lds_pencil_stride<M, T>();
   constexpr int LDS_ELEMS = NST > 1 ? T * SQ : 1;
   constexpr bool TWL = bluestein_table_in_lds<M, T, BL>();
+  constexpr bool CHL = bluestein_chirp_in_lds<M, T, BL>();
   constexpr int ST = TWL ? stage_table_size<M, BL>() : 0;
-  __shared__ float2 lds[LDS_ELEMS + ST];
+  __shared__ float2 lds[LDS_ELEMS + bluestein_lds_tables<M, T, BL>()];
   const int64_t n = a.res_mask;
   const float2* __restrict__ chirp = twp;
   const float2* __restrict__ filt = twp + n;
@@ -137,6 +153,16 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
     for (int i = 0; i < (ST + T * P - 1) / (T * P); ++i) {
       const int j = tid + T * P * i;
       if (j < ST) st[j] = tw[stage_table_root<M, BL>(j)];
+    }
+  }
+  // the chirp after it, for the store (the input multiply reads it from
+  // global memory together with the input, before any barrier)
+  float2* lchirp = st + ST;
+  if constexpr (CHL) {
+#pragma unroll
+    for (int i = 0; i < (M / 2 + T * P - 1) / (T * P); ++i) {
+      const int j = tid + T * P * i;
+      if (j < n) lchirp[j] = chirp[j];
     }
   }
   const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
@@ -171,7 +197,7 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
       for (int e = 0; e < E; ++e) {
         const int k = (M - (p + P * e)) & (M - 1);
         if (k < n) {
-          float2 y = cmul(v[e], chirp[k]);
+          float2 y = cmul(v[e], CHL ? lchirp[k] : chirp[k]);
           if (a.conj_out) y.y = -y.y;
           d[k * a.oks] = y;
         }
@@ -199,7 +225,7 @@ KernelInfo kernel_info_bluestein() {
   constexpr int E = BL::E;
   constexpr int SQ = lds_pencil_stride<M, T>();
   constexpr int LDS = (num_stages<BL>() > 1 ? T * SQ : 1) * 8 +
-                      (bluestein_table_in_lds<M, T, BL>() ? stage_table_size<M, BL>() * 8 : 0);
+                      bluestein_lds_tables<M, T, BL>() * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(T * (M / E) <= 1024, "workgroup too large");
   KernelInfo k{M, T, MODE_ROW, MODE_COL, 0, T * (M / E), LDS,
