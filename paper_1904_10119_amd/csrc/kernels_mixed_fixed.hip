@@ -41,5 +41,17 @@ void register_kernels_mixed_fixed(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 3200, 0x804040505>());  // 5*5*4*4*8
   v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 3600, 0x40403030505>());  // 5*5*3*3*4*4
   v.push_back(kernel_info_mixed_fixed<2, 4096, 512, 4000, 0x804050505>());  // 5*5*5*4*8
+  v.push_back(kernel_info_mixed_fixed<64, 128, 512, 56, 0x807>());  // 7*8
+  v.push_back(kernel_info_mixed_fixed<64, 128, 512, 112, 0x1007>());  // 7*16
+  v.push_back(kernel_info_mixed_fixed<16, 512, 512, 168, 0x80307>());  // 7*3*8
+  v.push_back(kernel_info_mixed_fixed<16, 512, 512, 224, 0x80407>());  // 7*4*8
+  v.push_back(kernel_info_mixed_fixed<16, 512, 512, 336, 0x100307>());  // 7*3*16
+  v.push_back(kernel_info_mixed_fixed<16, 512, 512, 448, 0x80807>());  // 7*8*8
+  v.push_back(kernel_info_mixed_fixed<8, 1024, 512, 672, 0x8040307>());  // 7*3*4*8
+  v.push_back(kernel_info_mixed_fixed<8, 1024, 512, 896, 0x100807>());  // 7*8*16
+  v.push_back(kernel_info_mixed_fixed<8, 1024, 512, 1008, 0x10030307>());  // 7*3*3*16
+  v.push_back(kernel_info_mixed_fixed<4, 2048, 512, 1344, 0x8080307>());  // 7*3*8*8
+  v.push_back(kernel_info_mixed_fixed<4, 2048, 512, 1792, 0x101007>());  // 7*16*16
+  v.push_back(kernel_info_mixed_fixed<4, 2048, 512, 2016, 0x804030307>());  // 7*3*3*4*8
 }
 }  // namespace dft3d

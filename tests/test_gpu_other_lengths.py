@@ -216,7 +216,8 @@ def test_lengths_near_the_limits(n):
 
 @pytest.mark.parametrize("n", [48, 60, 72, 80, 96, 100, 120, 125, 144, 160, 192, 200, 240, 250,
                                300, 320, 384, 400, 480, 500, 600, 640, 768, 800, 960, 1000,
-                               1200, 1536, 2000, 2400, 2500, 3000, 3072, 3200, 3600, 4000])
+                               1200, 1536, 2000, 2400, 2500, 3000, 3072, 3200, 3600, 4000,
+                               56, 112, 168, 224, 336, 448, 672, 896, 1008, 1344, 1792, 2016])
 def test_fixed_length_kernels(n):
     """The lengths with a kernel compiled for them, on the innermost and the
     outermost axis, forward and inverse, against direct sums."""

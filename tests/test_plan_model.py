@@ -496,7 +496,8 @@ def test_mixed_kernel_runs_its_radices(tile):
 
 FIXED_LENGTHS = [48, 60, 72, 80, 96, 100, 120, 125, 144, 160, 192, 200, 240, 250, 300, 320,
                  384, 400, 480, 500, 600, 640, 768, 800, 960, 1000, 1200, 1536, 2000,
-                 2400, 2500, 3000, 3072, 3200, 3600, 4000]
+                 2400, 2500, 3000, 3072, 3200, 3600, 4000,
+                 56, 112, 168, 224, 336, 448, 672, 896, 1008, 1344, 1792, 2016]
 
 
 @pytest.mark.parametrize("n", FIXED_LENGTHS)
