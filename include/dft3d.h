@@ -126,6 +126,13 @@ enum dft3d_option {
                                 one-sided streaming kernels exist (length
                                 1024); slower than 0 at 1024^3 as measured,
                                 offered to the autotuner */
+  DFT3D_OPT_BATCH_LAUNCH = 11, /* batched calls (Section 4's point that no
+                                one decomposition suits every shape, served
+                                by one pool of workers): 0 = one launch per
+                                pass level (default); 1 = one persistent
+                                launch for the whole batch, replayed from a
+                                HIP graph the library builds, used when every
+                                plan of the batch has 1 */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 
@@ -209,6 +216,18 @@ int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
  * invalidates graphs that captured it. */
 int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
                           void* const* out, int count, int sign, void* stream);
+
+/* Describe, without touching any device, how dft3d_execute_batched lays out
+ * `count` problems of shapes shapes[3i .. 3i+2] planned with `schedule`
+ * (NATURAL layout, default options) when `launch` is the
+ * DFT3D_OPT_BATCH_LAUNCH value of every plan: a NUL-terminated JSON text with
+ * the work items in level-major order (problem, pass, first tile, tiles,
+ * the item it waits for, transform length, plane rows, pencils, pencils per
+ * tile), the per-level launches, the ticket total and the workgroup shape.
+ * Written into buf (at most len bytes, truncated if needed); the full length
+ * goes to *needed (may be NULL).  Same argument validation as dft3d_plan. */
+int dft3d_batch_describe(const int64_t* shapes, int count, int schedule, int launch,
+                         char* buf, size_t len, size_t* needed);
 
 /* Autotuner: time candidate schedules and kernel options (pencil with and
  * without the persistent kernels, split long axes, other tiles, grouped

@@ -1,18 +1,25 @@
-// Batched form: many 3D DFTs of different shapes in a few launches.
+// Batched form: many 3D DFTs of different shapes in a few launches, or in
+// one.
 //
 // Every (problem, pass) of a batch becomes a work item; the tiles of all
-// items of one pass level are laid out consecutively, and one launch of
-// batch_level_kernel runs a whole level (one workgroup per tile, the tile's
-// item found by binary search).  Fused plane passes (slab) are items of
-// their own kind, one workgroup per plane, run by batch_plane_level_kernel
-// in a launch of their own for the level.  The kernel boundary between levels orders
-// each pass of a problem after the previous one, so there are no waits
-// between workgroups: three launches run 96 pencil-schedule problems.
+// items of one pass level are laid out consecutively (level-major order).
 //
-// batch_persistent_kernel (one launch for all levels, tiles taken from an
-// atomic queue with per-item completion counters) is kept for study but is
-// not used: on MI355X its first runs did not complete (see the design
-// notes), and it stays switched off until the cause is shown.
+// Level launches: one launch of batch_level_kernel runs a whole level (one
+// workgroup per tile, the tile's item found by binary search).  Fused plane
+// passes (slab) are items of their own kind, one workgroup per plane, run by
+// batch_plane_level_kernel in a launch of their own for the level.  The
+// kernel boundary between levels orders each pass of a problem after the
+// previous one.
+//
+// One persistent launch: batch_persistent_kernel runs every level.  Resident
+// workgroups take tickets (tile numbers in level-major order) from a device
+// counter; before a tile of pass k of a problem runs, the workgroup waits
+// until every tile of pass k - 1 of that problem has been counted done.
+// Those tiles have smaller tickets, so the holder of the smallest unfinished
+// ticket never waits and the launch always drains, whatever number of
+// workgroups is resident.  Waits are bounded (a poll limit, after which the
+// workgroup flags an error and goes on), so a broken descriptor table cannot
+// hang the device.
 #pragma once
 
 #include "pass_kernel.h"
@@ -49,10 +56,15 @@ __host__ __device__ constexpr bool batch_plane_shape(int n1, int n2) {
   return (n1 == 32 || n1 == 64 || n1 == 128) && (n2 == 32 || n2 == 64 || n2 == 128);
 }
 
-struct BatchState {  // zeroed before every launch
+// Counters of the persistent launch.  Zero before the first launch (the
+// host clears them once); the last workgroup to leave a launch zeroes head,
+// exited and every done[] counter again, so launches and graph replays need
+// no reset in between.  error is sticky (cleared by the host when it reads
+// it).
+struct BatchState {
   unsigned long long head;  // next ticket
+  unsigned int exited;      // workgroups that have left the ticket loop
   unsigned int error;       // set when a bounded wait runs out
-  unsigned int pad;
 };
 
 // LDS bytes of the largest tile the batched kernel runs.
@@ -176,80 +188,148 @@ batch_plane_level_kernel(const BatchItem* __restrict__ items, int item_lo, int i
 #undef DFT3D_PLANE_CASE
 }
 
-__global__ void __launch_bounds__(kBatchThreads)
-batch_zero_kernel(BatchState* st, unsigned int* done, int nitems) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    st->head = 0;
-    st->error = 0;
-  }
-  for (int j = i; j < nitems; j += gridDim.x * blockDim.x) done[j] = 0;
+// LDS of the persistent kernel: the largest 1D tile or small plane.
+constexpr int kBatchPersistentLds = cmax(kBatchLdsElems, plane_lds_elems<128, 32>());
+
+// Plane shapes the persistent kernel runs (small planes, 256 threads).
+__host__ __device__ constexpr bool batch_persistent_plane_shape(int n1, int n2) {
+  return batch_plane_shape(n1, n2) && n1 * n2 <= kBatchSmallPlane;
 }
 
+// The item a ticket belongs to: the last of [lo, hi) whose first tile is at
+// or before it.
+__device__ __forceinline__ int batch_find_item(const BatchItem* items, int lo, int hi,
+                                               int64_t ticket) {
+  hi -= 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= ticket) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One small-plane item tile (a whole plane) on 256 threads.
+__device__ __noinline__ void batch_small_plane(const BatchItem& it, int64_t plane,
+                                                  float2* lds, int tid) {
+#define DFT3D_PLANE_CASE(A, B)                                                               \
+  if (it.n1 == A && it.n == B) {                                                             \
+    plane_run<A, B, A * B / kBatchThreads>(it.src, it.dst, it.tw, it.twp, it.a, plane, lds, \
+                                           tid);                                            \
+    return;                                                                                  \
+  }
+  DFT3D_PLANE_CASE(32, 32)
+  DFT3D_PLANE_CASE(32, 64)
+  DFT3D_PLANE_CASE(32, 128)
+  DFT3D_PLANE_CASE(64, 32)
+  DFT3D_PLANE_CASE(64, 64)
+  DFT3D_PLANE_CASE(128, 32)
+#undef DFT3D_PLANE_CASE
+}
+
+// A 1D item tile of the persistent kernel, kept out of line so that the
+// kernel's registers are those of the largest tile kind, not of all of them
+// at once.
+template <int N>
+__device__ __noinline__ void batch_tile_call(const BatchItem& it, int64_t tile, float2* lds) {
+  batch_tile_modes<N>(it, tile, lds);
+}
+
+// Wave-uniform copies (lane 0's value) of values every lane holds alike.
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform_i64(long long v) {
+  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)(v & 0xffffffffll));
+  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// All levels of a batch in one launch (see the top of this file).  items
+// [0, nitems) in level-major order, total = tickets = sum of ntiles; an
+// item's dep is the item of the same problem one level earlier (-1 at level
+// 0).  At most spin_limit polls per wait.
+//
+// Control flow inside the ticket loop is wave-uniform only: the work of
+// "thread 0" is done by the whole first wave (branch on the wave index,
+// atomics whose operand is 1 on thread 0 and 0 elsewhere) and every wave
+// polls for itself.  A divergent `if (threadIdx.x == 0)` block at the end
+// of the loop and another at its start were merged by the compiler across
+// the back-edge into an inner loop around the barriers from which lane 0
+// of the first wave was masked off: the other lanes re-ran the same tile
+// forever and the launch never finished.
 __global__ void __launch_bounds__(kBatchThreads)
 batch_persistent_kernel(const BatchItem* __restrict__ items, int nitems, int64_t total,
                         BatchState* st, unsigned int* done, unsigned int spin_limit) {
-  __shared__ float2 lds[kBatchLdsElems];
-  __shared__ long long s_ticket;
-  __shared__ int s_item;
+  __shared__ float2 lds[kBatchPersistentLds];
+  __shared__ long long s_ticket[2];  // [0]: thread 0's ticket; [1]: other lanes' writes
   const int tid = threadIdx.x;
-  while (true) {
-    if (tid == 0) {
-      const unsigned long long t =
-          __hip_atomic_fetch_add(&st->head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      long long ticket = (long long)t;
-      int item = -1;
-      if (ticket < total) {
-        // last item whose first tile is at or before the ticket
-        int lo = 0, hi = nitems - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (items[mid].first <= ticket) lo = mid; else hi = mid - 1;
-        }
-        item = lo;
-        const int dep = items[item].dep;
-        if (dep >= 0) {
-          const unsigned int need = (unsigned int)items[dep].ntiles;
-          unsigned int spins = 0;
-          while (load_relaxed(&done[dep]) < need) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins >= spin_limit) {  // never expected; stay hang-free
-              __hip_atomic_fetch_or(&st->error, 1u, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-          }
-          // one acquire per satisfied wait: the producers' stores become
-          // visible here, and the barrier below extends that to every wave
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-      }
-      s_ticket = ticket;
-      s_item = item;
+  const unsigned int one = tid == 0 ? 1u : 0u;
+  const bool wave0 = uniform_i32(tid) < 64;  // wave-uniform
+  for (;;) {
+    if (wave0) {
+      const unsigned long long t = __hip_atomic_fetch_add(
+          &st->head, (unsigned long long)one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_ticket[one ? 0 : 1] = (long long)t;
     }
     __syncthreads();
-    const long long ticket = s_ticket;
-    const int item = s_item;
+    const long long ticket = uniform_i64(s_ticket[0]);
     if (ticket >= total) break;
+    const int item = uniform_i32(batch_find_item(items, 0, nitems, ticket));
     const BatchItem& it = items[item];
-    const int64_t tile = ticket - it.first;
-    switch (it.n) {
-      case 1: batch_tile_modes<1>(it, tile, lds); break;
-      case 2: batch_tile_modes<2>(it, tile, lds); break;
-      case 4: batch_tile_modes<4>(it, tile, lds); break;
-      case 8: batch_tile_modes<8>(it, tile, lds); break;
-      case 16: batch_tile_modes<16>(it, tile, lds); break;
-      case 32: batch_tile_modes<32>(it, tile, lds); break;
-      case 64: batch_tile_modes<64>(it, tile, lds); break;
-      case 128: batch_tile_modes<128>(it, tile, lds); break;
-      default: batch_tile_modes<256>(it, tile, lds); break;
+    const int dep = uniform_i32(it.dep);
+    if (dep >= 0) {
+      // every wave waits for itself (no barrier needed before its loads)
+      const unsigned int need = (unsigned int)uniform_i64(items[dep].ntiles);
+      unsigned int polls = 0;
+      while ((unsigned int)uniform_i32((int)load_relaxed(&done[dep])) < need) {
+        ++polls;
+        // give up at the limit, or at once when another wait already ran
+        // out (the results are then void and reported as such)
+        if (polls >= spin_limit ||
+            ((polls & 63u) == 0 && uniform_i32((int)load_relaxed(&st->error)) != 0)) {
+          __hip_atomic_fetch_or(&st->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      // one acquire per satisfied wait: the producers' stores are visible
+      // to this wave's loads from here on
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    const int64_t tile = ticket - uniform_i64(it.first);
+    if (uniform_i32(it.n1) > 0) {
+      batch_small_plane(it, tile, lds, tid);
+    } else {
+      switch (uniform_i32(it.n)) {
+        case 1: batch_tile_call<1>(it, tile, lds); break;
+        case 2: batch_tile_call<2>(it, tile, lds); break;
+        case 4: batch_tile_call<4>(it, tile, lds); break;
+        case 8: batch_tile_call<8>(it, tile, lds); break;
+        case 16: batch_tile_call<16>(it, tile, lds); break;
+        case 32: batch_tile_call<32>(it, tile, lds); break;
+        case 64: batch_tile_call<64>(it, tile, lds); break;
+        case 128: batch_tile_call<128>(it, tile, lds); break;
+        default: batch_tile_call<256>(it, tile, lds); break;
+      }
     }
     // every wave's stores complete and visible device-wide before the tile
-    // is counted
+    // is counted; the barrier also ends every read of lds and of s_ticket
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (tid == 0)
-      __hip_atomic_fetch_add(&done[item], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (wave0)
+      __hip_atomic_fetch_add(&done[item], one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // The last workgroup to leave zeroes the counters for the next launch:
+  // every other workgroup has taken its final ticket by then.
+  if (wave0) {
+    const unsigned int prev = (unsigned int)uniform_i32((int)__hip_atomic_fetch_add(
+        &st->exited, one, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT));
+    if (prev + 1 == gridDim.x) {
+      for (int i = tid; i < nitems; i += 64)
+        __hip_atomic_store(&done[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) {
+        __hip_atomic_store(&st->head, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st->exited, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
   }
 }
 

@@ -213,6 +213,10 @@ int apply_option(Options& o, int key, int64_t value) {
       if (value < -1 || value > 4096) return DFT3D_ERR_INVALID_ARG;
       o.pencil_group = (int)value;
       return DFT3D_OK;
+    case DFT3D_OPT_BATCH_LAUNCH:
+      if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
+      o.batch_launch = (int)value;
+      return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
   }
@@ -230,10 +234,11 @@ void destroy_twin(dft3d_plan_s* p) {
   p->batch_twin = nullptr;
 }
 
-dft3d_plan_s* batch_view(dft3d_plan_s* p) {
+dft3d_plan_s* batch_view(dft3d_plan_s* p, bool persistent) {
   bool plane = false;
   for (const Pass& ps : p->passes)
-    plane = plane || (ps.k->plane_rows > 0 && !batch_runs_plane(ps.k->plane_rows, ps.k->n));
+    plane = plane ||
+            (ps.k->plane_rows > 0 && !batch_runs_plane(ps.k->plane_rows, ps.k->n, persistent));
   if (!plane) return p;
   if (p->batch_twin) return p->batch_twin;
   dft3d_plan_s* t = new (std::nothrow) dft3d_plan_s();
@@ -266,6 +271,45 @@ int ensure_workspace(dft3d_plan_s* p) {
     p->ws = w;
     p->ws_bytes = p->ws_need;
     p->ws_owned = true;
+  }
+  return DFT3D_OK;
+}
+
+int check_device(const dft3d_plan_s* p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return DFT3D_ERR_HIP;
+  }
+  return dev == p->device ? DFT3D_OK : DFT3D_ERR_INVALID_ARG;
+}
+
+int execute_passes(dft3d_plan_s* p, const void* in, void* out, int sign, hipStream_t s,
+                   void* ws) {
+  const size_t bytes = (size_t)(p->n[0] * p->n[1] * p->n[2]) * sizeof(float2);
+  if (p->ws_need > 0 && (!ws || overlaps(ws, in, bytes) || overlaps(ws, out, bytes)))
+    return DFT3D_ERR_INVALID_ARG;
+  if (fault("launch")) return DFT3D_ERR_HIP;
+  float2* bufs[3] = {const_cast<float2*>(static_cast<const float2*>(in)),
+                     static_cast<float2*>(out), static_cast<float2*>(ws)};
+  // a shuffled plan's inverse takes shuffled input through its own list
+  const bool inv_list = sign == 1 && !p->ipasses.empty();
+  const std::vector<Pass>& list = inv_list ? p->ipasses : p->passes;
+  const std::vector<int64_t>& tw_off = inv_list ? p->itw_off : p->tw_off;
+  const std::vector<int64_t>& twp_off = inv_list ? p->itwp_off : p->twp_off;
+  const size_t np = list.size();
+  for (size_t i = 0; i < np; ++i) {
+    const Pass& ps = list[i];
+    PassArgs a = ps.args;
+    // inverse as conj(DFT(conj(x))): every pass reading the input conjugates
+    // it; the last pass writes every output element and conjugates them
+    a.conj_in = (sign == 1 && ps.src == BUF_IN) ? 1 : 0;
+    a.conj_out = (sign == 1 && i + 1 == np) ? 1 : 0;
+    const float2* tw = p->tables + tw_off[i];
+    const float2* twp = p->tables + twp_off[i];
+    hipError_t e =
+        ps.k->launch(a, bufs[ps.src] + ps.in_off, bufs[ps.dst] + ps.out_off, tw, twp, s);
+    if (e != hipSuccess) return DFT3D_ERR_HIP;
   }
   return DFT3D_OK;
 }
@@ -315,6 +359,45 @@ int dft3d_plan_describe(int64_t n0, int64_t n1, int64_t n2, int schedule, int la
   }
   const std::string s = describe_passes(n, resolved, layout, passes,
                                         layout == DFT3D_LAYOUT_SHUFFLED ? &ipasses : nullptr, ws);
+  if (needed) *needed = s.size() + 1;
+  if (buf && len > 0) {
+    const size_t m = s.size() < len - 1 ? s.size() : len - 1;
+    std::memcpy(buf, s.data(), m);
+    buf[m] = '\0';
+  }
+  return DFT3D_OK;
+}
+
+int dft3d_batch_describe(const int64_t* shapes, int count, int schedule, int launch,
+                         char* buf, size_t len, size_t* needed) {
+  if (count < 0 || (count > 0 && !shapes) || (launch != 0 && launch != 1))
+    return DFT3D_ERR_INVALID_ARG;
+  std::vector<std::vector<Pass>> lists((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    const int64_t* n = shapes + 3 * i;
+    int st = validate(n[0], n[1], n[2], schedule, DFT3D_LAYOUT_NATURAL);
+    if (st != DFT3D_OK) return st;
+    Options opt;
+    opt.batch_launch = launch;
+    size_t ws = 0;
+    int resolved = 0;
+    st = build_passes(n, schedule, DFT3D_LAYOUT_NATURAL, opt, lists[i], ws, resolved);
+    if (st != DFT3D_OK) return st;
+    // as batch_view: plane passes the form does not cover run unfused
+    bool uncovered = false;
+    for (const Pass& ps : lists[i])
+      uncovered = uncovered || (ps.k->plane_rows > 0 &&
+                                !batch_runs_plane(ps.k->plane_rows, ps.k->n, launch == 1));
+    if (uncovered) {
+      opt.fused_plane = 0;
+      lists[i].clear();
+      st = build_passes(n, schedule, DFT3D_LAYOUT_NATURAL, opt, lists[i], ws, resolved);
+      if (st != DFT3D_OK) return st;
+    }
+  }
+  std::vector<const std::vector<Pass>*> ptrs;
+  for (const auto& l : lists) ptrs.push_back(&l);
+  const std::string s = batch_describe(ptrs, launch == 1);
   if (needed) *needed = s.size() + 1;
   if (buf && len > 0) {
     const size_t m = s.size() < len - 1 ? s.size() : len - 1;
@@ -386,6 +469,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_FUSED_PLANE: *value = p->opt.fused_plane; break;
     case DFT3D_OPT_FUSED_AXES: *value = p->opt.fused_axes; break;
     case DFT3D_OPT_PENCIL_GROUP: *value = p->opt.pencil_group; break;
+    case DFT3D_OPT_BATCH_LAUNCH: *value = p->opt.batch_launch; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }
@@ -416,18 +500,6 @@ int dft3d_set_workspace(dft3d_plan_t p, void* dev_ptr, size_t bytes) {
 }
 
 
-namespace {
-// Plans run on the device they were created on.
-int check_device(const dft3d_plan_s* p) {
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) {
-    (void)hipGetLastError();
-    return DFT3D_ERR_HIP;
-  }
-  return dev == p->device ? DFT3D_OK : DFT3D_ERR_INVALID_ARG;
-}
-}  // namespace
-
 int dft3d_execute(dft3d_plan_t p, const void* in, void* out, int sign, void* stream) {
   if (!p || !in || !out || (sign != -1 && sign != 1)) return DFT3D_ERR_INVALID_ARG;
   {
@@ -440,32 +512,7 @@ int dft3d_execute(dft3d_plan_t p, const void* in, void* out, int sign, void* str
     const int st = ensure_workspace(p);
     if (st != DFT3D_OK) return st;
   }
-  if (p->ws_need > 0 && (overlaps(p->ws, in, bytes) || overlaps(p->ws, out, bytes)))
-    return DFT3D_ERR_INVALID_ARG;
-  if (fault("launch")) return DFT3D_ERR_HIP;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  float2* bufs[3] = {const_cast<float2*>(static_cast<const float2*>(in)),
-                     static_cast<float2*>(out), static_cast<float2*>(p->ws)};
-  // a shuffled plan's inverse takes shuffled input through its own list
-  const bool inv_list = sign == 1 && !p->ipasses.empty();
-  const std::vector<Pass>& list = inv_list ? p->ipasses : p->passes;
-  const std::vector<int64_t>& tw_off = inv_list ? p->itw_off : p->tw_off;
-  const std::vector<int64_t>& twp_off = inv_list ? p->itwp_off : p->twp_off;
-  const size_t np = list.size();
-  for (size_t i = 0; i < np; ++i) {
-    const Pass& ps = list[i];
-    PassArgs a = ps.args;
-    // inverse as conj(DFT(conj(x))): every pass reading the input conjugates
-    // it; the last pass writes every output element and conjugates them
-    a.conj_in = (sign == 1 && ps.src == BUF_IN) ? 1 : 0;
-    a.conj_out = (sign == 1 && i + 1 == np) ? 1 : 0;
-    const float2* tw = p->tables + tw_off[i];
-    const float2* twp = p->tables + twp_off[i];
-    hipError_t e =
-        ps.k->launch(a, bufs[ps.src] + ps.in_off, bufs[ps.dst] + ps.out_off, tw, twp, s);
-    if (e != hipSuccess) return DFT3D_ERR_HIP;
-  }
-  return DFT3D_OK;
+  return execute_passes(p, in, out, sign, static_cast<hipStream_t>(stream), p->ws);
 }
 
 int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,

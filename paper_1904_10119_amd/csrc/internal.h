@@ -142,6 +142,7 @@ struct Options {
   int fused_plane = 1; // slab: one fused 2D pass for planes that fit in LDS
   int fused_axes = 1;  // volumetric: V2 of an axis and V1 of the next in one pass
   int pencil_group = 0; // pencil: planes per group of the first two passes (0 = all, -1 = auto)
+  int batch_launch = 0; // batched calls: 0 one launch per pass level, 1 one persistent launch
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success
@@ -192,6 +193,13 @@ struct dft3d_plan_s {
 namespace dft3d {
 // Allocates the plan-owned workspace if needed (dft3d status).
 int ensure_workspace(dft3d_plan_s* p);
+// DFT3D_OK if the current device is the plan's, else a status.
+int check_device(const dft3d_plan_s* p);
+// Enqueues the plan's passes on s with `ws` as the workspace (at least
+// p->ws_need bytes, disjoint from in and out; may be null when the plan needs
+// none).  Arguments are validated by the caller.  Allocates nothing.
+int execute_passes(dft3d_plan_s* p, const void* in, void* out, int sign, hipStream_t s,
+                   void* ws);
 // Batched execution (batch.hip) and its cache upkeep.
 int batch_execute(dft3d_plan_s* const* plans, const void* const* in,
                   void* const* out, int count, int sign, hipStream_t stream);
@@ -199,9 +207,13 @@ void batch_forget_plan(const dft3d_plan_s* p);
 // AUTO plans: apply the autotuner's recorded choice for the shape, if any.
 void tune_lookup(dft3d_plan_s* p);
 // The plan whose passes the batched kernels run for p: p itself, or, when
-// p has a fused plane pass the batched plane kernel does not cover, its
-// twin without fused plane passes (created on first use; null on failure).
-dft3d_plan_s* batch_view(dft3d_plan_s* p);
-// Whether the batched plane kernel covers (n1, n2) planes.
-bool batch_runs_plane(int n1, int n2);
+// p has a fused plane pass the batched form (`persistent`: the one-launch
+// form) does not cover, its twin without fused plane passes (created on
+// first use; null on failure).
+dft3d_plan_s* batch_view(dft3d_plan_s* p, bool persistent);
+// Whether the batched plane kernels of a form cover (n1, n2) planes.
+bool batch_runs_plane(int n1, int n2, bool persistent);
+// Device-free description of how a batch of plans with these pass lists is
+// laid out (JSON; see dft3d_batch_describe).
+std::string batch_describe(const std::vector<const std::vector<Pass>*>& lists, bool persistent);
 }  // namespace dft3d

@@ -19,7 +19,7 @@ PRECISIONS = {"fp32": 0, "bf16x1": 1, "fp16x1": 2, "bf16x6": 3, "bf16x9": 4,
               "fp16x3": 5}
 OPT_PRECISION, OPT_TILE, OPT_XCD_REMAP, OPT_SPLIT_MAX, OPT_NONTEMPORAL = 1, 2, 3, 4, 5
 OPT_PERSISTENT, OPT_SLAB_GROUP, OPT_FUSED_PLANE, OPT_FUSED_AXES = 6, 7, 8, 9
-OPT_PENCIL_GROUP = 10
+OPT_PENCIL_GROUP, OPT_BATCH_LAUNCH = 10, 11
 OPT_NUM_PASSES = 100
 
 OK = 0
@@ -35,7 +35,8 @@ ERR_WORKSPACE_TOO_SMALL = -7
 EXPORTS = ("dft3d_status_string", "dft3d_plan", "dft3d_plan_describe",
            "dft3d_plan_set_option", "dft3d_plan_get_option",
            "dft3d_workspace_size", "dft3d_set_workspace", "dft3d_execute",
-           "dft3d_execute_batched", "dft3d_autotune", "dft3d_destroy")
+           "dft3d_execute_batched", "dft3d_autotune", "dft3d_destroy",
+           "dft3d_batch_describe")
 
 _lib = None
 
@@ -77,6 +78,8 @@ def lib():
     L.dft3d_autotune.argtypes = [i64, i64, i64, vp, vp, vp, ctypes.POINTER(ci),
                                  ctypes.POINTER(ctypes.c_double)]
     L.dft3d_destroy.argtypes = [vp]
+    L.dft3d_batch_describe.argtypes = [ctypes.POINTER(i64), ci, ci, ci, ctypes.c_char_p,
+                                       sz, ctypes.POINTER(sz)]
     for f in EXPORTS[1:]:
         getattr(L, f).restype = ci
     _lib = L
@@ -92,7 +95,8 @@ OPTION_KEYS = {"precision": OPT_PRECISION, "tile": OPT_TILE,
                "xcd_remap": OPT_XCD_REMAP, "split_max": OPT_SPLIT_MAX,
                "nontemporal": OPT_NONTEMPORAL, "persistent": OPT_PERSISTENT,
                "slab_group": OPT_SLAB_GROUP, "fused_plane": OPT_FUSED_PLANE,
-               "fused_axes": OPT_FUSED_AXES, "pencil_group": OPT_PENCIL_GROUP}
+               "fused_axes": OPT_FUSED_AXES, "pencil_group": OPT_PENCIL_GROUP,
+               "batch_launch": OPT_BATCH_LAUNCH}
 
 
 def describe(shape: Sequence[int], schedule: str = "auto",
@@ -112,6 +116,22 @@ def describe(shape: Sequence[int], schedule: str = "auto",
     return json.loads(buf.value.decode())
 
 
+BATCH_LAUNCHES = {"levels": 0, "persistent": 1}
+
+
+def describe_batch(shapes, schedule: str = "auto", launch: str = "levels") -> dict:
+    """Work items and launches of a batched call over `shapes` (no device)."""
+    flat = [int(v) for s in shapes for v in s]
+    arr = (ctypes.c_int64 * max(1, len(flat)))(*flat)
+    need = ctypes.c_size_t(0)
+    L = lib()
+    args = (arr, len(shapes), SCHEDULES[schedule], BATCH_LAUNCHES[launch])
+    _check(L.dft3d_batch_describe(*args, None, 0, ctypes.byref(need)), "batch_describe")
+    buf = ctypes.create_string_buffer(need.value)
+    _check(L.dft3d_batch_describe(*args, buf, need.value, None), "batch_describe")
+    return json.loads(buf.value.decode())
+
+
 class Plan:
     """Owns a dft3d_plan_t.  The workspace is a torch tensor on the plan's
     device, so torch's caching allocator owns that memory."""
@@ -121,7 +141,7 @@ class Plan:
                  tile: int = 0, split_max: int = 0, xcd_remap: int = 1,
                  nontemporal: int = -1, persistent: int = -1,
                  slab_group: int = -2, fused_plane: int = -1, fused_axes: int = -1,
-                 pencil_group: int = -2):
+                 pencil_group: int = -2, batch_launch: int = -1):
         self.shape = tuple(int(s) for s in shape)
         self.schedule = schedule
         h = ctypes.c_void_p()
@@ -151,6 +171,8 @@ class Plan:
                 self.set_option(OPT_FUSED_AXES, fused_axes)
             if pencil_group >= -1:
                 self.set_option(OPT_PENCIL_GROUP, pencil_group)
+            if batch_launch >= 0:
+                self.set_option(OPT_BATCH_LAUNCH, batch_launch)
         except Exception:
             self.close()
             raise
@@ -285,13 +307,16 @@ def ifftn(x, **kw):
 
 
 def fftn_batched(xs: List, inverse: bool = False, outs: Optional[List] = None,
-                 schedule: str = "auto"):
-    """Many 3D DFTs of possibly different shapes in one library call."""
+                 schedule: str = "auto", launch: str = "levels"):
+    """Many 3D DFTs of possibly different shapes in one library call;
+    launch="persistent" runs the whole batch as one persistent launch."""
     import torch
     n = len(xs)
     if outs is None:
         outs = [torch.empty_like(x) for x in xs]
-    plans = [get_plan(x.shape, schedule, "fp32", x.device.index or 0) for x in xs]
+    bl = BATCH_LAUNCHES[launch]
+    plans = [get_plan(x.shape, schedule, "fp32", x.device.index or 0,
+                      **({"batch_launch": bl} if bl else {})) for x in xs]
     for p, x in zip(plans, xs):
         p.bind_workspace(x.device)
     arr = ctypes.c_void_p * max(n, 1)

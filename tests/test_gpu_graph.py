@@ -89,16 +89,18 @@ def test_graph_replay_matches_eager(shape, schedule, layout):
     p.close()
 
 
-def test_batched_graph_replay_matches_eager():
+@pytest.mark.parametrize("launch", ["levels", "persistent"])
+def test_batched_graph_replay_matches_eager(launch):
     """Batched execution captured after an eager call with the same buffers:
     replays reproduce the eager result bit for bit, also after eager batched
     calls with other output buffers in between (which must not disturb the
     captured descriptors), and transform new values put in the inputs."""
     shapes = [(32, 64, 128), (64, 64, 64), (8, 16, 4), (128, 32, 16), (32, 32, 32)]
+    print("case batched graph", launch, shapes, flush=True)
     xs = [torch.from_numpy(inputs.uniform_c64(s, 50 + i)).cuda() for i, s in enumerate(shapes)]
     outs = [torch.empty_like(x) for x in xs]
     for inverse in (False, True):
-        dft3d.fftn_batched(xs, outs=outs, inverse=inverse)     # eager: descriptors on device
+        dft3d.fftn_batched(xs, outs=outs, inverse=inverse, launch=launch)     # eager: descriptors on device
         torch.cuda.synchronize()
         eager = [o.clone() for o in outs]
         g = torch.cuda.CUDAGraph()
@@ -106,7 +108,7 @@ def test_batched_graph_replay_matches_eager():
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
-                dft3d.fftn_batched(xs, outs=outs, inverse=inverse)
+                dft3d.fftn_batched(xs, outs=outs, inverse=inverse, launch=launch)
         torch.cuda.current_stream().wait_stream(s)
         for rep in range(3):
             for o in outs:
@@ -115,7 +117,7 @@ def test_batched_graph_replay_matches_eager():
             torch.cuda.synchronize()
             for o, e in zip(outs, eager):
                 assert torch.equal(o, e), rep
-            other = dft3d.fftn_batched(xs, inverse=inverse)   # other output buffers
+            other = dft3d.fftn_batched(xs, inverse=inverse, launch=launch)   # other output buffers
             torch.cuda.synchronize()
             for o, e in zip(other, eager):
                 assert torch.equal(o, e)
