@@ -63,6 +63,8 @@ def _load():
     lib.oracle_fft_pencils_radix2.argtypes = [fp, i64, i64, i64, ci, ci, i64,
                                               i64, dp]
     lib.oracle_num_threads.argtypes = []
+    lib.oracle_set_num_threads.argtypes = [ci]
+    lib.oracle_set_num_threads.restype = None
     for f in ("oracle_dft1d_direct", "oracle_dft3d_direct",
               "oracle_dft3d_sample_pencils", "oracle_fft1d_radix2",
               "oracle_fft3d_radix2", "oracle_fft_pencils_radix2",
@@ -95,6 +97,11 @@ def _as_c128(x) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads the oracle uses from now on (timing on one core)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def dft1d(x, sign: int = -1, method: str = "direct") -> np.ndarray:
@@ -130,6 +137,53 @@ def dft3d(x, sign: int = -1, method: str = "direct") -> np.ndarray:
     else:
         raise ValueError(method)
     return y
+
+
+def dft3d_fft_c64(x_c64: np.ndarray, sign: int = -1) -> np.ndarray:
+    """O2 (recursive radix-2, FP64) of a complex64 (n0, n1, n2) array,
+    widened exactly to complex128 and transformed in place: the same result
+    as ``dft3d(x, sign, "fft")`` with one FP64 array instead of two (for
+    2^30-point inputs)."""
+    xa = np.asarray(x_c64)
+    if xa.ndim != 3:
+        raise ValueError("expected a 3D array")
+    n0, n1, n2 = xa.shape
+    y = np.empty(xa.shape, dtype=np.complex128)
+    for i in range(0, n0, 16):  # widen slab by slab (no second full copy)
+        y[i:i + 16] = xa[i:i + 16]
+    _check(_load().oracle_fft3d_radix2(_dptr(y), _dptr(y), n0, n1, n2, sign),
+           "oracle_fft3d_radix2")
+    return y
+
+
+def compare(a, ref, planes: int = 16, where: bool = False):
+    """Errors of ``a`` against the FP64 ``ref`` over every element, taken
+    slab by slab (no full-size temporaries): ``(rel_l2, max_rel)`` with
+    rel_l2 = ||a - ref||_2 / ||ref||_2 and max_rel = max |a - ref| / rms(ref),
+    the largest single-element error relative to the root mean square of the
+    reference; with ``where`` also the index tuple of that element."""
+    a = np.asarray(a)
+    r = np.asarray(ref)
+    if a.shape != r.shape:
+        raise ValueError(f"shapes differ: {a.shape} vs {r.shape}")
+    num = 0.0
+    den = 0.0
+    worst = 0.0
+    at = (0,) * a.ndim
+    for i in range(0, a.shape[0], planes):
+        d = a[i:i + planes].astype(np.complex128) - r[i:i + planes]
+        e2 = d.real * d.real + d.imag * d.imag
+        num += float(e2.sum())
+        if e2.size and float(e2.max()) > worst:
+            worst = float(e2.max())
+            loc = np.unravel_index(int(np.argmax(e2)), e2.shape)
+            at = (i + int(loc[0]),) + tuple(int(v) for v in loc[1:])
+        rr = r[i:i + planes]
+        den += float((rr.real * rr.real + rr.imag * rr.imag).sum())
+    rms = np.sqrt(den / max(1, a.size))
+    rel = np.sqrt(num / den) if den > 0 else np.sqrt(num)
+    wr = float(np.sqrt(worst) / rms) if rms > 0 else float(np.sqrt(worst))
+    return (float(rel), wr, at) if where else (float(rel), wr)
 
 
 def sample_pencils(x_c64: np.ndarray, k0, k1, sign: int = -1) -> np.ndarray:

@@ -75,6 +75,9 @@ int oracle_fft_pencils_radix2(const float* x, int64_t n0, int64_t n1,
 /* Number of OpenMP threads the oracle runs with. */
 int oracle_num_threads(void);
 
+/* Threads for later calls (timing on one core vs all host cores). */
+void oracle_set_num_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

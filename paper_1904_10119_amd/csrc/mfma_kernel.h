@@ -237,15 +237,32 @@ __device__ __forceinline__ void mfma_load(float2 (&v)[kMfmaRegs], const float2* 
 //
 // The matrix cores do not round their dot products to nearest: measured on
 // random operands the result carries a bias of a fraction of an ulp of one
-// sign.  Summed coherently by the later stages and axes (at the DC bins)
-// that bias grows with the transform size, so every other vector (by the
-// parity of pencil + butterfly) is transformed negated and negated back,
-// which makes the bias alternate in sign and cancel in those sums.  The
-// negations are exact.
+// sign.  Summed coherently by the later stages and axes, that bias grows
+// with the transform size wherever the weights of a sum line up with it: at
+// the DC bins when every vector is transformed alike, and still at some
+// output of a 1024^3 transform (4.6e-5 of the output rms, 2.8 times the
+// per-element bar of 10 tol(N)) when every other vector by the parity of
+// pencil + butterfly was transformed negated, a pattern that repeats with
+// every tile.  Each vector (pencil b, butterfly t, stage NS) is therefore
+// transformed with a pseudo-random sign from a hash of (b, t, NS) and the
+// result multiplied by the same sign (exact operations): the biases then
+// add like independent rounding errors at every output.
+__device__ __forceinline__ float mfma_vector_sign(int64_t b, int t, int NS) {
+  unsigned int x = (unsigned int)b * 0x9e3779b9u + (unsigned int)(t * 16 + __builtin_ctz(NS)) *
+                                                       0x85ebca77u;
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return (x & 0x80000000u) ? -1.0f : 1.0f;
+}
+
 template <int N, int PREC>
 __device__ __forceinline__ void mfma_leaf_store(const float2 (&x)[4], const LeafA<PREC>& A,
-                                                float2* out, int q, int t, int NS, int lane) {
-  const float sgn = ((q + t) & 1) ? -1.0f : 1.0f;
+                                                float2* out, int64_t pbase, int q, int t,
+                                                int NS, int lane) {
+  const float sgn = mfma_vector_sign(pbase + q, t, NS);
   float xs[8];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -273,7 +290,8 @@ __device__ __forceinline__ void mfma_leaf_store(const float2 (&x)[4], const Leaf
 // inverse), output to LDS buffer out.
 template <int N, int LM, int PREC>
 __device__ __forceinline__ void mfma_first_stage(const float2 (&v)[kMfmaRegs], float2* out,
-                                                 const LeafA<PREC>& A, int conj, int tid) {
+                                                 const LeafA<PREC>& A, int conj,
+                                                 int64_t pbase, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int g4 = 0; g4 < 4; ++g4) {
@@ -285,7 +303,7 @@ __device__ __forceinline__ void mfma_first_stage(const float2 (&v)[kMfmaRegs], f
       x[k] = v[g4 * 4 + k];
       if (conj) x[k].y = -x[k].y;
     }
-    mfma_leaf_store<N, PREC>(x, A, out, q, t, 1, lane);
+    mfma_leaf_store<N, PREC>(x, A, out, pbase, q, t, 1, lane);
   }
 }
 
@@ -296,7 +314,8 @@ __device__ __forceinline__ void mfma_first_stage(const float2 (&v)[kMfmaRegs], f
 // workgroups per CU.
 template <int N, int PREC>
 __device__ __forceinline__ void mfma_later_stages(float2* io, const float2* ltw,
-                                                  const LeafA<PREC>& A, int tid) {
+                                                  const LeafA<PREC>& A, int64_t pbase,
+                                                  int tid) {
   constexpr int S16 = mfma_stages<N>();
   constexpr int stride = N / 16;
   const int lane = tid & 63, wave = tid >> 6;
@@ -322,7 +341,7 @@ __device__ __forceinline__ void mfma_later_stages(float2* io, const float2* ltw,
     for (int g4 = 0; g4 < 4; ++g4) {
       int q, t;
       mfma_vec<N, MODE_ROW>(wave * 64 + g4 * 16 + (lane & 15), q, t);
-      mfma_leaf_store<N, PREC>(x[g4], A, io, q, t, NS, lane);
+      mfma_leaf_store<N, PREC>(x[g4], A, io, pbase, q, t, NS, lane);
     }
     __syncthreads();  // every output of the stage is written
     NS *= 16;
@@ -336,7 +355,7 @@ __device__ __forceinline__ void mfma_later_stages(float2* io, const float2* ltw,
 template <int N, int PREC>
 __device__ __forceinline__ int mfma_later_stages_pingpong(float2 (*buf)[mfma_buf_elems<N>()],
                                                  const float2* ltw, const LeafA<PREC>& A,
-                                                 int tid) {
+                                                 int64_t pbase, int tid) {
   constexpr int S16 = mfma_stages<N>();
   constexpr int stride = N / 16;
   const int lane = tid & 63, wave = tid >> 6;
@@ -359,7 +378,7 @@ __device__ __forceinline__ int mfma_later_stages_pingpong(float2 (*buf)[mfma_buf
         const int r = rb + k;
         x[k] = cmul(in[mfma_lds<N>(q, t + r * stride)], ltw[tm * r * twstep]);
       }
-      mfma_leaf_store<N, PREC>(x, A, out, q, t, NS, lane);
+      mfma_leaf_store<N, PREC>(x, A, out, pbase, q, t, NS, lane);
     }
     __syncthreads();
     cur ^= 1;
@@ -436,9 +455,10 @@ fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
   for (int i = tid; i < N; i += mfma_threads<N>()) ltw[i] = tw[i];
   LeafA<PREC> A;
   A.load(leaf, tid & 63);
-  mfma_first_stage<N, LM, PREC>(v, buf, A, a.conj_in, tid);
+  constexpr int T = mfma_tile_elems<N>() / N;
+  mfma_first_stage<N, LM, PREC>(v, buf, A, a.conj_in, tile * T, tid);
   __syncthreads();
-  mfma_later_stages<N, PREC>(buf, ltw, A, tid);
+  mfma_later_stages<N, PREC>(buf, ltw, A, tile * T, tid);
   mfma_finish<N, SM>(buf, dst, ltw, a, tile, tid);
 }
 
@@ -466,13 +486,14 @@ fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restric
   A.load(leaf, tid & 63);
   __syncthreads();  // twiddles in LDS
   while (true) {
-    mfma_first_stage<N, LM, PREC>(v, buf[0], A, a.conj_in, tid);
+    const int64_t tile = tile_index(w, ntiles, a.xcd_remap);
+    mfma_first_stage<N, LM, PREC>(v, buf[0], A, a.conj_in, tile * T, tid);
     __syncthreads();
     const int64_t wn = w + G;
     // prefetch the next tile (past the end: the last tile again, in bounds)
     mfma_load<N, LM>(v, src, a, tile_index(wn < last ? wn : last, ntiles, a.xcd_remap), tid);
-    const int cur = mfma_later_stages_pingpong<N, PREC>(buf, ltw, A, tid);
-    mfma_finish<N, SM>(buf[cur], dst, ltw, a, tile_index(w, ntiles, a.xcd_remap), tid);
+    const int cur = mfma_later_stages_pingpong<N, PREC>(buf, ltw, A, tile * T, tid);
+    mfma_finish<N, SM>(buf[cur], dst, ltw, a, tile, tid);
     __syncthreads();  // every read of the result buffer is done
     w = wn;
     if (w >= ntiles) break;

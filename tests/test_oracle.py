@@ -224,3 +224,36 @@ def test_bad_arguments_raise():
         oracle.dft3d(np.zeros((4, 4, 4)), 2, "direct")  # bad sign
     with pytest.raises(oracle.OracleError):
         oracle.sample_pencils(np.zeros((4, 4, 4), np.complex64), [4], [0])
+
+
+def test_fft_c64_in_place_equals_o2_and_compare_matches_definitions():
+    """dft3d_fft_c64 (O2 on one FP64 array, for 2^30-point inputs) is O2
+    exactly; compare() gives rel_l2 and the largest element error relative
+    to the reference's root mean square, also for a planted single-element
+    error."""
+    from paper_1904_10119_amd import inputs
+    x = inputs.uniform_c64((16, 8, 32), 21)
+    a = oracle.dft3d(x, -1, "fft")
+    b = oracle.dft3d_fft_c64(x, -1)
+    assert np.array_equal(a, b)
+    a_inv = oracle.dft3d(x, +1, "fft")
+    assert np.array_equal(a_inv, oracle.dft3d_fft_c64(x, +1))
+    y = a.astype(np.complex64)
+    rel, worst = oracle.compare(y, a, planes=3)
+    assert rel == pytest.approx(oracle.rel_l2(y, a), rel=1e-12)
+    rms = np.sqrt(np.mean(np.abs(a) ** 2))
+    assert worst == pytest.approx(np.max(np.abs(y - a)) / rms, rel=1e-12)
+    z = y.copy()
+    z[5, 3, 7] += 0.5 * rms
+    rel2, worst2, at = oracle.compare(z, a, planes=4, where=True)
+    assert worst2 == pytest.approx(np.abs(z[5, 3, 7] - a[5, 3, 7]) / rms, rel=1e-6)
+    assert at == (5, 3, 7)
+    assert rel2 > rel
+
+
+def test_thread_count_can_be_set():
+    n = oracle.num_threads()
+    oracle.set_num_threads(1)
+    assert oracle.num_threads() == 1
+    oracle.set_num_threads(n)
+    assert oracle.num_threads() == n
