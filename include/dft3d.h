@@ -229,6 +229,26 @@ int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
 int dft3d_batch_describe(const int64_t* shapes, int count, int schedule, int launch,
                          char* buf, size_t len, size_t* needed);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform as dft3d_execute on the same plan (same kernels, bitwise equal
+ * output), with the workspace taken from a static device array of
+ * DFT3D_NOALLOC_MAX_WORKSPACE bytes that the library holds on every GPU it
+ * runs on until the process ends, instead of a plan-owned or bound buffer.
+ * Never allocates or frees device memory and ignores any workspace bound to
+ * the plan.  in, out, sign, stream and the device rule are as for
+ * dft3d_execute.  A plan whose dft3d_workspace_size exceeds the maximum
+ * (transforms above 2^24 points on the PENCIL and VOLUMETRIC schedules) is
+ * rejected with DFT3D_ERR_WORKSPACE_TOO_SMALL before anything is enqueued;
+ * SLAB plans need no workspace and take any size.  All calls on one GPU share
+ * that GPU's array: calls whose execution may overlap in time on one GPU
+ * (different streams without ordering, different host threads) race and give
+ * wrong results; calls in one stream's order are safe.  The first call on a
+ * device looks the array's address up (no allocation). */
+#define DFT3D_NOALLOC_MAX_WORKSPACE ((size_t)128 << 20)
+int dft3d_execute_noalloc(dft3d_plan_t plan, const void* in, void* out, int sign,
+                          void* stream);
+
 /* Autotuner: time candidate schedules and kernel options (pencil with and
  * without the persistent kernels, split long axes, other tiles, grouped
  * first passes; slab; volumetric) for a (n0, n1, n2) transform on the

@@ -36,7 +36,7 @@ EXPORTS = ("dft3d_status_string", "dft3d_plan", "dft3d_plan_describe",
            "dft3d_plan_set_option", "dft3d_plan_get_option",
            "dft3d_workspace_size", "dft3d_set_workspace", "dft3d_execute",
            "dft3d_execute_batched", "dft3d_autotune", "dft3d_destroy",
-           "dft3d_batch_describe")
+           "dft3d_execute_noalloc", "dft3d_batch_describe")
 
 _lib = None
 
@@ -78,6 +78,7 @@ def lib():
     L.dft3d_autotune.argtypes = [i64, i64, i64, vp, vp, vp, ctypes.POINTER(ci),
                                  ctypes.POINTER(ctypes.c_double)]
     L.dft3d_destroy.argtypes = [vp]
+    L.dft3d_execute_noalloc.argtypes = [vp, vp, vp, ci, vp]
     L.dft3d_batch_describe.argtypes = [ctypes.POINTER(i64), ci, ci, ci, ctypes.c_char_p,
                                        sz, ctypes.POINTER(sz)]
     for f in EXPORTS[1:]:
@@ -221,6 +222,20 @@ class Plan:
         _check(lib().dft3d_execute(self._h, x.data_ptr(), out.data_ptr(),
                                    1 if inverse else -1, s.cuda_stream),
                "dft3d_execute")
+
+    def execute_noalloc(self, x, out, inverse: bool = False, stream=None) -> None:
+        """As execute(), through dft3d_execute_noalloc: the workspace is the
+        library's static per-device array (nothing is allocated)."""
+        import torch
+        for t in (x, out):
+            if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("expected contiguous complex64 CUDA tensors")
+            if tuple(t.shape) != self.shape:
+                raise ValueError(f"shape {tuple(t.shape)} != plan {self.shape}")
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
+        _check(lib().dft3d_execute_noalloc(self._h, x.data_ptr(), out.data_ptr(),
+                                           1 if inverse else -1, s.cuda_stream),
+               "dft3d_execute_noalloc")
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

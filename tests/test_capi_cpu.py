@@ -67,6 +67,7 @@ def test_null_handles_rejected():
     assert L.dft3d_plan_get_option(None, 1, ctypes.byref(v)) == dft3d.ERR_INVALID_ARG
     assert L.dft3d_workspace_size(None, ctypes.byref(sz)) == dft3d.ERR_INVALID_ARG
     assert L.dft3d_execute(None, 1, 2, -1, None) == dft3d.ERR_INVALID_ARG
+    assert L.dft3d_execute_noalloc(None, 1, 2, -1, None) == dft3d.ERR_INVALID_ARG
     assert L.dft3d_destroy(None) == dft3d.OK
     assert L.dft3d_execute_batched(None, None, None, 0, -1, None) == dft3d.OK
     assert L.dft3d_execute_batched(None, None, None, 1, -1, None) == dft3d.ERR_INVALID_ARG
