@@ -139,7 +139,12 @@ enum dft3d_option {
 /* Text for a status code; never NULL. */
 const char* dft3d_status_string(int status);
 
-/* Build a plan for a (n0, n1, n2) complex64 transform.  Each n_d is in
+/* Build a plan for a (n0, n1, n2) complex64 transform: the 3D DFT of Section
+ * 2.1 eqs. (1)-(2) applied along the three axes (Section 2.3), decomposed as
+ * the schedule says (slab: eq. (6), Fig. 5; pencil: eq. (8), Fig. 6;
+ * volumetric: Fig. 9, eqs. (13)-(17)).  As in the paper's Fig. 10, the shape
+ * and layout are described once and the transform is run many times.  Each
+ * n_d is in
  * [1, 4096].  Powers of two run on every schedule.  Other lengths (the
  * paper's experiments use powers of two) run on the pencil schedule (or AUTO,
  * which then picks it) with FP32 precision and the natural layout, one
@@ -157,7 +162,9 @@ const char* dft3d_status_string(int status);
 int dft3d_plan(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout,
                dft3d_plan_t* out);
 
-/* Describe the pass list a plan with the given options would use, without
+/* Describe the pass list a plan with the given options would use (the
+ * sequence of batched local DFTs and redistributions of Section 2.4 that the
+ * schedule becomes on one device), without
  * touching any device: keys[i] / values[i] (nopts pairs, as for
  * dft3d_plan_set_option; both may be NULL when nopts == 0) are applied to the
  * default options, then a NUL-terminated JSON text is written into buf (at
@@ -167,10 +174,21 @@ int dft3d_plan_describe(int64_t n0, int64_t n1, int64_t n2, int schedule,
                         int layout, const int* keys, const int64_t* values,
                         int nopts, char* buf, size_t len, size_t* needed);
 
+/* Set / read one option of a plan (enum dft3d_option): the tuning choices
+ * of a decomposition that do not change the result in exact arithmetic (the
+ * four-step split of a long axis, Section 3.2; tile shapes; the leaf
+ * arithmetic of the split-precision forms).  set_option validates the value
+ * (INVALID_ARG), rebuilds the pass list and uploads its tables; on failure
+ * (OUT_OF_MEMORY / HIP_ERROR) the previous pass list and options stay in
+ * force.  get_option writes the current value to *value.  NULL plan or value:
+ * INVALID_ARG. */
 int dft3d_plan_set_option(dft3d_plan_t plan, int key, int64_t value);
 int dft3d_plan_get_option(dft3d_plan_t plan, int key, int64_t* value);
 
-/* Bytes of device workspace dft3d_execute needs (0 if none). */
+/* Bytes of device workspace dft3d_execute needs (0 if none): the second
+ * buffer a redistribution writes into when it cannot work in place (the
+ * target B of eq. (12)); N * 8 bytes for the pencil and volumetric
+ * schedules, 0 for slab.  NULL arguments: INVALID_ARG. */
 int dft3d_workspace_size(dft3d_plan_t plan, size_t* bytes);
 
 /* Hand the plan a caller-owned device buffer of `bytes` bytes to use as
@@ -181,7 +199,10 @@ int dft3d_workspace_size(dft3d_plan_t plan, size_t* bytes);
 int dft3d_set_workspace(dft3d_plan_t plan, void* dev_ptr, size_t bytes);
 
 /* Enqueue the transform on `stream` (a hipStream_t; NULL = default stream)
- * and return.  in, out: device pointers of n0 n1 n2 complex64, distinct and
+ * and return: the passes of the plan's schedule, each a batched 1D DFT
+ * (Section 2.1, eq. (3) inside a pass) with the redistribution to the next
+ * axis folded into its loads and stores (Section 2.3 eqs. (6)-(8); Section
+ * 3.2, Fig. 9 and eqs. (13)-(17) for the volumetric schedule).  in, out: device pointers of n0 n1 n2 complex64, distinct and
  * non-overlapping (in == out is INVALID_ARG); in is never written.
  * sign = -1 forward, +1 inverse, anything else INVALID_ARG.  The current
  * device must be the one the plan was created on (INVALID_ARG otherwise).
@@ -195,25 +216,40 @@ int dft3d_set_workspace(dft3d_plan_t plan, void* dev_ptr, size_t bytes);
 int dft3d_execute(dft3d_plan_t plan, const void* in, void* out, int sign,
                   void* stream);
 
-/* Enqueue `count` transforms of possibly different shapes together: one
- * kernel launch per pass level covers the tiles of every problem at that
- * level.  plans[i] describes problem i (the same plan may appear more than
- * once), in[i] and out[i] are its device buffers (same rules as
- * dft3d_execute; distinct problems must not share buffers).  The first call
- * for a given sequence of plans builds the work descriptors (and workspaces
- * for repeated plans); later calls with the same sequence only refresh the
- * buffer pointers.  Plans whose passes exceed length 256 run one after
- * another.  count == 0 is a no-op.  Plans must use the NATURAL layout and
- * FP32.  Not thread-safe for concurrent calls with overlapping plans.
- * A call with the same plans, buffers and sign as the previous one reuses
- * the descriptors already on the device (no upload).  Capture into a HIP
- * graph: on a capturing stream the call records only its kernel launches,
- * so an earlier call outside the capture must have used exactly these
- * plans, buffers and sign (and bound every workspace); otherwise it returns
- * DFT3D_ERR_UNSUPPORTED_SCHEDULE before enqueueing anything.  Those
- * descriptors then stay fixed while the plans live (later calls with other
- * buffers get descriptor sets of their own); destroying or changing a plan
- * invalidates graphs that captured it. */
+/* Enqueue `count` transforms of possibly different shapes together (the
+ * paper finds that no single decomposition is fastest for every size,
+ * Section 4; one pool of workers serves every problem, as its threads serve
+ * both computation and packing in Fig. 11): one kernel launch per pass level
+ * covers the tiles of every problem at that level, or, with
+ * DFT3D_OPT_BATCH_LAUNCH = 1 on every plan, one persistent launch runs every
+ * level (a device ticket queue; a tile of pass k of a problem starts after
+ * every tile of its pass k - 1; the launch is replayed from a HIP graph the
+ * library builds once per descriptor set).
+ *
+ * plans[i] describes problem i (the same plan may appear more than once),
+ * in[i] and out[i] are its device buffers (same rules as dft3d_execute;
+ * distinct problems must not share buffers).  Problems whose workspaces
+ * would be shared (a repeated plan, or distinct plans bound to overlapping
+ * buffers with dft3d_set_workspace) get private workspaces for the batched
+ * call, since their passes run at the same time.  The first call for a given
+ * sequence of plans builds the work descriptors; later calls with the same
+ * sequence only refresh the buffer pointers.  Plans whose passes exceed
+ * length 256 or are split four-step (volumetric) run one after another.
+ * count == 0 is a no-op.  Plans must use the NATURAL layout and FP32
+ * (UNSUPPORTED_SCHEDULE otherwise).  Not thread-safe for concurrent calls
+ * with overlapping plans; calls with the same plans must be ordered (the
+ * persistent form's counters belong to its descriptor set).  A call with the
+ * same plans, buffers and sign as the previous one reuses the descriptors
+ * already on the device (no upload).  The persistent form's waits are
+ * bounded: with DFT3D_BATCH_CHECK=1 in the environment a call waits for its
+ * launch and returns DFT3D_ERR_HIP if a wait ran out (never expected).
+ * Capture into a HIP graph: on a capturing stream the call records only its
+ * kernel launches, so an earlier call outside the capture must have used
+ * exactly these plans, buffers and sign (and bound every workspace);
+ * otherwise it returns DFT3D_ERR_UNSUPPORTED_SCHEDULE before enqueueing
+ * anything.  Those descriptors then stay fixed while the plans live (later
+ * calls with other buffers get descriptor sets of their own); destroying or
+ * changing a plan invalidates graphs that captured it. */
 int dft3d_execute_batched(const dft3d_plan_t* plans, const void* const* in,
                           void* const* out, int count, int sign, void* stream);
 
@@ -249,7 +285,8 @@ int dft3d_batch_describe(const int64_t* shapes, int count, int schedule, int lau
 int dft3d_execute_noalloc(dft3d_plan_t plan, const void* in, void* out, int sign,
                           void* stream);
 
-/* Autotuner: time candidate schedules and kernel options (pencil with and
+/* Autotuner (the choice of decomposition per problem size that Section 4
+ * measures by hand): time candidate schedules and kernel options (pencil with and
  * without the persistent kernels, split long axes, other tiles, grouped
  * first passes; slab; volumetric) for a (n0, n1, n2) transform on the
  * current device, on `in`
@@ -265,8 +302,9 @@ int dft3d_autotune(int64_t n0, int64_t n1, int64_t n2, const void* in,
                    void* out, void* stream, int* best_schedule,
                    double* best_ms);
 
-/* Release the plan, its device tables and any plan-owned workspace.
- * NULL is accepted. */
+/* Release the plan, its device tables, any plan-owned workspace and the
+ * batched descriptor sets that use it (waiting for their last launch).
+ * NULL is accepted (DFT3D_OK). */
 int dft3d_destroy(dft3d_plan_t plan);
 
 #ifdef __cplusplus

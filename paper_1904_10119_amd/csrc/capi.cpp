@@ -20,6 +20,17 @@ bool fault(const char* what) {
   return e && std::strcmp(e, what) == 0;
 }
 
+// DFT3D_MAX_WORKSPACE_BYTES: plan-owned workspaces above this many bytes are
+// refused with DFT3D_ERR_OUT_OF_MEMORY instead of being allocated (a cap for
+// shared devices; also forces the out-of-memory path in tests).
+bool workspace_over_cap(size_t bytes) {
+  const char* e = std::getenv("DFT3D_MAX_WORKSPACE_BYTES");
+  if (!e || !*e) return false;
+  char* end = nullptr;
+  const unsigned long long cap = std::strtoull(e, &end, 10);
+  return end && *end == '\0' && bytes > cap;
+}
+
 int validate(int64_t n0, int64_t n1, int64_t n2, int schedule, int layout) {
   if (schedule < DFT3D_SCHED_AUTO || schedule > DFT3D_SCHED_VOLUMETRIC)
     return DFT3D_ERR_INVALID_ARG;
@@ -264,7 +275,8 @@ int ensure_workspace(dft3d_plan_s* p) {
     if (!p->ws_owned && p->ws) return DFT3D_ERR_WORKSPACE_TOO_SMALL;
     free_workspace(p);
     void* w = nullptr;
-    if (fault("alloc") || hipMalloc(&w, p->ws_need) != hipSuccess) {
+    if (fault("alloc") || workspace_over_cap(p->ws_need) ||
+        hipMalloc(&w, p->ws_need) != hipSuccess) {
       (void)hipGetLastError();
       return DFT3D_ERR_OUT_OF_MEMORY;
     }

@@ -138,7 +138,11 @@ __device__ __forceinline__ void leaf16(const LeafA<PREC>& A, const float (&xs)[8
     for (int k = 0; k < 8; ++k) m = fmaxf(m, fabsf(xs[k]));
     m = fmaxf(m, __shfl_xor(m, 16));
     m = fmaxf(m, __shfl_xor(m, 32));
-    const int e = m > 0.f ? __builtin_amdgcn_frexp_expf(m) : 0;  // m in [2^(e-1), 2^e)
+    // m in [2^(e-1), 2^e); e is kept at -100 or above so that the scale
+    // 2^(15 - e) stays finite (a vector below 2^-101 is scaled by 2^115:
+    // smaller than ideal, never inf or NaN)
+    int e = m > 0.f ? __builtin_amdgcn_frexp_expf(m) : 0;
+    e = e < -100 ? -100 : e;
     const float s = __builtin_amdgcn_ldexpf(1.0f, 15 - e);
     float xv[8];
 #pragma unroll

@@ -11,7 +11,9 @@ import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdft3d.so")
+# DFT3D_LIBRARY selects another build of the same library (the sanitizer
+# build of build.py --sanitize); the default is the in-tree libdft3d.so.
+LIB_PATH = os.environ.get("DFT3D_LIBRARY") or os.path.join(_HERE, "libdft3d.so")
 
 SCHEDULES = {"auto": 0, "slab": 1, "pencil": 2, "volumetric": 3}
 LAYOUTS = {"natural": 0, "shuffled": 1}

@@ -121,3 +121,49 @@ def test_one_tile_and_persistent_forms(precision, shape):
             p.close()
             assert oracle.rel_l2(outs[-1], ref) <= oracle.tol(x.size), (pers, sign)
         assert oracle.rel_l2(outs[0], outs[1]) <= oracle.tol(x.size)
+
+
+@pytest.mark.parametrize("precision", SPLIT)
+@pytest.mark.parametrize("scale", [0.0, 1e-30, 1e-36, 1e-41, 1e30])
+def test_split_extreme_magnitudes(precision, scale):
+    """The splits at the ends of the FP32 range: all-zero input, tiny
+    (1e-36 makes every 16-vector's largest component fall below 2^-101, where
+    the fp16 scale is capped), subnormal (1e-41) and huge inputs.  Outputs
+    are finite; down to 1e-36 they meet the FP32 tolerance relative to the
+    exact transform of the same (rounded) input, and the subnormal case is
+    checked against the output's size for fp16x3 (the input itself carries
+    only a few significant bits there)."""
+    shape = (8, 32, 64)
+    say("case extreme", precision, scale)
+    x = (inputs.uniform_c64(shape, 33).astype(np.complex128) * scale).astype(np.complex64)
+    y = run(x, precision)
+    assert np.isfinite(y.view(np.float32)).all(), (precision, scale)
+    ref = oracle.dft3d(x.astype(np.complex128), -1, "fft")
+    if scale == 0.0:
+        assert not y.any()
+        return
+    if scale >= 1e-36:
+        err = oracle.rel_l2(y, ref)
+        say("  ", err)
+        assert err <= oracle.tol(x.size), (precision, scale, err)
+    elif precision == "fp16x3":
+        # the scaled fp16 terms keep ~15 bits of these inputs
+        err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        say("  subnormal max error / max output", err)
+        assert err <= 1e-3, (precision, scale, err)
+    # bf16 terms of subnormal inputs may be flushed by the matrix cores:
+    # only finiteness is required there
+
+
+@pytest.mark.parametrize("precision", SPLIT)
+def test_split_zero_pencils_among_data(precision):
+    """Pencils that are exactly zero between ordinary ones (the fp16 scale's
+    zero branch, per 16-vector)."""
+    shape = (16, 16, 256)
+    x = inputs.uniform_c64(shape, 34)
+    x[:, ::3, :] = 0
+    x[::5] = 0
+    y = run(x, precision)
+    ref = oracle.dft3d(x.astype(np.complex128), -1, "fft")
+    assert np.isfinite(y.view(np.float32)).all()
+    assert oracle.rel_l2(y, ref) <= oracle.tol(x.size)
