@@ -23,7 +23,9 @@ The JSON line also carries:
                 every error in this line is measured against;
   configs       (unless --no-extras) the other workloads, each with its
                 error: 64^3 forward and inverse (latency), every schedule at
-                1024^3, every leaf precision at 256^3 and 1024^3, 96 uneven
+                1024^3, every leaf precision at 256^3 and 1024^3, the time
+                breakdown of every schedule at 1024^3 (full passes, passes
+                with the radix stages removed, plain copies), 96 uneven
                 problems batched (per pass level and in one persistent
                 launch) against one plan at a time, 2048 x 1024 x 512 auto
                 vs pencil, FP32 vs bf16x6 leaves, lengths that are not
@@ -393,6 +395,30 @@ def extras(x1024_host, refs):
         p.close()
     out["1024^3 pencil leaf precision"] = prec
     log(f"bench: 1024^3 precisions {prec}")
+
+    # time breakdown per schedule (the paper's split of a decomposition's
+    # time into communication, packing and local DFTs, on one device): the
+    # unfused pass list in full, with the radix stages removed (loads, LDS
+    # exchanges and stores only) and as plain copies of the array (the HBM
+    # floor of the same number of passes)
+    brk = {}
+    for s in ("pencil", "slab", "volumetric"):
+        ms = {}
+        for key, kw in (("full", {"fused_plane": 0, "fused_axes": 0}),
+                        ("move_only", {"move_only": 1}), ("copy", {"move_only": 2})):
+            p = dft3d.Plan((1024,) * 3, s, **kw)
+            ms[key] = timed(lambda: p.execute(x, y), 5)
+            n = p.num_passes
+            p.close()
+        brk[s] = {"passes": n, "full_ms": round(ms["full"], 3),
+                  "move_only_ms": round(ms["move_only"], 3), "copy_ms": round(ms["copy"], 3),
+                  "per_pass_ms": {k: round(v / n, 3) for k, v in ms.items()},
+                  "butterflies_share": round((ms["full"] - ms["move_only"]) / ms["full"], 3),
+                  "exchange_share": round((ms["move_only"] - ms["copy"]) / ms["full"], 3),
+                  "hbm_floor_share": round(ms["copy"] / ms["full"], 3),
+                  "copy_gbs": round(16.0 * N * n / (ms["copy"] * 1e-3) / 1e9, 1)}
+    out["1024^3 time breakdown (move-only passes)"] = brk
+    log(f"bench: 1024^3 breakdown {brk}")
     del x, y, z
     torch.cuda.empty_cache()
 

@@ -133,6 +133,20 @@ enum dft3d_option {
                                 launch for the whole batch, replayed from a
                                 HIP graph the library builds, used when every
                                 plan of the batch has 1 */
+  DFT3D_OPT_MOVE_ONLY = 12,  /* the data movement of a schedule alone, for
+                                the time breakdown the paper draws for its
+                                decompositions (Section 4.3: communication,
+                                packing and local DFTs): 0 = off (default);
+                                1 = every pass keeps its loads, LDS
+                                exchanges and stores with the radix stages
+                                (butterflies and twiddles) removed, so the
+                                output is a fixed permutation of the input;
+                                2 = every pass is a plain copy of the array
+                                (output = input), the HBM floor.  FP32,
+                                NATURAL layout, powers of two; fused plane,
+                                fused axes and grouped pencil passes are
+                                turned off (their unfused passes run);
+                                otherwise UNSUPPORTED_SCHEDULE */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

@@ -228,6 +228,10 @@ int apply_option(Options& o, int key, int64_t value) {
       if (value != 0 && value != 1) return DFT3D_ERR_INVALID_ARG;
       o.batch_launch = (int)value;
       return DFT3D_OK;
+    case DFT3D_OPT_MOVE_ONLY:
+      if (value < 0 || value > 2) return DFT3D_ERR_INVALID_ARG;
+      o.move_only = (int)value;
+      return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
   }
@@ -482,6 +486,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_FUSED_AXES: *value = p->opt.fused_axes; break;
     case DFT3D_OPT_PENCIL_GROUP: *value = p->opt.pencil_group; break;
     case DFT3D_OPT_BATCH_LAUNCH: *value = p->opt.batch_launch; break;
+    case DFT3D_OPT_MOVE_ONLY: *value = p->opt.move_only; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }

@@ -58,10 +58,16 @@ struct KernelInfo {
   int mixed = 0;      // > 0: mixed-radix pass in LDS for lengths up to n (the variant)
   int fixed_n = 0;              // mixed-radix pass compiled for this one length, 0: any
   uint64_t fixed_code = 0;      // and its radix code
+  int move_only = 0;  // 1: loads, LDS exchanges and stores of the pass with the radix
+                      // stages (butterflies and twiddles) removed; 2: a plain copy
+  int r0 = 0, r1 = 0, r2 = 0;   // FP32 pass kernels: the radix of each stage (1: none)
 };
 
 // All compiled pass kernels.
 const std::vector<KernelInfo>& kernel_registry();
+// The move-only form (mode 1: radix stages removed; mode 2: a plain copy of
+// the array) of an FP32 pass kernel, or null if none is compiled.
+const KernelInfo* find_move_only_kernel(const KernelInfo* k, int mode);
 const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle,
                               int persistent, int nontemporal);
 // The fused plane kernel for (n1, n2) planes, if compiled.
@@ -143,6 +149,7 @@ struct Options {
   int fused_axes = 1;  // volumetric: V2 of an axis and V1 of the next in one pass
   int pencil_group = 0; // pencil: planes per group of the first two passes (0 = all, -1 = auto)
   int batch_launch = 0; // batched calls: 0 one launch per pass level, 1 one persistent launch
+  int move_only = 0;    // 1: radix stages removed from every pass, 2: every pass a plain copy
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

@@ -111,9 +111,38 @@ __device__ __forceinline__ void leaf16(const LeafA<PREC>& A, const float (&xs)[8
                                        f32x4_t& yr, f32x4_t& yi) {
   constexpr int TERMS = LeafPolicy<PREC>::terms;
   const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
+  // Per-vector power-of-two scale (exact): the vector's 32 inputs sit in
+  // lanes l, l ^ 16, l ^ 32, l ^ 48; its largest component is brought to
+  // [2^14, 2^15).  fp16 terms need it for the format's range; bf16 terms
+  // share FP32's exponent range but need it for tiny vectors (below about
+  // 2^-100), whose residuals would otherwise fall into the subnormal range
+  // and lose bits or be flushed by the matrix cores.  The maximum over the
+  // four lanes comes from two lane swaps (v_permlane32_swap: lanes l and
+  // l ^ 32; v_permlane16_swap: rows 2j and 2j + 1, i.e. l and l ^ 16), no
+  // LDS round trip.  e is kept at -100 or above so that the scale
+  // 2^(15 - e) stays finite (a vector below 2^-101 is scaled by 2^115:
+  // smaller than ideal, never inf or NaN).
+  float m = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) m = fmaxf(m, fabsf(xs[k]));
+  {
+    const unsigned u = __builtin_bit_cast(unsigned, m);
+    const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    m = fmaxf(__builtin_bit_cast(float, (unsigned)h[0]), __builtin_bit_cast(float, (unsigned)h[1]));
+    const unsigned w = __builtin_bit_cast(unsigned, m);
+    const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+    m = fmaxf(__builtin_bit_cast(float, (unsigned)r[0]), __builtin_bit_cast(float, (unsigned)r[1]));
+  }
+  int e = m > 0.f ? __builtin_amdgcn_frexp_expf(m) : 0;  // m in [2^(e-1), 2^e)
+  e = e < -100 ? -100 : e;
+  const float sc = __builtin_amdgcn_ldexpf(1.0f, 15 - e);
+  const float inv = __builtin_amdgcn_ldexpf(1.0f, e - 15);
+  float xv[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) xv[k] = xs[k] * sc;
   if constexpr (!LeafPolicy<PREC>::fp16) {
     bf16x8_t b[3];
-    split_bf16<TERMS>(xs, b);
+    split_bf16<TERMS>(xv, b);
     f32x4_t r = z, i = z;
     if constexpr (PREC == DFT3D_PREC_BF16X9) {  // orders 4 and 3
       r = mfma_bf16(A.a[2][0], b[2], r); i = mfma_bf16(A.a[2][1], b[2], i);
@@ -128,25 +157,9 @@ __device__ __forceinline__ void leaf16(const LeafA<PREC>& A, const float (&xs)[8
       r = mfma_bf16(A.a[0][0], b[1], r); i = mfma_bf16(A.a[0][1], b[1], i);
     }
     r = mfma_bf16(A.a[0][0], b[0], r); i = mfma_bf16(A.a[0][1], b[0], i);
-    yr = r;
-    yi = i;
+    yr = r * inv;
+    yi = i * inv;
   } else {
-    // per-vector power-of-two scale: the vector's 32 inputs sit in lanes
-    // l, l ^ 16, l ^ 32, l ^ 48
-    float m = 0.f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) m = fmaxf(m, fabsf(xs[k]));
-    m = fmaxf(m, __shfl_xor(m, 16));
-    m = fmaxf(m, __shfl_xor(m, 32));
-    // m in [2^(e-1), 2^e); e is kept at -100 or above so that the scale
-    // 2^(15 - e) stays finite (a vector below 2^-101 is scaled by 2^115:
-    // smaller than ideal, never inf or NaN)
-    int e = m > 0.f ? __builtin_amdgcn_frexp_expf(m) : 0;
-    e = e < -100 ? -100 : e;
-    const float s = __builtin_amdgcn_ldexpf(1.0f, 15 - e);
-    float xv[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) xv[k] = xs[k] * s;
     f16x8_t b[3];
     split_f16<TERMS>(xv, b);
     f32x4_t r0 = z, i0 = z;
@@ -158,7 +171,6 @@ __device__ __forceinline__ void leaf16(const LeafA<PREC>& A, const float (&xs)[8
       i0 = i1 * (1.0f / 2048.0f);
     }
     r0 = mfma_f16(A.a[0][0], b[0], r0); i0 = mfma_f16(A.a[0][1], b[0], i0);
-    const float inv = __builtin_amdgcn_ldexpf(1.0f, e - 15);
     yr = r0 * inv;
     yi = i0 * inv;
   }

@@ -118,9 +118,12 @@ __device__ __forceinline__ void store_c64(float2* p, float2 v, bool nt) {
   }
 }
 
-template <int N, int E, int P, int NS, int R>
+// MV (move only): the stage is left out (no twiddles, no butterflies), so a
+// pass moves its data exactly as the full pass does and nothing else.
+template <int N, int E, int P, int NS, int R, bool MV = false>
 __device__ __forceinline__ void radix_stage(float2 (&v)[E], int p,
                                             const float2* __restrict__ tw) {
+  if constexpr (MV) return;
   constexpr int U = E / R;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -168,8 +171,11 @@ __device__ __forceinline__ void lds_exchange(float2 (&v)[E], float2* lds, int ti
 // Streaming (non-temporal) accesses of a pass kernel, by its NT parameter:
 // 0 none, 1 loads and stores, 2 loads only, 3 stores only.  The one-sided
 // forms serve passes whose other side is meant to stay in the caches.
-constexpr bool nt_loads(int nt) { return nt == 1 || nt == 2; }
-constexpr bool nt_stores(int nt) { return nt == 1 || nt == 3; }
+// Bit 2 of NT (NT = 4..7) selects the move-only form of a pass kernel:
+// the same loads, LDS exchanges and stores with the radix stages removed.
+constexpr bool nt_loads(int nt) { return (nt & 3) == 1 || (nt & 3) == 2; }
+constexpr bool nt_stores(int nt) { return (nt & 3) == 1 || (nt & 3) == 3; }
+constexpr bool move_only(int nt) { return (nt & 4) != 0; }
 
 template <int N, int T, int E, int P, int LM, int NT>
 __device__ __forceinline__ void load_tile(float2 (&v)[E], const float2* src, const PassArgs& a,
@@ -192,22 +198,23 @@ __device__ __forceinline__ void transform_store_tile(float2 (&v)[E], float2* dst
                                                      int64_t tile, int tid, int q, int p) {
   constexpr int NST = num_stages<BL>();
   constexpr int R0 = BL::R0, R1 = BL::R1, R2 = BL::R2;
+  constexpr bool MV = move_only(NT);
   // inverse as conj(DFT(conj(x))); applied here, where the tile is first
   // used, so that a prefetched tile is not waited for early
   if (a.conj_in) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
   }
-  radix_stage<N, E, P, 1, R0>(v, p, tw);
+  radix_stage<N, E, P, 1, R0, MV>(v, p, tw);
   if constexpr (NST == 2) {
     lds_exchange<N, E, P, T, SQ, 1, R0, SM>(v, lds, tid, q, p);
-    radix_stage<N, E, P, R0, R1>(v, p, tw);
+    radix_stage<N, E, P, R0, R1, MV>(v, p, tw);
   } else if constexpr (NST == 3) {
     lds_exchange<N, E, P, T, SQ, 1, R0, MODE_ROW>(v, lds, tid, q, p);
-    radix_stage<N, E, P, R0, R1>(v, p, tw);
+    radix_stage<N, E, P, R0, R1, MV>(v, p, tw);
     __syncthreads();  // every read of the first exchange is done
     lds_exchange<N, E, P, T, SQ, R0, R1, SM>(v, lds, tid, q, p);
-    radix_stage<N, E, P, R0 * R1, R2>(v, p, tw);
+    radix_stage<N, E, P, R0 * R1, R2, MV>(v, p, tw);
   }
   const int64_t b = tile * T + q;
   if (b < a.B) {
@@ -219,7 +226,7 @@ __device__ __forceinline__ void transform_store_tile(float2 (&v)[E], float2* dst
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = p + P * e;
-      if constexpr (TW) v[e] = cmul(v[e], twp[(res * k) & a.twp_mask]);
+      if constexpr (TW && !MV) v[e] = cmul(v[e], twp[(res * k) & a.twp_mask]);
       if (a.conj_out) v[e].y = -v[e].y;
     }
 #pragma unroll
@@ -348,14 +355,24 @@ hipError_t launch_persistent(const PassArgs& a, const float2* src, float2* dst,
   return hipGetLastError();
 }
 
+template <class BL>
+void set_radices(KernelInfo& k) {
+  k.r0 = BL::R0;
+  k.r1 = BL::R1;
+  k.r2 = BL::R2;
+}
+
 template <int N, int T, int LM, int SM, int TW, int NT, class BL>
 KernelInfo kernel_info_persistent() {
   constexpr int E = BL::E;
   constexpr int SQ = lds_pencil_stride<N, T>();
   constexpr int LDS = (T * SQ + N) * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
-  return KernelInfo{N, T, LM, SM, TW, T * (N / E), LDS,
-                    &launch_persistent<N, T, LM, SM, TW, NT, BL>, 1, NT};
+  KernelInfo k{N, T, LM, SM, TW, T * (N / E), LDS,
+               &launch_persistent<N, T, LM, SM, TW, NT, BL>, 1, NT & 3};
+  k.move_only = move_only(NT) ? 1 : 0;
+  set_radices<BL>(k);
+  return k;
 }
 
 template <int N, int T, int LM, int SM, int TW, int NT>
@@ -365,8 +382,11 @@ KernelInfo kernel_info() {
   constexpr int LDS = num_stages<Blocking<N>>() > 1 ? T * SQ * 8 : 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(T * (N / E) <= 1024, "workgroup too large");
-  return KernelInfo{N, T, LM, SM, TW, T * (N / E), LDS, &launch_pass<N, T, LM, SM, TW, NT>, 0,
-                    NT};
+  KernelInfo k{N, T, LM, SM, TW, T * (N / E), LDS, &launch_pass<N, T, LM, SM, TW, NT>, 0,
+               NT & 3};
+  k.move_only = move_only(NT) ? 1 : 0;
+  set_radices<Blocking<N>>(k);
+  return k;
 }
 
 // All four layout combinations used by the schedules for one (N, T):
@@ -381,10 +401,14 @@ void add_kernels_nt(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info<N, T, MODE_COL, MODE_COL, 0, NT>());
   v.push_back(kernel_info<N, T, MODE_COL, MODE_COL, 1, NT>());
 }
+// With their move-only forms (NT + 4): the same data movement without the
+// radix stages, for the time breakdown of a pass.
 template <int N, int T>
 void add_kernels(std::vector<KernelInfo>& v) {
   add_kernels_nt<N, T, 0>(v);
   add_kernels_nt<N, T, 1>(v);
+  add_kernels_nt<N, T, 4>(v);
+  add_kernels_nt<N, T, 5>(v);
 }
 
 // ROW->ROW with the four-step twiddle: the first half of a split axis whose
@@ -405,6 +429,65 @@ template <int N, int T, class BL = Blocking<N>>
 void add_persistent_kernels(std::vector<KernelInfo>& v) {
   add_persistent_kernels_nt<N, T, 0, BL>(v);
   add_persistent_kernels_nt<N, T, 1, BL>(v);
+  add_persistent_kernels_nt<N, T, 4, BL>(v);
+  add_persistent_kernels_nt<N, T, 5, BL>(v);
+}
+
+// A plain copy of the B * N points of a pass from src to dst (streaming
+// 16-byte accesses, two points each, or 8-byte ones for an odd point count;
+// grid-stride loop): the HBM floor a pass of that size can reach, used by
+// the move-only option's copy mode.
+template <class V>
+__global__ void __launch_bounds__(256)
+copy_pass_kernel(const V* __restrict__ src, V* __restrict__ dst, int64_t count) {
+  // chunks of 256 x 8 elements: each thread issues its 8 loads before its
+  // stores, every load and store instruction coalesced across the wave
+  constexpr int U = 8;
+  const int64_t chunks = (count + 256 * U - 1) / (256 * U);
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int64_t base = c * 256 * U + threadIdx.x;
+    V x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * 256;
+      if (i < count) x[u] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * 256;
+      if (i < count) __builtin_nontemporal_store(x[u], dst + i);
+    }
+  }
+}
+
+template <int N>
+hipError_t launch_copy(const PassArgs& a, const float2* src, float2* dst, const float2*,
+                       const float2*, hipStream_t stream) {
+  const int64_t count = a.B * N;
+  if (count <= 0) return hipSuccess;
+  const int64_t cap = (int64_t)device_cu_count() * 32;
+  if (count % 2 == 0) {
+    int64_t blocks = (count / 2 + 2047) / 2048;
+    if (blocks > cap) blocks = cap;
+    using V16 = float __attribute__((ext_vector_type(4)));
+    hipLaunchKernelGGL(copy_pass_kernel<V16>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       reinterpret_cast<const V16*>(src), reinterpret_cast<V16*>(dst),
+                       count / 2);
+  } else {
+    int64_t blocks = (count + 2047) / 2048;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(copy_pass_kernel<unsigned long long>, dim3((unsigned)blocks), dim3(256),
+                       0, stream, reinterpret_cast<const unsigned long long*>(src),
+                       reinterpret_cast<unsigned long long*>(dst), count);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+KernelInfo kernel_info_copy() {
+  KernelInfo k{N, 0, MODE_ROW, MODE_ROW, 0, 256, 0, &launch_copy<N>, 0, 1};
+  k.move_only = 2;
+  return k;
 }
 
 // Rotate-on-write passes with one streaming side: the first two passes of

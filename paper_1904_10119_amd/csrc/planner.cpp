@@ -97,7 +97,7 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw &&
         k.persistent == 0 && k.nontemporal == nt && k.precision == 0 && k.plane_rows == 0 &&
-        k.fused_axes == 0 && k.bluestein == 0)
+        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.move_only == 0)
       return &k;
   return nullptr;
 }
@@ -518,11 +518,23 @@ void assign_chain(std::vector<Pass>& passes, size_t first, size_t& ws_needed_fla
 
 }  // namespace
 
-int build_passes(const int64_t n[3], int schedule, int layout, const Options& opt,
+int build_passes(const int64_t n[3], int schedule, int layout, const Options& given,
                  std::vector<Pass>& passes, size_t& ws_bytes, int& resolved,
                  bool from_layout) {
   passes.clear();
   ws_bytes = 0;
+  // Move-only plans (the time breakdown of Section 4.3 on one device): the
+  // schedule's passes with unfused kernels, each replaced by its form
+  // without radix stages (1) or by a plain copy (2); FP32, natural layout,
+  // powers of two.
+  Options opt = given;
+  if (opt.move_only) {
+    if (opt.precision != DFT3D_PREC_FP32 || layout != DFT3D_LAYOUT_NATURAL)
+      return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+    opt.fused_plane = 0;
+    opt.fused_axes = 0;
+    opt.pencil_group = 0;
+  }
   // powers of two up to 4096; other lengths through the mixed-radix or the
   // Bluestein pass (pencil schedule, FP32, natural layout only)
   bool any_other = false;
@@ -691,6 +703,21 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& op
     passes.clear();
     return b.status;
   }
+  if (opt.move_only) {
+    if (any_other) {
+      passes.clear();
+      return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+    }
+    for (Pass& ps : passes) {
+      const KernelInfo* m = find_move_only_kernel(ps.k, opt.move_only);
+      if (!m) {
+        passes.clear();
+        return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+      }
+      ps.k = m;
+      ps.label += opt.move_only == 1 ? " move-only" : " copy";
+    }
+  }
   ws_bytes = need_ws ? (size_t)total * 8 : 0;
   return DFT3D_OK;
 }
@@ -709,11 +736,16 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << ",\"nontemporal\":" << p.k->nontemporal << ",\"precision\":" << p.k->precision
        << ",\"plane_rows\":" << p.k->plane_rows << ",\"fused_axes\":" << p.k->fused_axes
        << ",\"bluestein\":" << p.k->bluestein << ",\"bl_n\":" << p.bl_n
-       << ",\"mixed\":" << p.k->mixed << ",\"fixed_n\":" << p.k->fixed_n << ",\"radices\":[";
+       << ",\"mixed\":" << p.k->mixed << ",\"fixed_n\":" << p.k->fixed_n
+       << ",\"move_only\":" << p.k->move_only << ",\"radices\":[";
     if (p.k->mixed) {  // the stage radices, first stage first
       bool first = true;
       for (uint64_t c = (uint64_t)p.args.twp_mask; c; c >>= 8, first = false)
         os << (first ? "" : ",") << (c & 255);
+    } else if (p.k->r0 > 0) {  // FP32 pass kernels: their radix stages
+      os << p.k->r0;
+      if (p.k->r1 > 1) os << "," << p.k->r1;
+      if (p.k->r2 > 1) os << "," << p.k->r2;
     }
     os << "]"
        << ",\"threads\":" << p.k->threads

@@ -44,8 +44,24 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
         k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0 &&
-        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0)
+        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.move_only == 0)
       return &k;
+  return nullptr;
+}
+
+const KernelInfo* find_move_only_kernel(const KernelInfo* k, int mode) {
+  if (!k || k->precision || k->plane_rows || k->fused_axes || k->bluestein || k->mixed ||
+      k->move_only)
+    return nullptr;
+  for (const KernelInfo& c : kernel_registry()) {
+    if (c.move_only != mode) continue;
+    if (mode == 2 && c.n == k->n) return &c;
+    if (mode == 1 && c.n == k->n && c.tile == k->tile && c.lmode == k->lmode &&
+        c.smode == k->smode && c.post_twiddle == k->post_twiddle &&
+        c.persistent == k->persistent && c.nontemporal == k->nontemporal &&
+        c.r0 == k->r0 && c.r1 == k->r1 && c.r2 == k->r2)
+      return &c;
+  }
   return nullptr;
 }
 

@@ -128,7 +128,9 @@ def test_one_tile_and_persistent_forms(precision, shape):
 def test_split_extreme_magnitudes(precision, scale):
     """The splits at the ends of the FP32 range: all-zero input, tiny
     (1e-36 makes every 16-vector's largest component fall below 2^-101, where
-    the fp16 scale is capped), subnormal (1e-41) and huge inputs.  Outputs
+    the per-vector power-of-two scale is capped; unscaled, the bf16 residuals
+    of such inputs fell into the subnormal range: 4.6e-5 rel_l2 for bf16x6),
+    subnormal (1e-41) and huge inputs.  Outputs
     are finite; down to 1e-36 they meet the FP32 tolerance relative to the
     exact transform of the same (rounded) input, and the subnormal case is
     checked against the output's size for fp16x3 (the input itself carries

@@ -552,3 +552,111 @@ def test_grouped_pencil_computes_the_dft(shape, group):
     check_pass_maps(d, x.size)
     for sign in (-1, 1):
         assert oracle.rel_l2(run_model(x, d, sign), oracle.dft3d(x, sign, "fft")) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Move-only plans (DFT3D_OPT_MOVE_ONLY): the passes' data movement alone.
+
+def stockham_identity_perm(n, radices):
+    """The Stockham stage maps of the pass kernels (input t + r n/R of the
+    radix-R stage after ns goes to (t div ns) ns R + (t mod ns) + r ns) with
+    every butterfly and twiddle removed: out[k] = in[perm[k]]."""
+    src = np.arange(n)
+    ns = 1
+    for R in radices:
+        nr = n // R
+        out = np.empty_like(src)
+        t = np.arange(nr)
+        for r in range(R):
+            out[(t // ns) * ns * R + (t % ns) + r * ns] = src[t + r * nr]
+        src = out
+        ns *= R
+    assert ns == n
+    return src
+
+
+def run_move_model(x, d, sign=-1):
+    """Run a move-only (1) or copy (2) pass list on x, as the kernels move
+    data: per pencil the identity-butterfly permutation, or a flat copy."""
+    n_total = x.size
+    n_ws = max(n_total, d["workspace_bytes"] // 8)
+    bufs = {"in": x.reshape(-1).copy(),
+            "out": np.full(n_total, np.nan, x.dtype),
+            "ws": np.full(n_ws, np.nan, x.dtype)}
+    passes = d["passes"]
+    for i, p in enumerate(passes):
+        a = p["args"]
+        if p["move_only"] == 2:
+            m = a["B"] * p["n"]
+            bufs[p["dst"]][p["out_off"]:p["out_off"] + m] = \
+                bufs[p["src"]][p["in_off"]:p["in_off"] + m]
+            continue
+        assert p["move_only"] == 1
+        ia = addresses(a, p["n"], True)
+        oa = addresses(a, p["n"], False)
+        v = bufs[p["src"]][ia + p["in_off"]]
+        if sign == 1 and p["src"] == "in":
+            v = np.conj(v)
+        y = v[:, stockham_identity_perm(p["n"], p["radices"])]
+        if sign == 1 and i == len(passes) - 1:
+            y = np.conj(y)
+        bufs[p["dst"]][oa + p["out_off"]] = y
+    return bufs["out"].reshape(x.shape)
+
+
+def test_power_of_two_stage_radices_compute_the_dft():
+    """The radix lists the FP32 pass kernels report, run through the same
+    Stockham stage formulas with their butterflies and twiddles, give the
+    DFT: the stage maps the move-only model uses are the kernels' own."""
+    seen = set()
+    for lg in range(1, 13):
+        n = 1 << lg
+        for shape in ((1, 1, n), (1, n, 2), (n, 2, 2)):
+            for sch in ("pencil", "slab"):
+                for p in dft3d.describe(shape, sch, fused_plane=0)["passes"]:
+                    key = (p["n"], tuple(p["radices"]))
+                    if p["n"] < 2 or key in seen:
+                        continue
+                    seen.add(key)
+                    assert int(np.prod(p["radices"])) == p["n"], p
+                    x = np.random.default_rng(p["n"]).standard_normal(p["n"]) * (1 + 1j)
+                    got = stockham_mixed(x, p["radices"])
+                    assert oracle.rel_l2(got, np.fft.fft(x)) < 1e-12, key
+    assert len(seen) >= 12
+
+
+@pytest.mark.parametrize("shape", [(2, 4, 8), (16, 16, 16), (32, 4, 64), (4, 64, 2),
+                                   (64, 32, 16), (2048, 2, 4), (1, 1, 1)])
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("mode", [1, 2])
+def test_move_only_plans(shape, schedule, mode):
+    """Move-only plans: every pass has a move-only kernel, the maps stay in
+    bounds, the output is a permutation of the input (mode 1) or the input
+    itself (mode 2), forward and inverse alike."""
+    d = dft3d.describe(shape, schedule, move_only=mode)
+    assert all(p["move_only"] == mode for p in d["passes"])
+    assert not any(p["plane_rows"] or p["fused_axes"] for p in d["passes"])
+    N = shape[0] * shape[1] * shape[2]
+    check_pass_maps(d, N)
+    g = np.random.default_rng(N)
+    x = (g.standard_normal(shape) + 1j * g.standard_normal(shape)).astype(np.complex64)
+    for sign in (-1, 1):
+        y = run_move_model(x, d, sign)
+        if mode == 2:
+            assert np.array_equal(y, x)
+        else:
+            assert np.array_equal(np.sort_complex(y.reshape(-1)), np.sort_complex(x.reshape(-1)))
+    # the same passes as the full plan, in the same buffers
+    full = dft3d.describe(shape, schedule, fused_plane=0, fused_axes=0)["passes"]
+    assert [(p["src"], p["dst"], p["n"], p["args"]) for p in d["passes"]] == \
+        [(p["src"], p["dst"], p["n"], p["args"]) for p in full]
+
+
+def test_move_only_limits():
+    for opts in ({"move_only": 1, "precision": "bf16x6"}, {"move_only": 3}):
+        with pytest.raises(dft3d.Dft3dError):
+            dft3d.describe((64, 64, 64), "pencil", **opts)
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((100, 64, 64), "pencil", move_only=1)
+    with pytest.raises(dft3d.Dft3dError):
+        dft3d.describe((64, 64, 64), "volumetric", "shuffled", move_only=1)
