@@ -15,6 +15,11 @@
 // [m][j], j = c + C (kk + K l').  Stage 2: thread = one column j -> the a
 // rows from LDS -> DFT_a -> twiddle -> store.
 //
+// SHUF = 1 (the shuffled layout, Section 2.4): axis d's final exchange is
+// left out, so output l' of run k' stays where its input run lay, at axis
+// position a k' + l' (the pass's run field has equal input and output
+// strides); axis d-1 is written as in natural order.
+//
 // PassArgs fields used: tile t splits into f0 = t & m0, f1 = (t >> s0) & m1
 // (the residue r'), f2 = t >> s1; tile bases f0 is0 + f1 is1 + f2 is2 (in)
 // and f0 os0 + f1 os1 + f2 os2 (out); ijs = row step A' * S_{d-1}; oks =
@@ -66,7 +71,7 @@ __device__ __forceinline__ void fused_stage1(float2 (&v)[A], float2* lds, int co
 }
 
 // Stage 2: column j = tid over the a rows, DFT, twiddle w_{n'}^{r' k2}, store.
-template <int A, int KC, int CONTIG>
+template <int A, int KC, int CONTIG, int SHUF>
 __device__ __forceinline__ void fused_stage2(const float2* lds, float2* dst,
                                              const float2* __restrict__ twp, const PassArgs& a,
                                              const FusedTile& ft, int tid) {
@@ -77,7 +82,8 @@ __device__ __forceinline__ void fused_stage2(const float2* lds, float2* dst,
   for (int m = 0; m < A; ++m) v[m] = lds[m * fused_row<A, KC>() + lds_pad_index(tid)];
   dft<A>(v);
   const int c = tid % C, kk = (tid / C) % K, lp = tid / KC;
-  float2* d = dst + ft.out_base + (kk + a.res_mask * lp) * a.oks + c;
+  const int64_t pos = SHUF ? (int64_t)kk * A + lp : kk + a.res_mask * lp;
+  float2* d = dst + ft.out_base + pos * a.oks + c;
 #pragma unroll
   for (int k2 = 0; k2 < A; ++k2) {
     float2 w = cmul(v[k2], twp[(ft.r * k2) & a.twp_mask]);
@@ -87,7 +93,7 @@ __device__ __forceinline__ void fused_stage2(const float2* lds, float2* dst,
 }
 
 // One tile per workgroup.
-template <int A, int KC, int CONTIG>
+template <int A, int KC, int CONTIG, int SHUF>
 __global__ void __launch_bounds__(A* KC)
 fft_fused_axes_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
                       const float2* __restrict__ twp, const PassArgs a) {
@@ -98,7 +104,7 @@ fft_fused_axes_kernel(const float2* src, float2* dst, const float2* __restrict__
   fused_load<A, KC, CONTIG>(v, src, a, ft, tid);
   fused_stage1<A, KC, CONTIG>(v, lds, a.conj_in, tid);
   __syncthreads();
-  fused_stage2<A, KC, CONTIG>(lds, dst, twp, a, ft, tid);
+  fused_stage2<A, KC, CONTIG, SHUF>(lds, dst, twp, a, ft, tid);
 }
 
 // Persistent form: about one workgroup per CU walks the tiles w, w + G, ...
@@ -106,7 +112,7 @@ fft_fused_axes_kernel(const float2* src, float2* dst, const float2* __restrict__
 // tile's first stage has left them, so the loads are in flight during the
 // second stage and the stores.  Past the last tile the prefetch re-reads
 // the last tile (in bounds).
-template <int A, int KC, int CONTIG>
+template <int A, int KC, int CONTIG, int SHUF>
 __global__ void __launch_bounds__(A* KC)
 fft_fused_axes_persistent(const float2* src, float2* dst, const float2* __restrict__ tw,
                           const float2* __restrict__ twp, const PassArgs a) {
@@ -122,26 +128,26 @@ fft_fused_axes_persistent(const float2* src, float2* dst, const float2* __restri
     __syncthreads();
     const int64_t wn = w + G;
     fused_load<A, KC, CONTIG>(v, src, a, fused_tile(wn < last ? wn : last, a), tid);
-    fused_stage2<A, KC, CONTIG>(lds, dst, twp, a, fused_tile(w, a), tid);
+    fused_stage2<A, KC, CONTIG, SHUF>(lds, dst, twp, a, fused_tile(w, a), tid);
     __syncthreads();  // every read of the tile is done before the next writes
     w = wn;
     if (w >= ntiles) break;
   }
 }
 
-template <int A, int KC, int CONTIG>
+template <int A, int KC, int CONTIG, int SHUF>
 hipError_t launch_fused_axes(const PassArgs& a, const float2* src, float2* dst,
                              const float2* tw, const float2* twp, hipStream_t stream) {
   if (a.B <= 0) return hipSuccess;
   if (a.B > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((fft_fused_axes_kernel<A, KC, CONTIG>), dim3((unsigned)a.B), dim3(A * KC),
-                     0, stream, src, dst, tw, twp, a);
+  hipLaunchKernelGGL((fft_fused_axes_kernel<A, KC, CONTIG, SHUF>), dim3((unsigned)a.B),
+                     dim3(A * KC), 0, stream, src, dst, tw, twp, a);
   return hipGetLastError();
 }
 
 int device_cu_count();
 
-template <int A, int KC, int CONTIG>
+template <int A, int KC, int CONTIG, int SHUF>
 hipError_t launch_fused_axes_persistent(const PassArgs& a, const float2* src, float2* dst,
                                         const float2* tw, const float2* twp,
                                         hipStream_t stream) {
@@ -150,28 +156,28 @@ hipError_t launch_fused_axes_persistent(const PassArgs& a, const float2* src, fl
   if (per_cu < 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, fft_fused_axes_persistent<A, KC, CONTIG>, A * KC, 0) != hipSuccess)
+            &nb, fft_fused_axes_persistent<A, KC, CONTIG, SHUF>, A * KC, 0) != hipSuccess)
       return hipGetLastError();
     per_cu = nb > 0 ? nb : 1;
   }
   int64_t grid = (int64_t)device_cu_count() * per_cu;
   if (grid > a.B) grid = a.B;
-  hipLaunchKernelGGL((fft_fused_axes_persistent<A, KC, CONTIG>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((fft_fused_axes_persistent<A, KC, CONTIG, SHUF>), dim3((unsigned)grid),
                      dim3(A * KC), 0, stream, src, dst, tw, twp, a);
   return hipGetLastError();
 }
 
-template <int A, int KC, int CONTIG, int PERS>
+template <int A, int KC, int CONTIG, int PERS, int SHUF = 0>
 KernelInfo kernel_info_fused_axes() {
   constexpr int LDS = A * fused_row<A, KC>() * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
   static_assert(A * KC <= 1024, "workgroup too large");
   const int mode = CONTIG ? MODE_ROW : MODE_COL;
   KernelInfo k{A, KC, mode, mode, 1, A * KC, LDS,
-               PERS ? &launch_fused_axes_persistent<A, KC, CONTIG>
-                    : &launch_fused_axes<A, KC, CONTIG>,
+               PERS ? &launch_fused_axes_persistent<A, KC, CONTIG, SHUF>
+                    : &launch_fused_axes<A, KC, CONTIG, SHUF>,
                PERS, 0, 0};
-  k.fused_axes = 1;
+  k.fused_axes = SHUF ? 2 : 1;
   return k;
 }
 

@@ -308,26 +308,30 @@ void volumetric_v2(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis
 // is [outer][n_prev][n][inner] with outer == 1 unless the V2 runs are
 // contiguous (inner == 1).
 bool volumetric_fused(Builder& b, int64_t outer, int64_t n_prev, int64_t n, int64_t inner,
-                      int axis, int persistent) {
+                      int axis, int persistent, bool shuffled) {
   int64_t A, Bf, Ap, Bp;
   split_axis(n, A, Bf);
   split_axis(n_prev, Ap, Bp);
   if (A != Bp) return false;
   const int contig = inner == 1;
-  const KernelInfo* k = find_fused_axes_kernel((int)A, contig, persistent);
+  const KernelInfo* k = find_fused_axes_kernel((int)A, contig, persistent, shuffled ? 1 : 0);
   if (!k) return false;
   const int64_t KC = k->tile;
   const int64_t sd = inner, sprev = n * inner, so = n_prev * sprev;
   char lab[64];
-  std::snprintf(lab, sizeof lab, "vol%d.V2+vol%d.V1 DFT%lldx%lld", axis, axis - 1,
-                (long long)A, (long long)Bp);
+  std::snprintf(lab, sizeof lab, "vol%d.V2+vol%d.V1 DFT%lldx%lld%s", axis, axis - 1,
+                (long long)A, (long long)Bp, shuffled ? " shuffled" : "");
+  // the run field: natural output k + b l' (runs KC apart at stride 1),
+  // shuffled output a k' + l' where the run was read (same stride as in)
   if (contig) {
     if (Bf % KC) return false;
-    Field f[3] = {{Bf / KC, KC * A * sd, KC * sd}, {Ap, sprev, sprev}, {outer, so, so}};
+    Field f[3] = {{Bf / KC, KC * A * sd, shuffled ? KC * A * sd : KC * sd},
+                  {Ap, sprev, sprev}, {outer, so, so}};
     b.add_fused(k, f, Ap * sprev, sd, Bf, n_prev, (int)A, lab);
   } else {
     if (outer != 1 || inner % KC) return false;
-    Field f[3] = {{inner / KC, KC, KC}, {Ap, sprev, sprev}, {Bf, A * sd, sd}};
+    Field f[3] = {{inner / KC, KC, KC}, {Ap, sprev, sprev},
+                  {Bf, A * sd, shuffled ? A * sd : sd}};
     b.add_fused(k, f, Ap * sprev, sd, Bf, n_prev, (int)A, lab);
   }
   return true;
@@ -640,9 +644,11 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
       if (b.status == DFT3D_OK) passes.back().src = passes.back().dst = BUF_OUT;
     }
   } else {  // VOLUMETRIC
-    // natural FP32 plans fuse V2 of an axis with V1 of the next where the
-    // split factors match (four passes instead of six for 256^3, 1024^3)
-    const bool fuse = opt.fused_axes && !shuffled && opt.precision == DFT3D_PREC_FP32;
+    // FP32 plans fuse V2 of an axis with V1 of the next where the split
+    // factors match (four passes instead of six for 256^3, 1024^3)
+    // (the shuffled forward list too: its fused passes leave the finished
+    // axis in digit order; the inverse from the shuffled order is unfused)
+    const bool fuse = opt.fused_axes && !from_layout && opt.precision == DFT3D_PREC_FP32;
     int pending = -1;  // axis whose V2 is still to come
     auto dims = [&n](int axis, int64_t& outer, int64_t& inner) {
       outer = 1;
@@ -673,7 +679,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
           // it measured no faster (15.0 vs 14.7 ms for the schedule), the
           // one-tile form's workgroup turnover already overlaps the phases
           const int pers = opt.persistent && opt.nontemporal == 1;
-          if (volumetric_fused(b, outer, n[axis], n[pending], pin, pending, pers)) {
+          if (volumetric_fused(b, outer, n[axis], n[pending], pin, pending, pers, shuffled)) {
             pending = axis;
             continue;
           }

@@ -57,7 +57,10 @@ def fused_tiles(p):
     c = np.arange(C)[None, None, None, :, None]
     l = np.arange(A)[None, None, None, None, :]
     ia = ib[:, None, None, None, None] + m * RM + (kk * A + l) * SD + c
-    oa = ob[:, None, None, None, None] + m * RM + (kk + b * l) * SD + c
+    if p["fused_axes"] == 2:   # shuffled: output l' of run k' where the run was read
+        oa = ob[:, None, None, None, None] + m * RM + (kk * A + l) * SD + c
+    else:
+        oa = ob[:, None, None, None, None] + m * RM + (kk + b * l) * SD + c
     return ia, oa, f1
 
 
@@ -223,7 +226,7 @@ SHUFFLED_SHAPES = [(1, 1, 1), (2, 4, 8), (8, 2, 4), (16, 16, 16), (32, 4, 64), (
                    (2, 256, 8), (64, 1, 32), (4096, 2, 1), (1, 2, 2048), (8, 16, 32)]
 
 
-@pytest.mark.parametrize("shape", SHUFFLED_SHAPES)
+@pytest.mark.parametrize("shape", SHUFFLED_SHAPES + [(2, 256, 256), (256, 256, 32)])
 @pytest.mark.parametrize("schedule", ["volumetric", "auto"])
 def test_shuffled_pass_lists(shape, schedule):
     """Forward list: natural input to the documented shuffled order; inverse
