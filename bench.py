@@ -605,6 +605,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--shape", default="1024,1024,1024")
     ap.add_argument("--schedule", default="auto")
+    ap.add_argument("--layout", default="natural",
+                    help="layout of the timed plan (natural, shuffled)")
     ap.add_argument("--precision", default="fp32",
                     help="leaf arithmetic of the timed plan (fp32, bf16x6, ...)")
     ap.add_argument("--no-extras", action="store_true",
@@ -628,7 +630,8 @@ def main():
     flops = 5.0 * N * math.log2(N)
     log(f"bench: generating {shape} input")
     x_host = inputs.uniform_c64(shape, 2)
-    default = shape == (1024, 1024, 1024) and args.precision == "fp32"
+    default = (shape == (1024, 1024, 1024) and args.precision == "fp32" and
+               args.layout == "natural")
     base, refs = (None, {})
     if not args.no_cpu_baseline and default:
         log("bench: CPU leg (FP64 oracle: baseline timing and references)")
@@ -636,9 +639,9 @@ def main():
     x = torch.from_numpy(x_host).cuda()
     out = torch.empty_like(x)
 
-    plan = dft3d.Plan(shape, args.schedule, precision=args.precision)
+    plan = dft3d.Plan(shape, args.schedule, layout=args.layout, precision=args.precision)
     npass = plan.num_passes
-    desc = dft3d.describe(shape, args.schedule, precision=args.precision)
+    desc = dft3d.describe(shape, args.schedule, args.layout, precision=args.precision)
     log(f"bench: schedule {desc['schedule']} passes "
         f"{[p['label'] for p in desc['passes']]}")
     ms, wall, per = time_plan(plan, x, out, args.steps, args.warmup)

@@ -54,8 +54,19 @@ __device__ __forceinline__ void fused_load(float2 (&v)[A], const float2* src, co
   for (int l = 0; l < A; ++l) v[l] = s[l * a.oks];
 }
 
+// Column j of the LDS tile holding output l' of run (c, kk): natural order
+// runs kk fastest after c (a stage-2 wave then stores consecutive kk, which
+// are consecutive along axis d); the shuffled order runs l' fastest after c
+// (consecutive l' are consecutive along axis d there).
+template <int A, int KC, int CONTIG, int SHUF>
+__device__ __forceinline__ int fused_column(int c, int kk, int lp) {
+  constexpr int K = CONTIG ? KC : 1;
+  constexpr int C = CONTIG ? 1 : KC;
+  return SHUF ? c + C * (lp + A * kk) : c + C * (kk + K * lp);
+}
+
 // Stage 1: DFT_a over l in registers, results to the LDS tile [m][j].
-template <int A, int KC, int CONTIG>
+template <int A, int KC, int CONTIG, int SHUF>
 __device__ __forceinline__ void fused_stage1(float2 (&v)[A], float2* lds, int conj, int tid) {
   constexpr int K = CONTIG ? KC : 1;
   constexpr int C = CONTIG ? 1 : KC;
@@ -67,7 +78,8 @@ __device__ __forceinline__ void fused_stage1(float2 (&v)[A], float2* lds, int co
   dft<A>(v);
   float2* row = lds + m * fused_row<A, KC>();
 #pragma unroll
-  for (int lp = 0; lp < A; ++lp) row[lds_pad_index(c + C * (kk + K * lp))] = v[lp];
+  for (int lp = 0; lp < A; ++lp)
+    row[lds_pad_index(fused_column<A, KC, CONTIG, SHUF>(c, kk, lp))] = v[lp];
 }
 
 // Stage 2: column j = tid over the a rows, DFT, twiddle w_{n'}^{r' k2}, store.
@@ -81,7 +93,10 @@ __device__ __forceinline__ void fused_stage2(const float2* lds, float2* dst,
 #pragma unroll
   for (int m = 0; m < A; ++m) v[m] = lds[m * fused_row<A, KC>() + lds_pad_index(tid)];
   dft<A>(v);
-  const int c = tid % C, kk = (tid / C) % K, lp = tid / KC;
+  // column tid's run and output (the inverse of fused_column)
+  const int c = tid % C;
+  const int kk = SHUF ? tid / (C * A) : (tid / C) % K;
+  const int lp = SHUF ? (tid / C) % A : tid / KC;
   const int64_t pos = SHUF ? (int64_t)kk * A + lp : kk + a.res_mask * lp;
   float2* d = dst + ft.out_base + pos * a.oks + c;
 #pragma unroll
@@ -102,7 +117,7 @@ fft_fused_axes_kernel(const float2* src, float2* dst, const float2* __restrict__
   const FusedTile ft = fused_tile(blockIdx.x, a);
   float2 v[A];
   fused_load<A, KC, CONTIG>(v, src, a, ft, tid);
-  fused_stage1<A, KC, CONTIG>(v, lds, a.conj_in, tid);
+  fused_stage1<A, KC, CONTIG, SHUF>(v, lds, a.conj_in, tid);
   __syncthreads();
   fused_stage2<A, KC, CONTIG, SHUF>(lds, dst, twp, a, ft, tid);
 }
@@ -124,7 +139,7 @@ fft_fused_axes_persistent(const float2* src, float2* dst, const float2* __restri
   float2 v[A];
   fused_load<A, KC, CONTIG>(v, src, a, fused_tile(w, a), tid);
   while (true) {
-    fused_stage1<A, KC, CONTIG>(v, lds, a.conj_in, tid);
+    fused_stage1<A, KC, CONTIG, SHUF>(v, lds, a.conj_in, tid);
     __syncthreads();
     const int64_t wn = w + G;
     fused_load<A, KC, CONTIG>(v, src, a, fused_tile(wn < last ? wn : last, a), tid);
