@@ -106,8 +106,10 @@ __device__ __forceinline__ void split_f16(const float (&x)[8], f16x8_t (&b)[3]) 
 // vector l % 16 (real parts of rows 8 (l/16) .. +7 for l/16 < 2, imaginary
 // parts of rows 8 (l/16 - 2) .. +7 otherwise) and receives Yr, Yi of rows
 // 4 (l/16) .. +3 of the same vector.
+// sgn (+1 or -1) is the vector's sign (see mfma_vector_sign), folded into
+// the power-of-two scale and its inverse: both exact.
 template <int PREC>
-__device__ __forceinline__ void leaf16(const LeafA<PREC>& A, const float (&xs)[8],
+__device__ __forceinline__ void leaf16(const LeafA<PREC>& A, const float (&xs)[8], float sgn,
                                        f32x4_t& yr, f32x4_t& yi) {
   constexpr int TERMS = LeafPolicy<PREC>::terms;
   const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
@@ -135,8 +137,8 @@ __device__ __forceinline__ void leaf16(const LeafA<PREC>& A, const float (&xs)[8
   }
   int e = m > 0.f ? __builtin_amdgcn_frexp_expf(m) : 0;  // m in [2^(e-1), 2^e)
   e = e < -100 ? -100 : e;
-  const float sc = __builtin_amdgcn_ldexpf(1.0f, 15 - e);
-  const float inv = __builtin_amdgcn_ldexpf(1.0f, e - 15);
+  const float sc = __builtin_amdgcn_ldexpf(sgn, 15 - e);
+  const float inv = __builtin_amdgcn_ldexpf(sgn, e - 15);
   float xv[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) xv[k] = xs[k] * sc;
@@ -233,15 +235,19 @@ __device__ __forceinline__ void mfma_load(float2 (&v)[kMfmaRegs], const float2* 
   constexpr int stride = N / 16;
   const int lane = tid & 63, wave = tid >> 6;
   const int rb = 8 * ((lane >> 4) & 1) + 4 * (lane >> 5);
+  // element stride along the pencil: 1 in ROW mode (by construction)
+  const int64_t js = LM == MODE_ROW ? 1 : a.ijs;
 #pragma unroll
   for (int g4 = 0; g4 < 4; ++g4) {
     int q, t;
     mfma_vec<N, LM>(wave * 64 + g4 * 16 + (lane & 15), q, t);
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
-    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2) +
+                      (int64_t)(t + rb * stride) * js;
+    const int64_t step = (int64_t)stride * js;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[g4 * 4 + k] = s[(int64_t)(t + (rb + k) * stride) * a.ijs];
+    for (int k = 0; k < 4; ++k) v[g4 * 4 + k] = s[k * step];
   }
 }
 
@@ -285,15 +291,14 @@ __device__ __forceinline__ void mfma_leaf_store(const float2 (&x)[4], const Leaf
     // lane < 32 keeps its real part and gets the partner's; lane >= 32
     // gets the partner's imaginary part and keeps its own
     const auto sw = __builtin_amdgcn_permlane32_swap(
-        __builtin_bit_cast(unsigned, x[k].x * sgn), __builtin_bit_cast(unsigned, x[k].y * sgn),
-        false, false);
+        __builtin_bit_cast(unsigned, x[k].x), __builtin_bit_cast(unsigned, x[k].y), false, false);
     xs[k] = __builtin_bit_cast(float, (unsigned)sw[0]);
     xs[4 + k] = __builtin_bit_cast(float, (unsigned)sw[1]);
   }
+  // the four lanes of a vector (l, l ^ 16, l ^ 32, l ^ 48) share (q, t), so
+  // the sign needs no exchange
   f32x4_t yr, yi;
-  leaf16<PREC>(A, xs, yr, yi);
-  yr *= sgn;
-  yi *= sgn;
+  leaf16<PREC>(A, xs, sgn, yr, yi);
   const int h = lane >> 4;
   const int tm = t & (NS - 1);
   const int base = (t / NS) * NS * 16 + tm;
@@ -430,12 +435,16 @@ __device__ __forceinline__ void mfma_finish(const float2* res, float2* dst, cons
       dft<REST>(v);
       const int64_t b = tile * T + q;
       if (b < a.B) {
-        float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+        // element stride along the pencil: 1 in ROW mode (by construction)
+        const int64_t ks = SM == MODE_ROW ? 1 : a.oks;
+        float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2) +
+                    (int64_t)t * ks;
+        const int64_t step = (int64_t)BF * ks;
 #pragma unroll
         for (int r = 0; r < REST; ++r) {
           float2 o = v[r];
           if (a.conj_out) o.y = -o.y;
-          d[(int64_t)(t + r * BF) * a.oks] = o;
+          d[r * step] = o;
         }
       }
     }
@@ -450,9 +459,9 @@ __device__ __forceinline__ void mfma_finish(const float2* res, float2* dst, cons
       const int64_t b = tile * T + q;
       float2 v = res[mfma_lds<N>(q, k)];
       if (a.conj_out) v.y = -v.y;
+      const int64_t ks = SM == MODE_ROW ? 1 : a.oks;
       if (b < a.B)
-        dst[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2) +
-            (int64_t)k * a.oks] = v;
+        dst[pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2) + (int64_t)k * ks] = v;
     }
   }
 }
