@@ -383,15 +383,17 @@ def extras(x1024_host, refs):
         log(f"bench: 1024^3 {key} {sched[key]}")
     out["1024^3 schedules"] = sched
     prec = {}
-    for pr in ("fp32", "bf16x6", "bf16x9", "fp16x3"):
-        p = dft3d.Plan((1024,) * 3, "pencil", precision=pr)
+    for pr, lf in (("fp32", 0), ("bf16x6", 16), ("bf16x9", 16), ("fp16x3", 16),
+                   ("bf16x6", 32), ("bf16x9", 32), ("fp16x3", 32)):
+        key = pr if lf in (0, 16) else f"{pr} leaf32"
+        p = dft3d.Plan((1024,) * 3, "pencil", precision=pr, mfma_leaf=lf)
         f = timed(lambda: p.execute(x, y), 3)
-        prec[pr] = {"fwd_ms": round(f, 3), "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1)}
+        prec[key] = {"fwd_ms": round(f, 3), "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1)}
         if pr != "fp32":
-            prec[pr].update(check_1024(p, pr, roundtrip=False))
+            prec[key].update(check_1024(p, key, roundtrip=False))
         else:
-            prec[pr].update({k: v for k, v in sched["pencil"].items()
-                             if k in ("rel_l2", "max_elem_err_rms")})
+            prec[key].update({k: v for k, v in sched["pencil"].items()
+                              if k in ("rel_l2", "max_elem_err_rms")})
         p.close()
     out["1024^3 pencil leaf precision"] = prec
     log(f"bench: 1024^3 precisions {prec}")
@@ -429,14 +431,16 @@ def extras(x1024_host, refs):
     x = torch.from_numpy(xh).cuda()
     y = torch.empty_like(x)
     prec = {}
-    for pr in ("fp32", "bf16x1", "fp16x1", "bf16x6", "bf16x9", "fp16x3"):
-        p = dft3d.Plan(shape, "pencil", precision=pr)
+    for pr, lf in (("fp32", 0), ("bf16x1", 16), ("fp16x1", 16), ("bf16x6", 16),
+                   ("bf16x9", 16), ("fp16x3", 16), ("bf16x6", 32), ("fp16x3", 32)):
+        key = pr if lf in (0, 16) else f"{pr} leaf32"
+        p = dft3d.Plan(shape, "pencil", precision=pr, mfma_leaf=lf)
         f = timed(lambda: p.execute(x, y), 20)
-        prec[pr] = {"fwd_ms": round(f, 4),
-                    "fwd_gflops": round(5.0 * N * 24 / (f * 1e-3) / 1e9, 1)}
+        prec[key] = {"fwd_ms": round(f, 4),
+                     "fwd_gflops": round(5.0 * N * 24 / (f * 1e-3) / 1e9, 1)}
         if yref is not None:
             p.execute(x, y)
-            prec[pr].update(err_fields(y.cpu().numpy(), yref))
+            prec[key].update(err_fields(y.cpu().numpy(), yref))
         p.close()
     out["256^3 pencil leaf precision"] = prec
     log(f"bench: 256^3 precisions {prec}")
@@ -503,7 +507,8 @@ def extras(x1024_host, refs):
     z = torch.empty_like(x)
     r = {}
     runs = [("auto untuned", dict(schedule="auto")), ("pencil", dict(schedule="pencil")),
-            ("auto bf16x6", dict(schedule="auto", precision="bf16x6"))]
+            ("auto bf16x6", dict(schedule="auto", precision="bf16x6")),
+            ("auto bf16x6 leaf32", dict(schedule="auto", precision="bf16x6", mfma_leaf=32))]
     for name, kw in runs:
         p = dft3d.Plan(shape, **kw)
         f = timed(lambda: p.execute(x, y), 3)
@@ -609,6 +614,8 @@ def main():
                     help="layout of the timed plan (natural, shuffled)")
     ap.add_argument("--precision", default="fp32",
                     help="leaf arithmetic of the timed plan (fp32, bf16x6, ...)")
+    ap.add_argument("--mfma-leaf", type=int, default=0,
+                    help="split-precision leaf length of the timed plan (16, 32; 0 default)")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the 1024^3 headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -639,9 +646,12 @@ def main():
     x = torch.from_numpy(x_host).cuda()
     out = torch.empty_like(x)
 
-    plan = dft3d.Plan(shape, args.schedule, layout=args.layout, precision=args.precision)
+    leaf = {"mfma_leaf": args.mfma_leaf} if args.mfma_leaf else {}
+    plan = dft3d.Plan(shape, args.schedule, layout=args.layout, precision=args.precision,
+                      **leaf)
     npass = plan.num_passes
-    desc = dft3d.describe(shape, args.schedule, args.layout, precision=args.precision)
+    desc = dft3d.describe(shape, args.schedule, args.layout, precision=args.precision,
+                          **leaf)
     log(f"bench: schedule {desc['schedule']} passes "
         f"{[p['label'] for p in desc['passes']]}")
     ms, wall, per = time_plan(plan, x, out, args.steps, args.warmup)

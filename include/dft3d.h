@@ -147,6 +147,16 @@ enum dft3d_option {
                                 fused axes and grouped pencil passes are
                                 turned off (their unfused passes run);
                                 otherwise UNSUPPORTED_SCHEDULE */
+  DFT3D_OPT_MFMA_LEAF = 13,  /* split-precision passes: the length of the
+                                DFT leaves on the matrix cores (Section 2.1,
+                                eqs. (1)-(2): the small DFT as a dense
+                                product): 16 or 32; 0 = the default for
+                                each pass length and precision (32 for
+                                lengths 128, 256, 4096 and for fp16 forms at
+                                1024, else 16).  Leaves of 32 exist for
+                                lengths 32^s r with r < 16 (32 .. 256,
+                                1024 .. 4096); other lengths keep leaves of
+                                16.  Other values: INVALID_ARG */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

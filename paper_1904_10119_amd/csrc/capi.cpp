@@ -232,6 +232,10 @@ int apply_option(Options& o, int key, int64_t value) {
       if (value < 0 || value > 2) return DFT3D_ERR_INVALID_ARG;
       o.move_only = (int)value;
       return DFT3D_OK;
+    case DFT3D_OPT_MFMA_LEAF:
+      if (value != 0 && value != 16 && value != 32) return DFT3D_ERR_INVALID_ARG;
+      o.mfma_leaf = (int)value;
+      return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
   }
@@ -487,6 +491,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_PENCIL_GROUP: *value = p->opt.pencil_group; break;
     case DFT3D_OPT_BATCH_LAUNCH: *value = p->opt.batch_launch; break;
     case DFT3D_OPT_MOVE_ONLY: *value = p->opt.move_only; break;
+    case DFT3D_OPT_MFMA_LEAF: *value = p->opt.mfma_leaf; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }

@@ -62,6 +62,7 @@ struct KernelInfo {
   int move_only = 0;  // 1: loads, LDS exchanges and stores of the pass with the radix
                       // stages (butterflies and twiddles) removed; 2: a plain copy
   int r0 = 0, r1 = 0, r2 = 0;   // FP32 pass kernels: the radix of each stage (1: none)
+  int mfma_leaf = 0;  // split-precision MFMA passes: the leaf length (16 or 32)
 };
 
 // All compiled pass kernels.
@@ -99,17 +100,21 @@ const KernelInfo* find_bluestein_kernel(int m, int tile);
 // shuffled: the finished axis left in the shuffled order).
 const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent, int shuffled);
 // The split-precision MFMA pass kernel for a length and layout, if any
-// (the persistent form when asked for and compiled, else the other form).
+// (the persistent form when asked for and compiled, else the other form),
+// with leaves of length leaf (16 or 32; 0: the default for the length).
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
-                                   int persistent);
+                                   int persistent, int leaf);
+// The default MFMA leaf length of a pass length and split precision.
+int default_mfma_leaf(int n, int precision);
 
 // Roots w_n^m = exp(-2 pi i m / n), m < n, computed in FP64 with exact
 // octant reduction and rounded once to FP32 (eq. (4) entries).
 void make_roots(int64_t n, float2* out);
 // The same root in FP64: (cos, sin) of 2 pi m / n (before the sign).
 void root_fp64(int64_t m, int64_t n, double& c, double& s);
-// MFMA leaf operand table for a precision (kLeafTableHalves 16-bit values).
-constexpr int kLeafTableFloat2 = 3 * 2 * 64 * 8 / 4;  // as float2 slots
+// MFMA leaf operand tables for a precision (length-16 table, then the odd
+// half table of the length-32 leaf; kLeafTableHalves 16-bit values).
+constexpr int kLeafTableFloat2 = 2 * 3 * 2 * 64 * 8 / 4;  // as float2 slots
 void make_leaf_table(int precision, unsigned short* out);
 // Bluestein tables for a length n that is not a power of two: the chirp
 // w[j] = exp(-pi i j^2 / n) (n entries) and the filter H / m, H = DFT_m of
@@ -152,6 +157,7 @@ struct Options {
   int pencil_group = 0; // pencil: planes per group of the first two passes (0 = all, -1 = auto)
   int batch_launch = 0; // batched calls: 0 one launch per pass level, 1 one persistent launch
   int move_only = 0;    // 1: radix stages removed from every pass, 2: every pass a plain copy
+  int mfma_leaf = 0;    // split-precision passes: leaf length 16 or 32, 0: default per length
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

@@ -147,7 +147,9 @@ struct Builder {
       // 256^3 bf16x6, 0.165 ms one tile per workgroup vs 0.185 persistent)
       const bool pers = opt.persistent &&
                         (opt.nontemporal != 2 || total_points * 8 >= kStreamBytes);
-      k = find_mfma_kernel(n, lmode, smode, opt.precision, pers);
+      k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, opt.mfma_leaf);
+      // a length without leaves of the asked length keeps its default leaves
+      if (!k && opt.mfma_leaf) k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, 0);
       if (k) leaf = opt.precision;
     }
     if (!k) k = pick_kernel(n, lmode, smode, tw, opt, total_points);
@@ -752,9 +754,15 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
       os << p.k->r0;
       if (p.k->r1 > 1) os << "," << p.k->r1;
       if (p.k->r2 > 1) os << "," << p.k->r2;
+    } else if (p.k->mfma_leaf) {  // MFMA passes: leaf stages, then the VALU rest
+      int n = p.k->n;
+      bool first = true;
+      for (; n >= p.k->mfma_leaf; n /= p.k->mfma_leaf, first = false)
+        os << (first ? "" : ",") << p.k->mfma_leaf;
+      if (n > 1) os << "," << n;
     }
     os << "]"
-       << ",\"threads\":" << p.k->threads
+       << ",\"mfma_leaf\":" << p.k->mfma_leaf << ",\"threads\":" << p.k->threads
        << ",\"lds_bytes\":" << p.k->lds_bytes << ",\"pencils\":" << p.args.B
        << ",\"src\":\"" << kBuf[p.src] << "\",\"dst\":\"" << kBuf[p.dst] << "\""
        << ",\"in_off\":" << p.in_off << ",\"out_off\":" << p.out_off

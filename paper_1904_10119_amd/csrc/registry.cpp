@@ -1,6 +1,7 @@
 // Registry of the compiled pass kernels.
 #include <algorithm>
 
+#include "../../include/dft3d.h"
 #include "internal.h"
 
 namespace dft3d {
@@ -12,6 +13,8 @@ void register_kernels_big(std::vector<KernelInfo>& v);
 void register_kernels_mfma_a(std::vector<KernelInfo>& v);
 void register_kernels_mfma_b(std::vector<KernelInfo>& v);
 void register_kernels_mfma_c(std::vector<KernelInfo>& v);
+void register_kernels_mfma_d(std::vector<KernelInfo>& v);
+void register_kernels_mfma_e(std::vector<KernelInfo>& v);
 void register_kernels_plane(std::vector<KernelInfo>& v);
 void register_kernels_fused(std::vector<KernelInfo>& v);
 void register_kernels_bluestein(std::vector<KernelInfo>& v);
@@ -28,6 +31,8 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_mfma_a(v);
     register_kernels_mfma_b(v);
     register_kernels_mfma_c(v);
+    register_kernels_mfma_d(v);
+    register_kernels_mfma_e(v);
     register_kernels_plane(v);
     register_kernels_fused(v);
     register_kernels_bluestein(v);
@@ -169,11 +174,23 @@ const KernelInfo* find_plane_kernel(int n1, int n2) {
   return nullptr;
 }
 
+// Measured on MI355X (pencil plans, leaf 32 / leaf 16 time): lengths 128,
+// 256 and 4096 0.87 .. 0.97 in every split form; 1024 0.98 for fp16x3 but
+// 1.01 .. 1.03 for the bf16 forms; 2048 1.01 .. 1.02; 64 1.10 .. 1.13.
+int default_mfma_leaf(int n, int precision) {
+  if (n == 128 || n == 256 || n == 4096) return 32;
+  if (n == 1024 && (precision == DFT3D_PREC_FP16X3 || precision == DFT3D_PREC_FP16X1))
+    return 32;
+  return 16;
+}
+
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
-                                   int persistent) {
+                                   int persistent, int leaf) {
+  if (leaf == 0) leaf = default_mfma_leaf(n, precision);
   const KernelInfo* other = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.n == n && k.lmode == lmode && k.smode == smode && k.precision == precision) {
+    if (k.n == n && k.lmode == lmode && k.smode == smode && k.precision == precision &&
+        k.mfma_leaf == leaf) {
       if (k.persistent == persistent) return &k;
       other = &k;
     }

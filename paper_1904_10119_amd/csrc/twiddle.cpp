@@ -75,8 +75,9 @@ unsigned short f16_bits(double v) {  // v exactly representable in fp16
 
 }  // namespace
 
-// Lane l of the 16x16x32 MFMA holds A[l % 16][8 (l / 16) + i]; matrix 0 is
-// [Fr | -Fi], matrix 1 is [Fi | Fr] with F[m][k] = w_16^{m k} (forward).
+// Lane l of the 16x16x32 MFMA holds A[l % 16][8 (l / 16) + i].  Length-16
+// leaf: matrix 0 is [Fr | -Fi], matrix 1 is [Fi | Fr] with F[m][k] =
+// w_16^{m k} (forward).
 // Each entry is split from FP64: bf16 terms unscaled, fp16 terms scaled by
 // 2^(11 t) so that the small terms stay normal.
 void make_leaf_table(int precision, unsigned short* out) {
@@ -99,6 +100,27 @@ void make_leaf_table(int precision, unsigned short* out) {
             r = fp16 ? (r - h) * 2048.0 : r - h;
           }
           out[((t * 2 + c) * 64 + lane) * 8 + i] = fp16 ? f16_bits(h) : bf16_bits(h);
+        }
+  // Length-32 leaf, odd-half table: H[p][k] = w_32^{p (2k + 1)} (p, k < 16),
+  // matrix 0 [Hr | -Hi], matrix 1 [Hi | Hr].
+  unsigned short* out32 = out + 3 * 2 * 64 * 8;
+  for (int t = 0; t < 3; ++t)
+    for (int c = 0; c < 2; ++c)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int i = 0; i < 8; ++i) {
+          const int p = lane % 16, k = 8 * (lane / 16) + i, col = k % 16;
+          double cs, sn;
+          root_fp64((int64_t)p * (2 * col + 1), 32, cs, sn);
+          const double hr = cs, hi = -sn;  // w_32^{p (2 col + 1)} = cos - i sin
+          double v;
+          if (c == 0) v = k < 16 ? hr : -hi;
+          else v = k < 16 ? hi : hr;
+          double r = v, h = 0.0;
+          for (int j = 0; j <= t; ++j) {
+            h = fp16 ? round_sig(r, 11, std::ldexp(1.0, -24)) : round_sig(r, 8, 0.0);
+            r = fp16 ? (r - h) * 2048.0 : r - h;
+          }
+          out32[((t * 2 + c) * 64 + lane) * 8 + i] = fp16 ? f16_bits(h) : bf16_bits(h);
         }
 }
 

@@ -21,7 +21,7 @@ PRECISIONS = {"fp32": 0, "bf16x1": 1, "fp16x1": 2, "bf16x6": 3, "bf16x9": 4,
               "fp16x3": 5}
 OPT_PRECISION, OPT_TILE, OPT_XCD_REMAP, OPT_SPLIT_MAX, OPT_NONTEMPORAL = 1, 2, 3, 4, 5
 OPT_PERSISTENT, OPT_SLAB_GROUP, OPT_FUSED_PLANE, OPT_FUSED_AXES = 6, 7, 8, 9
-OPT_PENCIL_GROUP, OPT_BATCH_LAUNCH, OPT_MOVE_ONLY = 10, 11, 12
+OPT_PENCIL_GROUP, OPT_BATCH_LAUNCH, OPT_MOVE_ONLY, OPT_MFMA_LEAF = 10, 11, 12, 13
 OPT_NUM_PASSES = 100
 
 OK = 0
@@ -99,7 +99,8 @@ OPTION_KEYS = {"precision": OPT_PRECISION, "tile": OPT_TILE,
                "nontemporal": OPT_NONTEMPORAL, "persistent": OPT_PERSISTENT,
                "slab_group": OPT_SLAB_GROUP, "fused_plane": OPT_FUSED_PLANE,
                "fused_axes": OPT_FUSED_AXES, "pencil_group": OPT_PENCIL_GROUP,
-               "batch_launch": OPT_BATCH_LAUNCH, "move_only": OPT_MOVE_ONLY}
+               "batch_launch": OPT_BATCH_LAUNCH, "move_only": OPT_MOVE_ONLY,
+               "mfma_leaf": OPT_MFMA_LEAF}
 
 
 def describe(shape: Sequence[int], schedule: str = "auto",
@@ -144,7 +145,8 @@ class Plan:
                  tile: int = 0, split_max: int = 0, xcd_remap: int = 1,
                  nontemporal: int = -1, persistent: int = -1,
                  slab_group: int = -2, fused_plane: int = -1, fused_axes: int = -1,
-                 pencil_group: int = -2, batch_launch: int = -1, move_only: int = 0):
+                 pencil_group: int = -2, batch_launch: int = -1, move_only: int = 0,
+                 mfma_leaf: int = 0):
         self.shape = tuple(int(s) for s in shape)
         self.schedule = schedule
         h = ctypes.c_void_p()
@@ -178,6 +180,8 @@ class Plan:
                 self.set_option(OPT_BATCH_LAUNCH, batch_launch)
             if move_only:
                 self.set_option(OPT_MOVE_ONLY, move_only)
+            if mfma_leaf:
+                self.set_option(OPT_MFMA_LEAF, mfma_leaf)
         except Exception:
             self.close()
             raise

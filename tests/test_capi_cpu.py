@@ -175,3 +175,23 @@ def test_split_precision_uses_mfma_leaves_where_available():
     # four-step first halves (post twiddle) stay FP32
     d = dft3d.describe((2048, 1024, 512), "auto", precision="fp16x3", split_max=1024)
     assert [p["precision"] > 0 for p in d["passes"]] == [True, True, False, True]
+
+
+def test_mfma_leaf_option():
+    """DFT3D_OPT_MFMA_LEAF: 32 gives length-32 leaves where they are
+    compiled (32^s r, r < 16), other lengths keep leaves of 16; FP32 plans
+    ignore it; values other than 0, 16, 32 are rejected."""
+    for n, want in ((32, [32]), (64, [32, 2]), (256, [32, 8]), (1024, [32, 32]),
+                    (2048, [32, 32, 2]), (4096, [32, 32, 4])):
+        d = dft3d.describe((4, 4, n), "pencil", precision="fp16x3", mfma_leaf=32)
+        p = d["passes"][0]
+        assert (p["n"], p["mfma_leaf"], p["radices"]) == (n, 32, want), p
+    d = dft3d.describe((4, 4, 512), "pencil", precision="bf16x6", mfma_leaf=32)
+    assert d["passes"][0]["mfma_leaf"] == 16 and d["passes"][0]["radices"] == [16, 16, 2]
+    d = dft3d.describe((4, 4, 1024), "pencil", precision="bf16x6", mfma_leaf=16)
+    assert d["passes"][0]["radices"] == [16, 16, 4]
+    d = dft3d.describe((4, 4, 1024), "pencil", mfma_leaf=32)
+    assert d["passes"][0]["mfma_leaf"] == 0
+    for bad in (1, 8, 64, -1):
+        with pytest.raises(dft3d.Dft3dError):
+            dft3d.describe((4, 4, 1024), "pencil", precision="bf16x6", mfma_leaf=bad)

@@ -76,11 +76,18 @@ def check(shape, got, ref, what):
 
 CASES_1024 = [("pencil", {}), ("slab", {}), ("volumetric", {}),
               ("pencil", {"precision": "bf16x6"}), ("pencil", {"precision": "bf16x9"}),
-              ("pencil", {"precision": "fp16x3"})]
+              ("pencil", {"precision": "fp16x3"}),
+              ("pencil", {"precision": "bf16x6", "mfma_leaf": 32}),
+              ("pencil", {"precision": "fp16x3", "mfma_leaf": 32})]
+
+
+def case_id(schedule, opts):
+    leaf = f"-leaf{opts['mfma_leaf']}" if "mfma_leaf" in opts else ""
+    return f"{schedule}-{opts.get('precision', 'fp32')}{leaf}"
 
 
 @pytest.mark.parametrize("schedule,opts", CASES_1024,
-                         ids=[f"{s}-{o.get('precision', 'fp32')}" for s, o in CASES_1024])
+                         ids=[case_id(s, o) for s, o in CASES_1024])
 def test_1024_cubed_forward_every_element(schedule, opts):
     shape = (1024, 1024, 1024)
     say("case fullsize forward", shape, schedule, opts)
@@ -127,11 +134,13 @@ def test_1024_cubed_shuffled_every_element():
 
 
 CASES_2048 = [("auto", {}, False), ("auto", {}, True), ("pencil", {}, False),
-              ("auto", {"precision": "bf16x6"}, False)]
+              ("auto", {"precision": "bf16x6"}, False),
+              ("auto", {"precision": "bf16x6", "mfma_leaf": 32}, False)]
 
 
 @pytest.mark.parametrize("schedule,opts,inverse", CASES_2048,
-                         ids=["auto-fwd", "auto-inv", "pencil-fwd", "auto-bf16x6"])
+                         ids=["auto-fwd", "auto-inv", "pencil-fwd", "auto-bf16x6",
+                              "auto-bf16x6-leaf32"])
 def test_2048_1024_512_every_element(schedule, opts, inverse):
     shape = (2048, 1024, 512)
     say("case fullsize", shape, schedule, opts, "inverse" if inverse else "forward")

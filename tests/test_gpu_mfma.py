@@ -1,8 +1,9 @@
-"""GPU parity of the split-precision MFMA leaves: radix-16 stages as real
-GEMMs on the matrix cores with bf16 / fp16 operand splitting and FP32
-accumulation.  The split forms (bf16x6, bf16x9, fp16x3) meet the same
-tolerance as FP32; the single-term forms (bf16x1, fp16x1) are reported and
-only checked against a loose bound."""
+"""GPU parity of the split-precision MFMA leaves of length 16 (forced with
+DFT3D_OPT_MFMA_LEAF = 16; the length-32 leaves have their own tests):
+radix-16 stages as real GEMMs on the matrix cores with bf16 / fp16
+operand splitting and FP32 accumulation.  The split forms (bf16x6,
+bf16x9, fp16x3) meet the same tolerance as FP32; the single-term forms
+(bf16x1, fp16x1) are reported and only checked against a loose bound."""
 import sys
 
 import numpy as np
@@ -32,7 +33,8 @@ def say(*a):
 
 def run(x, precision, schedule="pencil", inverse=False):
     xt = torch.from_numpy(x).cuda()
-    y = dft3d.fftn(xt, schedule=schedule, precision=precision, inverse=inverse)
+    y = dft3d.fftn(xt, schedule=schedule, precision=precision, inverse=inverse,
+                   mfma_leaf=0 if precision == "fp32" else 16)
     torch.cuda.synchronize()
     return y.cpu().numpy()
 
@@ -113,7 +115,8 @@ def test_one_tile_and_persistent_forms(precision, shape):
         ref = oracle.dft3d(x.astype(np.complex128), sign, "fft")
         outs = []
         for pers in (0, 1):
-            p = dft3d.Plan(shape, "pencil", precision=precision, persistent=pers)
+            p = dft3d.Plan(shape, "pencil", precision=precision, persistent=pers,
+                           mfma_leaf=16)
             y = torch.empty_like(xt)
             p.execute(xt, y, inverse=inv)
             torch.cuda.synchronize()
