@@ -534,13 +534,14 @@ def extras(x1024_host, refs):
     # lengths that are not powers of two, one pass per axis: 1000^3 and
     # 96^3 (mixed radix) and 1009^3 (Bluestein, convolution length 2048)
     bl = {}
-    for shape, reps in (((1000, 1000, 1000), 3), ((1009, 1009, 1009), 3),
-                        ((96, 96, 96), 100)):
+    for shape, reps, sch in (((1000, 1000, 1000), 3, "auto"), ((1009, 1009, 1009), 3, "auto"),
+                             ((96, 96, 96), 100, "auto"), ((1000, 1000, 1000), 3, "slab"),
+                             ((1000, 1000, 1000), 3, "volumetric")):
         key = str(shape[0])
         xh = refs[key][0] if have else inputs.uniform_c64(shape, 6)
         x = torch.from_numpy(xh).cuda()
         y = torch.empty_like(x)
-        p = dft3d.Plan(shape, "auto")
+        p = dft3d.Plan(shape, sch)
         f = timed(lambda: p.execute(x, y), reps)
         i = timed(lambda: p.execute(x, y, inverse=True), reps)
         n = p.num_passes
@@ -555,7 +556,7 @@ def extras(x1024_host, refs):
             else:
                 ent.update(sampled_err(y, refs[key][1], refs[key][2]))
         p.close()
-        bl["x".join(map(str, shape))] = ent
+        bl["x".join(map(str, shape)) + ("" if sch == "auto" else " " + sch)] = ent
         del x, y
         torch.cuda.empty_cache()
     out["other lengths"] = bl

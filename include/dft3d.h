@@ -170,15 +170,18 @@ const char* dft3d_status_string(int status);
  * and layout are described once and the transform is run many times.  Each
  * n_d is in
  * [1, 4096].  Powers of two run on every schedule.  Other lengths (the
- * paper's experiments use powers of two) run on the pencil schedule (or AUTO,
- * which then picks it) with FP32 precision and the natural layout, one
- * rotate-on-write pass per axis: a mixed-radix pass (radices 2, 3, 4, 5,
- * 7, 8, 10, 11, 13, 16) when every prime factor of n_d is at most 13, else
- * a Bluestein pass (the DFT of length n as a circular convolution of length
+ * paper's experiments use powers of two; it leaves sizes its process grid
+ * does not divide to future work, Section 3.2) run with FP32 precision and
+ * the natural layout on every schedule (AUTO picks pencil), one pass per
+ * such axis (rotate-on-write in the pencil schedule, in layout in the slab
+ * and volumetric schedules): a mixed-radix pass (radices 2, 3, 4, 5, 7, 8,
+ * 10, 11, 13, 16) when every prime factor of n_d is at most 13, else a
+ * Bluestein pass (the DFT of length n as a circular convolution of length
  * m, the power of two >= 2n - 1, up to 8192, done with two power-of-two FFTs
- * in the same workgroup).  Other schedules, precisions or layouts with such
- * lengths return UNSUPPORTED_SCHEDULE.  The workspace is N * 8 bytes as for
- * powers of two.  Validates the arguments first
+ * in the same workgroup).  Split precisions, the shuffled layout and
+ * move-only plans with such lengths return UNSUPPORTED_SCHEDULE.  The
+ * workspace is N * 8 bytes as for powers of two.  Validates the arguments
+ * first
  * (INVALID_ARG / UNSUPPORTED_SIZE / UNSUPPORTED_SCHEDULE), then needs a HIP
  * device (NO_DEVICE), then allocates and uploads the twiddle tables on the
  * current device (OUT_OF_MEMORY / HIP_ERROR).  *out receives the handle, or

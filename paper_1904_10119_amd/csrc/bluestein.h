@@ -24,7 +24,7 @@
 // H / m (m entries), both from FP64.
 #pragma once
 
-#include "pass_kernel.h"
+#include "pencil_index.h"
 
 namespace dft3d {
 
@@ -172,7 +172,7 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
     // pencils past the end of a ragged last tile read the last pencil
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
-    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+    const float2* s = src + pencil_offset_any(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -192,7 +192,7 @@ bluestein_axis_kernel(const float2* src, float2* dst, const float2* __restrict__
     bluestein_fft<M, BL, T, SQ, MODE_COL, E, P, TWL>(v, lds, tw, st, tid, q, p);
     const int64_t bo = tile * T + q;
     if (bo < a.B) {
-      float2* d = dst + pencil_offset(bo, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+      float2* d = dst + pencil_offset_any(bo, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int k = (M - (p + P * e)) & (M - 1);

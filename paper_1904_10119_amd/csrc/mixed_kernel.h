@@ -25,7 +25,7 @@
 // the first stage in the lowest bits (a zero byte ends the list).
 #pragma once
 
-#include "pass_kernel.h"
+#include "pencil_index.h"
 
 namespace dft3d {
 
@@ -245,7 +245,7 @@ __device__ __forceinline__ void mixed_rest(uint64_t code, int ns, float2* buf, f
   const int qs = tid % T;
   const int64_t b = tile * T + qs;
   if (b < a.B) {
-    float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+    float2* d = dst + pencil_offset_any(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
     const float2* ps = buf + qs * sq;
     constexpr int S = T * NMAX / TH;  // outputs per thread, at most
     constexpr int KS = TH / T;
@@ -299,7 +299,7 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
     // pencils past the end of a ragged last tile read the last pencil
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
-    const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+    const float2* s = src + pencil_offset_any(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
     const int R = (int)(code & 255);
     code >>= 8;
     with_radix<VAR, COMP>(R, [&](auto rc) {
@@ -349,7 +349,7 @@ fft_mixed_fixed(const float2* src, float2* dst, const float2* __restrict__ tw,
   }
   int64_t b = tile * T + q;
   b = b < a.B ? b : a.B - 1;
-  const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+  const float2* s = src + pencil_offset_any(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
   constexpr int R1 = (int)(CODE & 255);
   mixed_first_stage<R1, V>(s, a.ijs, a.conj_in, pen, N, p, P);
   mixed_stages_fixed<(CODE >> 8), R1, V, N>(pen, twv, p, P);

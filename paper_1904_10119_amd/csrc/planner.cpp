@@ -107,12 +107,42 @@ struct Field {  // one bit field of the pencil index
   int64_t in_stride, out_stride;
 };
 
+// Whether a pencil-index decomposition needs the general form: a field
+// whose count is not a power of two before the last field of count above 1.
+bool general_fields(const Field* f, int nf) {
+  while (nf > 1 && f[nf - 1].count == 1) --nf;
+  for (int i = 0; i + 1 < nf; ++i)
+    if (!is_pow2(f[i].count)) return true;
+  return false;
+}
+
 // Fills the pencil-index decomposition of a pass from up to three fields,
-// listed fastest first.
+// listed fastest first: bit fields, or where general_fields holds the
+// general form (s0 = s1 = -1, m0 and m1 the counts of the first two fields;
+// read only by the mixed-radix and Bluestein kernels, pencil_index.h).
 void set_fields(PassArgs& a, const Field* f, int nf) {
+  // trailing fields of count 1 after a count that is not a power of two
+  // drop out (that count then ends the bit fields)
+  for (int i = 0; i + 1 < nf; ++i)
+    if (!is_pow2(f[i].count)) {
+      while (nf > 1 && f[nf - 1].count == 1) --nf;
+      break;
+    }
   int64_t c0 = nf > 0 ? f[0].count : 1, c1 = nf > 1 ? f[1].count : 1;
   a.B = 1;
   for (int i = 0; i < nf; ++i) a.B *= f[i].count;
+  if (general_fields(f, nf)) {
+    a.s0 = a.s1 = -1;
+    a.m0 = c0;
+    a.m1 = c1;
+    a.is0 = f[0].in_stride;
+    a.os0 = f[0].out_stride;
+    a.is1 = f[1].in_stride;
+    a.os1 = f[1].out_stride;
+    a.is2 = nf > 2 ? f[2].in_stride : 0;
+    a.os2 = nf > 2 ? f[2].out_stride : 0;
+    return;
+  }
   a.s0 = nf > 1 ? ilog2(c0) : kNoSplit;
   a.m0 = nf > 1 ? c0 - 1 : (int64_t(1) << kNoSplit) - 1;
   a.is0 = nf > 0 ? f[0].in_stride : 0;
@@ -135,6 +165,17 @@ struct Builder {
   void add(int n, int lmode, int smode, int tw, const Field* f, int nf, int64_t ijs,
            int64_t oks, int64_t twp_len, int res_shift, int64_t res_mask,
            const std::string& label) {
+    if (general_fields(f, nf)) {
+      // pencil counts that are not powers of two (a shape with such an
+      // axis): the power-of-two kernels read bit fields only, the
+      // mixed-radix pass reads the general form and runs these lengths too
+      if (tw) {
+        status = DFT3D_ERR_UNSUPPORTED_SCHEDULE;
+        return;
+      }
+      add_mixed(n, f, nf, ijs, oks, label + " mixed");
+      return;
+    }
     const KernelInfo* k = nullptr;
     int leaf = 0;
     if (nt_side && opt.precision == DFT3D_PREC_FP32 && !tw)
@@ -414,6 +455,25 @@ void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
   }
 }
 
+// One pass of length n along an axis, in layout (element strides ijs, oks)
+// over the pencils of fields f: the power-of-two pass kernels, else the
+// mixed-radix pass (prime factors at most 13), else the one-pass Bluestein
+// axis.  Used by the slab and volumetric schedules, whose passes keep the
+// layout.
+void axis_pass(Builder& b, int64_t n, int lmode, int smode, const Field* f, int nf,
+               int64_t ijs, int64_t oks, const char* label) {
+  char lab[96];
+  if (is_pow2(n)) {
+    b.add((int)n, lmode, smode, 0, f, nf, ijs, oks, 0, 0, 0, label);
+  } else if (mixed_radix_code(n)) {
+    std::snprintf(lab, sizeof lab, "%s mixed", label);
+    b.add_mixed(n, f, nf, ijs, oks, lab);
+  } else {
+    std::snprintf(lab, sizeof lab, "%s via %lld", label, (long long)bluestein_length(n));
+    b.add_bluestein(n, f, nf, ijs, oks, lab);
+  }
+}
+
 // Grouped pencil schedule: planes of axis 0 taken G at a time through the
 // first two passes, so that a group's intermediate (G n1 n2 points, about
 // 256 MB) is read back by the second pass while it is still in the
@@ -553,8 +613,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
   if (layout != DFT3D_LAYOUT_NATURAL && layout != DFT3D_LAYOUT_SHUFFLED)
     return DFT3D_ERR_INVALID_ARG;
   const bool shuffled = layout == DFT3D_LAYOUT_SHUFFLED;
-  if (any_other && (shuffled || opt.precision != DFT3D_PREC_FP32 ||
-                    (schedule != DFT3D_SCHED_PENCIL && schedule != DFT3D_SCHED_AUTO)))
+  if (any_other && (shuffled || opt.precision != DFT3D_PREC_FP32 || opt.move_only))
     return DFT3D_ERR_UNSUPPORTED_SCHEDULE;
   // only the volumetric schedule has a digit exchange to leave out
   if (shuffled && schedule != DFT3D_SCHED_VOLUMETRIC && schedule != DFT3D_SCHED_AUTO)
@@ -623,7 +682,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
         Field f[1] = {{group * n[1], n[2], n[2]}};
         std::snprintf(lab, sizeof lab, "slab.rows DFT%lld planes %lld+%lld", (long long)n[2],
                       (long long)g0, (long long)group);
-        b.add((int)n[2], MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
+        axis_pass(b, n[2], MODE_ROW, MODE_ROW, f, 1, 1, 1, lab);
         if (b.status != DFT3D_OK) break;
         passes.back().src = BUF_IN;
         passes.back().dst = BUF_OUT;
@@ -633,7 +692,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
         Field f[2] = {{n[2], 1, 1}, {group, plane, plane}};
         std::snprintf(lab, sizeof lab, "slab.cols DFT%lld planes %lld+%lld", (long long)n[1],
                       (long long)g0, (long long)group);
-        b.add((int)n[1], MODE_COL, MODE_COL, 0, f, 2, n[2], n[2], 0, 0, 0, lab);
+        axis_pass(b, n[1], MODE_COL, MODE_COL, f, 2, n[2], n[2], lab);
         if (b.status != DFT3D_OK) break;
         passes.back().src = passes.back().dst = BUF_OUT;
         passes.back().in_off = passes.back().out_off = g0 * plane;
@@ -642,7 +701,7 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
     if (b.status == DFT3D_OK) {
       Field f[1] = {{plane, 1, 1}};
       std::snprintf(lab, sizeof lab, "slab.depth DFT%lld", (long long)n[0]);
-      b.add((int)n[0], MODE_COL, MODE_COL, 0, f, 1, plane, plane, 0, 0, 0, lab);
+      axis_pass(b, n[0], MODE_COL, MODE_COL, f, 1, plane, plane, lab);
       if (b.status == DFT3D_OK) passes.back().src = passes.back().dst = BUF_OUT;
     }
   } else {  // VOLUMETRIC
@@ -650,7 +709,8 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
     // factors match (four passes instead of six for 256^3, 1024^3)
     // (the shuffled forward list too: its fused passes leave the finished
     // axis in digit order; the inverse from the shuffled order is unfused)
-    const bool fuse = opt.fused_axes && !from_layout && opt.precision == DFT3D_PREC_FP32;
+    const bool fuse =
+        opt.fused_axes && !from_layout && opt.precision == DFT3D_PREC_FP32 && !any_other;
     int pending = -1;  // axis whose V2 is still to come
     auto dims = [&n](int axis, int64_t& outer, int64_t& inner) {
       outer = 1;
@@ -668,11 +728,15 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
     for (int axis = 2; axis >= 0; --axis) {
       int64_t outer = 1, inner = 1;
       dims(axis, outer, inner);
-      if (n[axis] >= 4 && shuffled && from_layout) {
+      // a four-step split needs power-of-two bit fields: the axis and the
+      // axes after it (the residue of the twiddle stage is a bit field of
+      // the pencil index); other axes run as one pass in layout
+      const bool split = n[axis] >= 4 && is_pow2(n[axis]) && is_pow2(inner);
+      if (split && shuffled && from_layout) {
         volumetric_axis_from_shuffled(b, outer, n[axis], inner, axis);
         continue;
       }
-      if (n[axis] >= 4) {
+      if (split) {
         if (pending == axis + 1 && fuse && n[pending] >= 4) {
           int64_t po, pin;
           dims(pending, po, pin);
@@ -692,15 +756,16 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
         continue;
       }
       flush();
-      {  // too short to split (its shuffled order is natural): one pass
+      {  // too short to split (its shuffled order is natural), or not a
+         // power of two: one pass in layout
         char lab[64];
         std::snprintf(lab, sizeof lab, "vol%d DFT%lld", axis, (long long)n[axis]);
         if (inner == 1) {
           Field f[1] = {{outer, n[axis], n[axis]}};
-          b.add((int)n[axis], MODE_ROW, MODE_ROW, 0, f, 1, 1, 1, 0, 0, 0, lab);
+          axis_pass(b, n[axis], MODE_ROW, MODE_ROW, f, 1, 1, 1, lab);
         } else {
           Field f[2] = {{inner, 1, 1}, {outer, n[axis] * inner, n[axis] * inner}};
-          b.add((int)n[axis], MODE_COL, MODE_COL, 0, f, 2, inner, inner, 0, 0, 0, lab);
+          axis_pass(b, n[axis], MODE_COL, MODE_COL, f, 2, inner, inner, lab);
         }
       }
     }

@@ -91,7 +91,7 @@ const KernelInfo* find_mixed_kernel(int64_t n, uint64_t code, int tile) {
     for (const KernelInfo& k : kernel_registry())
       if (k.mixed && k.fixed_n == n && k.fixed_code == code) return &k;
   for (const KernelInfo& k : kernel_registry())
-    if (k.mixed == variant && k.fixed_n == 0 && k.n >= n &&
+    if (k.mixed == variant && k.fixed_n == 0 && k.n > n &&
         mixed_kernel_runs(k.mixed, k.n, code)) {
       if (tile > 0 && k.tile == tile) return &k;  // the asked-for tile, if any
       if (!best || k.n < best->n) best = &k;      // else the first, smallest

@@ -78,15 +78,32 @@ SHAPES = [
 ]
 
 
+_refs = {}
+
+
+def direct_ref(x, sign):
+    """The oracle's direct sums of x (kept for the next schedule of the same
+    shape)."""
+    key = (x.shape, sign)
+    if key not in _refs:
+        if len(_refs) > 8:
+            _refs.clear()
+        _refs[key] = oracle.dft3d(x.astype(np.complex128), sign, "direct")
+    return _refs[key]
+
+
+@pytest.mark.parametrize("schedule", ["pencil", "auto", "slab", "volumetric"])
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("schedule", ["pencil", "auto"])
 def test_other_lengths_forward_inverse(shape, schedule):
+    """Every schedule: the pencil passes rotate; slab and volumetric keep the
+    layout (an axis that is not a power of two runs as one pass in layout,
+    with the general pencil index where the pencil counts need it)."""
     say("case other length", shape, schedule)
     x = inputs.uniform_c64(shape, 31)
     t = tol_bl(shape)
     for sign, inv in ((-1, False), (1, True)):
         y = gpu_fftn(x, inv, schedule)
-        ref = oracle.dft3d(x.astype(np.complex128), sign, "direct")
+        ref = direct_ref(x, sign)
         err = oracle.rel_l2(y, ref)
         say("  sign", sign, "rel_l2", err, "tol", t)
         assert err <= t, (shape, sign, err)
@@ -120,15 +137,18 @@ def test_other_lengths_special_inputs():
     assert np.max(np.abs(gpu_fftn(x) - ref)) < 2e-6
 
 
-@pytest.mark.parametrize("shape", [(1000, 1000, 100), (1009, 1000, 64)])
-def test_other_lengths_full_size_sampled(shape):
+@pytest.mark.parametrize("shape,schedule", [((1000, 1000, 100), "auto"),
+                                            ((1009, 1000, 64), "auto"),
+                                            ((1000, 1000, 100), "slab"),
+                                            ((1009, 1000, 64), "volumetric")])
+def test_other_lengths_full_size_sampled(shape, schedule):
     """1000 x 1000 x 100 (mixed radix on every axis) and 1009 x 1000 x 64
     (Bluestein, mixed radix, power of two): sampled output pencils against
     the oracle's direct sums, Parseval, round trip."""
-    say("case other lengths full size", shape)
+    say("case other lengths full size", shape, schedule)
     x = inputs.uniform_c64(shape, 33)
     xt = torch.from_numpy(x).cuda()
-    y = dft3d.fftn(xt, schedule="auto")
+    y = dft3d.fftn(xt, schedule=schedule)
     torch.cuda.synchronize()
     N = x.size
     t = tol_bl(shape)
@@ -143,7 +163,7 @@ def test_other_lengths_full_size_sampled(shape):
     ex = torch.sum(torch.view_as_real(xt).double() ** 2).item()
     ey = torch.sum(torch.view_as_real(y).double() ** 2).item()
     assert abs(ey / (N * ex) - 1.0) <= 2 * t
-    back = dft3d.fftn(y, schedule="auto", inverse=True)
+    back = dft3d.fftn(y, schedule=schedule, inverse=True)
     d = torch.view_as_real(back).double() / N - torch.view_as_real(xt).double()
     rt = (torch.linalg.vector_norm(d) /
           torch.linalg.vector_norm(torch.view_as_real(xt).double())).item()
@@ -165,13 +185,14 @@ def test_other_lengths_in_a_batch():
         assert oracle.rel_l2(y.cpu().numpy(), ref) <= tol_bl(x.shape)
 
 
-def test_other_lengths_rejected_by_other_schedules():
+def test_other_lengths_rejected_forms():
+    """Split-precision leaves and the shuffled layout are powers of two only."""
     x = torch.zeros((3, 4, 4), dtype=torch.complex64, device="cuda")
-    for sched in ("slab", "volumetric"):
+    for sched in ("pencil", "slab", "volumetric"):
         with pytest.raises(dft3d.Dft3dError):
-            dft3d.fftn(x, schedule=sched)
+            dft3d.fftn(x, schedule=sched, precision="bf16x6")
     with pytest.raises(dft3d.Dft3dError):
-        dft3d.fftn(x, schedule="pencil", precision="bf16x6")
+        dft3d.fftn(x, schedule="volumetric", layout="shuffled")
 
 
 @pytest.mark.parametrize("tile", [1, 2, 4, 8])

@@ -19,13 +19,22 @@ SHAPES = [(1, 1, 1), (2, 4, 8), (8, 2, 4), (16, 16, 16), (32, 4, 64), (4, 64, 2)
           (2, 256, 8), (64, 1, 32), (4096, 2, 1), (1, 2, 2048)]
 
 
+def fields(args, b=None):
+    """The pencil index split into its three fields: bit fields, or with
+    s0 = -1 the general form b mod m0, (b div m0) mod m1, b div (m0 m1)."""
+    if b is None:
+        b = np.arange(args["B"], dtype=np.int64)
+    if args["s0"] < 0:
+        m0, m1 = args["m0"], args["m1"]
+        return b % m0, (b // m0) % m1, b // (m0 * m1)
+    return b & args["m0"], (b >> args["s0"]) & args["m1"], b >> args["s1"]
+
+
 def addresses(args, n, inp):
-    B = args["B"]
-    b = np.arange(B, dtype=np.int64)
     st = args["is"] if inp else args["os"]
     js = args["ijs"] if inp else args["oks"]
-    base = ((b >> args["s1"]) * st[2] + ((b >> args["s0"]) & args["m1"]) * st[1]
-            + (b & args["m0"]) * st[0])
+    f0, f1, f2 = fields(args)
+    base = f2 * st[2] + f1 * st[1] + f0 * st[0]
     j = np.arange(n, dtype=np.int64)
     return base[:, None] + j[None, :] * js        # (B, n)
 
@@ -178,8 +187,8 @@ def check_pass_maps(d, N):
                 for inp in (True, False):
                     st = a["is"] if inp else a["os"]
                     js = a["ijs"] if inp else a["oks"]
-                    base = ((b >> a["s1"]) * st[2] + ((b >> a["s0"]) & a["m1"]) * st[1]
-                            + (b & a["m0"]) * st[0])
+                    f0, f1, f2 = fields(a, b)
+                    base = f2 * st[2] + f1 * st[1] + f0 * st[0]
                     off = p["in_off"] if inp else p["out_off"]
                     hi = base.max() + (pass_points(p) - 1) * js + off
                     assert base.min() + off >= 0 and hi < N, (p["label"], inp)
@@ -385,8 +394,9 @@ def test_bluestein_pass_maps_injective_and_in_bounds(shape):
     check_pass_maps(dft3d.describe(shape, "pencil"), shape[0] * shape[1] * shape[2])
 
 
-@pytest.mark.parametrize("schedule,opts", [("slab", {}), ("volumetric", {}),
-                                           ("pencil", {"precision": "bf16x6"})])
+@pytest.mark.parametrize("schedule,opts", [("pencil", {"precision": "bf16x6"}),
+                                           ("slab", {"precision": "fp16x3"}),
+                                           ("volumetric", {"move_only": 1})])
 def test_bluestein_limits(schedule, opts):
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((3, 4, 4), schedule, **opts)
@@ -394,6 +404,42 @@ def test_bluestein_limits(schedule, opts):
         dft3d.describe((4097, 4, 4), "pencil")
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((3, 4, 4), "auto", "shuffled")
+
+
+@pytest.mark.parametrize("shape", OTHER_SHAPES + [(20, 3, 64), (64, 64, 1000), (17, 4, 19),
+                                                  (1000, 64, 64), (64, 1000, 64)])
+@pytest.mark.parametrize("schedule", ["slab", "volumetric"])
+def test_other_lengths_on_slab_and_volumetric(shape, schedule):
+    """The slab and volumetric schedules over lengths that are not powers of
+    two: such axes run as one pass in layout (mixed radix or Bluestein);
+    pencil counts that are not powers of two before the last field use the
+    general index form (s0 = -1), which only those kernels read (a
+    power-of-two axis whose pencils need it runs through the mixed-radix
+    pass).  Every pass map is a bijection inside the buffers, and the pass
+    list computes the DFT forward and inverse (direct sums as reference)."""
+    d = dft3d.describe(shape, schedule)
+    assert d["schedule"] == schedule
+    N = shape[0] * shape[1] * shape[2]
+    for p in d["passes"]:
+        if p["args"]["s0"] < 0:
+            assert p["mixed"] or p["bluestein"], p["label"]
+    if schedule == "volumetric":
+        # axes that are powers of two with power-of-two axes after them are
+        # still split four-step style
+        for axis in range(3):
+            inner = int(np.prod(shape[axis + 1:]))
+            n = shape[axis]
+            split = n >= 4 and n & (n - 1) == 0 and inner & (inner - 1) == 0
+            labels = [p["label"] for p in d["passes"] if p["label"].startswith(f"vol{axis}")]
+            assert any(".V1" in l for l in labels) == split, (axis, labels)
+    check_pass_maps(d, N)
+    if N <= 1 << 16:
+        g = np.random.default_rng(sum(shape) + 5)
+        x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+        for sign in (-1, 1):
+            got = run_model(x, d, sign)
+            ref = oracle.dft3d(x, sign, "direct")
+            assert oracle.rel_l2(got, ref) < 1e-12, (shape, schedule, sign)
 
 
 def test_every_length_up_to_4096():
