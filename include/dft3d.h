@@ -157,6 +157,23 @@ enum dft3d_option {
                                 lengths 32^s r with r < 16 (32 .. 256,
                                 1024 .. 4096); other lengths keep leaves of
                                 16.  Other values: INVALID_ARG */
+  DFT3D_OPT_RADICES = 14,    /* the radix sequence of the passes of one
+                                length (Section 2.2: the 1D DFT as stages of
+                                smaller DFTs, eq. (3)): the stage radices, 8
+                                bits each, first stage in the lowest byte,
+                                each one of 2, 3, 4, 5, 7, 8, 10, 11, 13, 16,
+                                at most 8 stages, product n <= 2048 (the
+                                composites 10 and 16 only below 2048, not
+                                with 11 or 13).  FP32
+                                passes of length n without a four-step
+                                twiddle then run the mixed-radix kernel
+                                with these stages (powers of two too); other
+                                lengths keep their default.  0 = default
+                                (the compiled sequence of each length).
+                                Workgroup size is set by DFT3D_OPT_TILE:
+                                pencils per workgroup times the kernel's
+                                threads per pencil.  Other values:
+                                INVALID_ARG */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 
@@ -315,7 +332,8 @@ int dft3d_execute_noalloc(dft3d_plan_t plan, const void* in, void* out, int sign
 /* Autotuner (the choice of decomposition per problem size that Section 4
  * measures by hand): time candidate schedules and kernel options (pencil with and
  * without the persistent kernels, split long axes, other tiles, grouped
- * first passes; slab; volumetric) for a (n0, n1, n2) transform on the
+ * first passes, other radix sequences for axis lengths that are not powers
+ * of two; slab; volumetric) for a (n0, n1, n2) transform on the
  * current device, on `in`
  * and `out` (device buffers of n0 n1 n2 complex64; out is overwritten), in
  * stream order on `stream`, and record the fastest: DFT3D_SCHED_AUTO plans

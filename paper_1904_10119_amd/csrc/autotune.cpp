@@ -4,14 +4,16 @@
 // architecture name and the shape, optionally mirrored to a text file
 // (DFT3D_TUNE_CACHE): one line per entry,
 //   arch n0 n1 n2 schedule tile xcd_remap split_max nontemporal persistent
-//   slab_group pencil_group milliseconds
+//   slab_group pencil_group radices milliseconds
 // Lines whose architecture differs from the current device are ignored.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dft3d.h"
 #include "internal.h"
@@ -59,10 +61,11 @@ void load_file_locked() {
   char arch[64];
   long long n0, n1, n2;
   int sched, tile, xcd, split, nt, pers, group, pgroup;
+  unsigned long long radices;
   double ms;
-  while (std::fscanf(f, "%63s %lld %lld %lld %d %d %d %d %d %d %d %d %lf", arch, &n0, &n1,
-                     &n2, &sched, &tile, &xcd, &split, &nt, &pers, &group, &pgroup,
-                     &ms) == 13) {
+  while (std::fscanf(f, "%63s %lld %lld %lld %d %d %d %d %d %d %d %d %llu %lf", arch, &n0, &n1,
+                     &n2, &sched, &tile, &xcd, &split, &nt, &pers, &group, &pgroup, &radices,
+                     &ms) == 14) {
     const int64_t n[3] = {n0, n1, n2};
     TuneEntry e;
     e.schedule = sched;
@@ -73,6 +76,7 @@ void load_file_locked() {
     e.opt.persistent = pers;
     e.opt.slab_group = group;
     e.opt.pencil_group = pgroup;
+    e.opt.radices = radix_code_valid(radices) ? radices : 0;
     e.ms = ms;
     g_tune[key_of(arch, n)] = e;
   }
@@ -87,9 +91,10 @@ void save_file_locked() {
   if (!f) return;
   for (const auto& kv : g_tune) {
     const TuneEntry& e = kv.second;
-    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.6f\n", kv.first.c_str(), e.schedule,
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d %llu %.6f\n", kv.first.c_str(), e.schedule,
                  e.opt.tile, e.opt.xcd_remap, e.opt.split_max, e.opt.nontemporal,
-                 e.opt.persistent, e.opt.slab_group, e.opt.pencil_group, e.ms);
+                 e.opt.persistent, e.opt.slab_group, e.opt.pencil_group,
+                 (unsigned long long)e.opt.radices, e.ms);
   }
   std::fclose(f);
   std::rename(tmp.c_str(), path);
@@ -117,9 +122,10 @@ extern "C" int dft3d_autotune(int64_t n0, int64_t n1, int64_t n2, const void* in
   if (!in || !out) return DFT3D_ERR_INVALID_ARG;
   struct Cand {
     int schedule;
-    int key, value;  // one option on top of the defaults (key 0: none)
+    int key;        // one option on top of the defaults (key 0: none)
+    int64_t value;
   };
-  static const Cand cands[] = {
+  static const Cand fixed_cands[] = {
       {DFT3D_SCHED_PENCIL, 0, 0},
       {DFT3D_SCHED_PENCIL, DFT3D_OPT_PERSISTENT, 0},
       {DFT3D_SCHED_PENCIL, DFT3D_OPT_PENCIL_GROUP, -1},
@@ -132,6 +138,46 @@ extern "C" int dft3d_autotune(int64_t n0, int64_t n1, int64_t n2, const void* in
       {DFT3D_SCHED_SLAB, DFT3D_OPT_PERSISTENT, 0},
       {DFT3D_SCHED_VOLUMETRIC, 0, 0},
   };
+  std::vector<Cand> cands(std::begin(fixed_cands), std::end(fixed_cands));
+  // radix sequences: for each axis length with a mixed-radix pass, the
+  // default stage order reversed (powers of two first) and the power of two
+  // in radix-4 stages, on the pencil schedule
+  {
+    const int64_t lens[3] = {n0, n1, n2};
+    for (int d = 0; d < 3; ++d) {
+      const int64_t n = lens[d];
+      bool seen = false;
+      for (int e = 0; e < d; ++e) seen = seen || lens[e] == n;
+      if (seen || n < 2 || n > 2048 || (n & (n - 1)) == 0) continue;
+      const uint64_t code = mixed_radix_code(n);
+      if (!code) continue;
+      std::vector<int> r;
+      for (uint64_t c = code; c; c >>= 8) r.push_back((int)(c & 255));
+      std::vector<uint64_t> alts;
+      {  // reversed
+        uint64_t a = 0;
+        for (size_t i = 0; i < r.size(); ++i) a |= (uint64_t)r[r.size() - 1 - i] << (8 * i);
+        alts.push_back(a);
+      }
+      {  // odd radices kept, the power of two as radix-4 stages (and one 2)
+        std::vector<int> q;
+        int64_t two = 1;
+        for (int x : r) {
+          if (x == 2 || x == 4 || x == 8 || x == 16) two *= x;
+          else if (x == 10) { q.push_back(5); two *= 2; }
+          else q.push_back(x);
+        }
+        while (two >= 4) { q.push_back(4); two /= 4; }
+        if (two == 2) q.push_back(2);
+        uint64_t a = 0;
+        for (size_t i = 0; i < q.size() && i < 8; ++i) a |= (uint64_t)q[i] << (8 * i);
+        if (q.size() <= 8) alts.push_back(a);
+      }
+      for (uint64_t a : alts)
+        if (a != code && radix_code_valid(a) && radix_code_length(a) == n)
+          cands.push_back(Cand{DFT3D_SCHED_PENCIL, DFT3D_OPT_RADICES, (int64_t)a});
+    }
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

@@ -81,8 +81,8 @@ int rebuild(dft3d_plan_s* p) {
   // the filter stored right after the chirp)
   std::map<int64_t, int64_t> offsets;
   std::map<std::pair<int, int64_t>, int64_t> bl_offsets;
-  // mixed-radix stage twiddles per length n (key: n, value: offset)
-  std::map<int64_t, std::pair<int64_t, uint64_t>> mx_offsets;
+  // mixed-radix stage twiddles per length n and radix code (value: offset)
+  std::map<std::pair<int64_t, uint64_t>, int64_t> mx_offsets;
   int64_t total = 0;
   std::vector<const Pass*> all;
   for (const Pass& ps : passes) all.push_back(&ps);
@@ -90,10 +90,10 @@ int rebuild(dft3d_plan_s* p) {
   for (const Pass* pp : all) {
     const Pass& ps = *pp;
     if (ps.k->mixed) {
-      const int64_t len = ps.args.res_mask;
-      if (!mx_offsets.count(len)) {
-        mx_offsets[len] = {total, (uint64_t)ps.args.twp_mask};
-        total += len;
+      const std::pair<int64_t, uint64_t> key{ps.args.res_mask, (uint64_t)ps.args.twp_mask};
+      if (!mx_offsets.count(key)) {
+        mx_offsets[key] = total;
+        total += key.first;
       }
       continue;
     }
@@ -122,7 +122,7 @@ int rebuild(dft3d_plan_s* p) {
       make_leaf_table((int)-kv.first, reinterpret_cast<unsigned short*>(host.data() + kv.second));
   }
   for (auto& kv : mx_offsets)
-    make_mixed_twiddles(kv.first, kv.second.second, host.data() + kv.second.first);
+    make_mixed_twiddles(kv.first.first, kv.first.second, host.data() + kv.second);
   for (auto& kv : bl_offsets) {
     if (kv.first.first == 1)
       make_chirp(kv.first.second, host.data() + kv.second);
@@ -152,7 +152,7 @@ int rebuild(dft3d_plan_s* p) {
     twp.clear();
     for (const Pass& ps : list) {
       if (ps.k->mixed) {  // the stage twiddles of the length
-        tw.push_back(mx_offsets[ps.args.res_mask].first);
+        tw.push_back(mx_offsets[{ps.args.res_mask, (uint64_t)ps.args.twp_mask}]);
         twp.push_back(0);
         continue;
       }
@@ -235,6 +235,10 @@ int apply_option(Options& o, int key, int64_t value) {
     case DFT3D_OPT_MFMA_LEAF:
       if (value != 0 && value != 16 && value != 32) return DFT3D_ERR_INVALID_ARG;
       o.mfma_leaf = (int)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_RADICES:
+      if (!radix_code_valid((uint64_t)value)) return DFT3D_ERR_INVALID_ARG;
+      o.radices = (uint64_t)value;
       return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
@@ -492,6 +496,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_BATCH_LAUNCH: *value = p->opt.batch_launch; break;
     case DFT3D_OPT_MOVE_ONLY: *value = p->opt.move_only; break;
     case DFT3D_OPT_MFMA_LEAF: *value = p->opt.mfma_leaf; break;
+    case DFT3D_OPT_RADICES: *value = (int64_t)p->opt.radices; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }

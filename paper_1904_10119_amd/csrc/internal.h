@@ -88,6 +88,12 @@ const KernelInfo* find_mixed_kernel(int64_t n, uint64_t code, int tile);
 uint64_t mixed_radix_code(int64_t n);
 // The kernel variant a radix code needs.
 int mixed_variant(uint64_t code);
+// Whether a radix code is 0 or lists 1..8 stages of the mixed-radix
+// kernel's radices (2, 3, 4, 5, 7, 8, 10, 11, 13, 16) whose product is at
+// most 2048 and that a compiled mixed-radix kernel runs at that length.
+bool radix_code_valid(uint64_t code);
+// The product of a radix code's stages.
+int64_t radix_code_length(uint64_t code);
 // Whether a length is supported: every length 1..4096 (powers of two,
 // mixed radix when the prime factors are at most 13, else Bluestein with a
 // convolution length up to 8192).
@@ -158,6 +164,8 @@ struct Options {
   int batch_launch = 0; // batched calls: 0 one launch per pass level, 1 one persistent launch
   int move_only = 0;    // 1: radix stages removed from every pass, 2: every pass a plain copy
   int mfma_leaf = 0;    // split-precision passes: leaf length 16 or 32, 0: default per length
+  uint64_t radices = 0; // stage radices (8 bits each, first stage lowest) for the passes
+                        // of their product's length, run by the mixed-radix kernel; 0: default
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

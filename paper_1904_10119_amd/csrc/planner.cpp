@@ -176,6 +176,12 @@ struct Builder {
       add_mixed(n, f, nf, ijs, oks, label + " mixed");
       return;
     }
+    if (opt.radices && radix_code_length(opt.radices) == n && !tw &&
+        opt.precision == DFT3D_PREC_FP32 && !opt.move_only) {
+      // a radix sequence asked for this length: the mixed-radix pass runs it
+      add_mixed(n, f, nf, ijs, oks, label + " radices");
+      return;
+    }
     const KernelInfo* k = nullptr;
     int leaf = 0;
     if (nt_side && opt.precision == DFT3D_PREC_FP32 && !tw)
@@ -261,7 +267,8 @@ struct Builder {
   // (mixed_kernel.h documents the argument fields).
   void add_mixed(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
                  const std::string& label) {
-    const uint64_t code = mixed_radix_code(n);
+    const uint64_t code =
+        opt.radices && radix_code_length(opt.radices) == n ? opt.radices : mixed_radix_code(n);
     const KernelInfo* k = find_mixed_kernel(n, code, opt.tile);
     if (!k || !code) {
       status = DFT3D_ERR_UNSUPPORTED_SIZE;

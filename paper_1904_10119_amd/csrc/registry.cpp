@@ -144,6 +144,28 @@ int mixed_variant(uint64_t code) {
   return 1;
 }
 
+int64_t radix_code_length(uint64_t code) {
+  int64_t n = 1;
+  for (uint64_t c = code; c; c >>= 8) n *= (int64_t)(c & 255);
+  return n;
+}
+
+bool radix_code_valid(uint64_t code) {
+  if (code == 0) return true;
+  int stages = 0;
+  int64_t n = 1;
+  for (uint64_t c = code; c; c >>= 8) {
+    const int r = (int)(c & 255);
+    if (r != 2 && r != 3 && r != 4 && r != 5 && r != 7 && r != 8 && r != 10 && r != 11 &&
+        r != 13 && r != 16)
+      return false;  // a zero byte inside the code ends it early: rejected here too
+    n *= r;
+    if (++stages > 8 || n > 2048) return false;
+  }
+  // and a mixed-radix kernel runs the stages at that length
+  return find_mixed_kernel(n, code, 0) != nullptr;
+}
+
 bool length_supported(int64_t n) { return n >= 1 && n <= 4096; }
 
 const KernelInfo* find_bluestein_kernel(int m, int tile) {

@@ -22,6 +22,7 @@ PRECISIONS = {"fp32": 0, "bf16x1": 1, "fp16x1": 2, "bf16x6": 3, "bf16x9": 4,
 OPT_PRECISION, OPT_TILE, OPT_XCD_REMAP, OPT_SPLIT_MAX, OPT_NONTEMPORAL = 1, 2, 3, 4, 5
 OPT_PERSISTENT, OPT_SLAB_GROUP, OPT_FUSED_PLANE, OPT_FUSED_AXES = 6, 7, 8, 9
 OPT_PENCIL_GROUP, OPT_BATCH_LAUNCH, OPT_MOVE_ONLY, OPT_MFMA_LEAF = 10, 11, 12, 13
+OPT_RADICES = 14
 OPT_NUM_PASSES = 100
 
 OK = 0
@@ -100,15 +101,36 @@ OPTION_KEYS = {"precision": OPT_PRECISION, "tile": OPT_TILE,
                "slab_group": OPT_SLAB_GROUP, "fused_plane": OPT_FUSED_PLANE,
                "fused_axes": OPT_FUSED_AXES, "pencil_group": OPT_PENCIL_GROUP,
                "batch_launch": OPT_BATCH_LAUNCH, "move_only": OPT_MOVE_ONLY,
-               "mfma_leaf": OPT_MFMA_LEAF}
+               "mfma_leaf": OPT_MFMA_LEAF, "radices": OPT_RADICES}
+
+
+def radix_code(radices) -> int:
+    """DFT3D_OPT_RADICES value of a radix sequence (first stage first), or
+    the value itself if given as an int."""
+    if isinstance(radices, int):
+        return radices
+    radices = [int(r) for r in radices]
+    if len(radices) > 8 or any(not 0 < r < 256 for r in radices):
+        raise ValueError(f"radix sequence {radices}: at most 8 stages of 1..255")
+    code = 0
+    for i, r in enumerate(radices):
+        code |= r << (8 * i)
+    return code
+
+
+def _option_value(key, value) -> int:
+    if key == "precision":
+        return PRECISIONS[value]
+    if key == "radices":
+        return radix_code(value)
+    return int(value)
 
 
 def describe(shape: Sequence[int], schedule: str = "auto",
              layout: str = "natural", **opts) -> dict:
     """Pass list the library would run for `shape` (no device needed)."""
     n0, n1, n2 = (int(s) for s in shape)
-    items = [(OPTION_KEYS[k], PRECISIONS[v] if k == "precision" else int(v))
-             for k, v in opts.items()]
+    items = [(OPTION_KEYS[k], _option_value(k, v)) for k, v in opts.items()]
     keys = (ctypes.c_int * max(1, len(items)))(*[k for k, _ in items])
     vals = (ctypes.c_int64 * max(1, len(items)))(*[v for _, v in items])
     need = ctypes.c_size_t(0)
@@ -146,7 +168,7 @@ class Plan:
                  nontemporal: int = -1, persistent: int = -1,
                  slab_group: int = -2, fused_plane: int = -1, fused_axes: int = -1,
                  pencil_group: int = -2, batch_launch: int = -1, move_only: int = 0,
-                 mfma_leaf: int = 0):
+                 mfma_leaf: int = 0, radices=0):
         self.shape = tuple(int(s) for s in shape)
         self.schedule = schedule
         h = ctypes.c_void_p()
@@ -182,6 +204,8 @@ class Plan:
                 self.set_option(OPT_MOVE_ONLY, move_only)
             if mfma_leaf:
                 self.set_option(OPT_MFMA_LEAF, mfma_leaf)
+            if radices:
+                self.set_option(OPT_RADICES, radix_code(radices))
         except Exception:
             self.close()
             raise
@@ -262,6 +286,8 @@ _plans: Dict[Tuple, Plan] = {}
 
 
 def get_plan(shape, schedule="auto", precision="fp32", device_index=0, **opts) -> Plan:
+    if "radices" in opts:
+        opts["radices"] = radix_code(opts["radices"])
     key = (tuple(int(s) for s in shape), schedule, precision, device_index,
            tuple(sorted(opts.items())))
     p = _plans.get(key)

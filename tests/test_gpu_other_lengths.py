@@ -248,3 +248,52 @@ def test_fixed_length_kernels(n):
             y = gpu_fftn(x, inv)
             err = oracle.rel_l2(y, oracle.dft3d(x.astype(np.complex128), sign, "direct"))
             assert err <= tol_bl(shape), (shape, sign, err)
+
+
+RADIX_CASES = [((4, 2, 1000), [10, 10, 10]), ((4, 2, 1000), [8, 5, 5, 5]),
+               ((2, 4, 1024), [4, 4, 4, 4, 4]), ((2, 4, 64), [4, 16]), ((8, 3, 96), [2, 3, 16]),
+               ((6, 4, 143), [13, 11]), ((2, 2, 2048), [8, 8, 8, 4]), ((2, 8, 8), [2, 4]),
+               ((16, 1000, 3), [5, 8, 5, 5])]
+
+
+@pytest.mark.parametrize("shape,radices", RADIX_CASES)
+def test_radix_sequence_option(shape, radices):
+    """DFT3D_OPT_RADICES: the passes of the sequence's length run the
+    mixed-radix kernel with those stages (powers of two included), forward
+    and inverse against the oracle's direct sums, and against the default
+    plan."""
+    say("case radices", shape, radices)
+    x = inputs.uniform_c64(shape, 50)
+    xt = torch.from_numpy(x).cuda()
+    t = tol_bl(shape) + 1e-6 / 18  # one more rounding level at most for the stage order
+    for sign, inv in ((-1, False), (1, True)):
+        p = dft3d.Plan(shape, "pencil", radices=radices)
+        assert p.get_option(dft3d.OPT_RADICES) == dft3d.radix_code(radices)
+        y = torch.empty_like(xt)
+        p.execute(xt, y, inverse=inv)
+        torch.cuda.synchronize()
+        p.close()
+        got = y.cpu().numpy()
+        ref = direct_ref(x, sign)
+        err = oracle.rel_l2(got, ref)
+        say("  sign", sign, "rel_l2", err)
+        assert err <= t, (shape, radices, sign, err)
+        assert oracle.rel_l2(got, gpu_fftn(x, inv)) <= 2 * t
+
+
+def test_autotune_other_lengths_radix_candidates(tmp_path, monkeypatch):
+    """The autotuner on a shape with mixed-radix axes also times other radix
+    sequences; the recorded choice (whatever wins) is written to the cache
+    file with its radix code, and a later AUTO plan of the shape matches the
+    oracle."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("DFT3D_TUNE_CACHE", str(cache))
+    shape = (60, 100, 96)
+    r = dft3d.autotune(shape)
+    say("autotune", shape, r)
+    assert r["ms"] > 0
+    line = [l for l in cache.read_text().splitlines() if " 60 100 96 " in l]
+    assert len(line) == 1 and len(line[0].split()) == 14, line
+    x = inputs.uniform_c64(shape, 51)
+    y = gpu_fftn(x, schedule="auto")
+    assert oracle.rel_l2(y, direct_ref(x, -1)) <= tol_bl(shape) + 1e-6 / 18

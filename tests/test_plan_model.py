@@ -499,6 +499,43 @@ def test_mixed_stage_formulas(n):
     assert oracle.rel_l2(got, oracle.dft3d(x.reshape(n, 1, 1), -1, "direct").reshape(-1)) < 1e-12
 
 
+RADIX_CASES = [((4, 2, 1000), [10, 10, 10]), ((4, 2, 1000), [8, 5, 5, 5]),
+               ((2, 4, 1024), [4, 4, 4, 4, 4]), ((2, 4, 64), [4, 16]), ((8, 3, 96), [2, 3, 16]),
+               ((6, 4, 143), [13, 11]), ((2, 2, 2048), [8, 8, 8, 4]), ((2, 8, 8), [2, 4])]
+
+
+@pytest.mark.parametrize("shape,radices", RADIX_CASES)
+def test_radices_option(shape, radices):
+    """DFT3D_OPT_RADICES: the passes of the code's length run the mixed-radix
+    kernel with those stages (powers of two too), other lengths keep their
+    default; the stage formulas with that code give the DFT, and the pass
+    list computes the 3D DFT."""
+    n = int(np.prod(radices))
+    d = dft3d.describe(shape, "pencil", radices=radices)
+    hits = [p for p in d["passes"] if pass_points(p) == n]
+    assert hits and all(p["mixed"] and p["radices"] == radices for p in hits)
+    x1 = np.random.default_rng(n).standard_normal(n) + 1j * np.random.default_rng(n + 7).standard_normal(n)
+    got = stockham_mixed(x1, radices)
+    assert oracle.rel_l2(got, oracle.dft3d(x1.reshape(n, 1, 1), -1, "direct").reshape(-1)) < 1e-12
+    check_pass_maps(d, int(np.prod(shape)))
+    g = np.random.default_rng(3)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    method = "fft" if all(m & (m - 1) == 0 for m in shape) else "direct"
+    for sign in (-1, 1):
+        assert oracle.rel_l2(run_model(x, d, sign), oracle.dft3d(x, sign, method)) < 1e-12
+
+
+@pytest.mark.parametrize("radices", [[6, 5], [4, 0, 4], [16, 16, 16], [2] * 9, [1, 4], [17],
+                                     [16, 16, 8], [11, 10], [13, 16]])
+def test_radices_option_rejects(radices):
+    """Radices outside the kernel's set, a zero stage inside the code, a
+    product above 2048, more than 8 stages and composites the kernels do not
+    run at that length (16 at 2048, 10 or 16 beside 11 or 13) are
+    rejected."""
+    with pytest.raises((dft3d.Dft3dError, ValueError)):
+        dft3d.describe((4, 4, 64), "pencil", radices=radices)
+
+
 try:
     from hypothesis import given, settings, strategies as st
 except ImportError:  # pragma: no cover
