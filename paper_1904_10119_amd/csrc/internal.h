@@ -78,11 +78,12 @@ const KernelInfo* find_plane_kernel(int n1, int n2);
 // 10 and 16 up to a tile length of 2048; variant 2: 11 and 13, no
 // composites) runs every stage radix of a code.
 bool mixed_kernel_runs(int variant, int nmax, uint64_t code);
-// The mixed-radix pass kernel for length n and its radix code, among those
-// that run the code: the one with the given tile (pencils per workgroup) if
-// compiled, else the first registered with the smallest tile length >= n;
-// null if none.
-const KernelInfo* find_mixed_kernel(int64_t n, uint64_t code, int tile);
+// The mixed-radix pass kernel for length n, its radix code and the load
+// and store modes, among those that run the code: the one with the given
+// tile (pencils per workgroup) if compiled, else the first registered with
+// the smallest tile length above n; null if none.
+const KernelInfo* find_mixed_kernel(int64_t n, uint64_t code, int tile,
+                                    int lmode = MODE_ROW, int smode = MODE_COL);
 // Stage radices of a mixed-radix pass of length n, 8 bits per stage, first
 // stage lowest; 0 if n has a prime factor above 13 or is 1.
 uint64_t mixed_radix_code(int64_t n);

@@ -224,10 +224,13 @@ __device__ __forceinline__ void mixed_first_stage(const float2* s, int64_t ijs, 
   mixed_first_compute<R, V>(a, conj, pen, n, p, P);
 }
 
-// The later stages (radices in code, ns = the first radix) and the rotated
-// store of the tile's pencils (thread covers pencil tid mod T, outputs
-// k = tid / T + (TH / T) i).
-template <int T, int NMAX, int TH, int VAR>
+// The later stages (radices in code, ns = the first radix) and the store
+// of the tile's pencils: COL (rotated: consecutive pencils contiguous)
+// with the thread on pencil tid mod T and outputs k = tid / T + (TH / T) i,
+// so lanes run across the pencils; ROW (the pencil's own points
+// contiguous) with the thread on pencil tid / P and outputs k = p + P i, so
+// lanes run along the pencil.
+template <int T, int NMAX, int TH, int VAR, int SM = MODE_COL>
 __device__ __forceinline__ void mixed_rest(uint64_t code, int ns, float2* buf, float2* pen,
                                            const float2* twv, float2* dst, const PassArgs& a,
                                            int64_t tile, int n, int sq, int tid, int p) {
@@ -241,6 +244,23 @@ __device__ __forceinline__ void mixed_rest(uint64_t code, int ns, float2* buf, f
       mixed_stage<decltype(rc)::value, V>(pen, n, ns, twv, p, P);
     });
     ns *= R;
+  }
+  if constexpr (SM == MODE_ROW) {
+    const int q = tid / P;
+    const int64_t b = tile * T + q;
+    if (b < a.B) {
+      float2* d = dst + pencil_offset_any(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const int k = p + P * i;
+        if (k < n) {
+          float2 w = pen[k];
+          if (a.conj_out) w.y = -w.y;
+          d[k * a.oks] = w;
+        }
+      }
+    }
+    return;
   }
   const int qs = tid % T;
   const int64_t b = tile * T + qs;
@@ -267,8 +287,13 @@ __device__ __forceinline__ void mixed_rest(uint64_t code, int ns, float2* buf, f
 }
 
 // VAR: 1 without the radix-11 and radix-13 stages (whose registers would
-// lower the occupancy of every other stage too), 2 with them.
-template <int T, int NMAX, int TH, int VAR>
+// lower the occupancy of every other stage too), 2 with them.  LM, SM: the
+// load and store modes.  ROW loads run the first stage straight from
+// global memory (lanes along each pencil); COL loads (consecutive pencils
+// contiguous, the pencil's points at stride ijs) first copy the tile into
+// LDS with lanes across the pencils (thread on pencil tid mod T), then run
+// the first stage from there.
+template <int T, int NMAX, int TH, int VAR, int LM = MODE_ROW, int SM = MODE_COL>
 __global__ void __launch_bounds__(TH)
 fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
                  const float2* __restrict__ twp, const PassArgs a) {
@@ -295,7 +320,33 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
   }
   uint64_t code = (uint64_t)a.twp_mask;
   int ns;
-  {
+  if constexpr (LM == MODE_COL) {
+    {  // the tile into LDS, lanes across the pencils
+      const int qs = tid % T;
+      int64_t b = tile * T + qs;
+      b = b < a.B ? b : a.B - 1;
+      const float2* s =
+          src + pencil_offset_any(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+      float2* ps = buf + qs * sq;
+      constexpr int KS = TH / T;
+#pragma unroll
+      for (int i = 0; i < NMAX / KS; ++i) {
+        const int k = tid / T + KS * i;
+        if (k < n) ps[k] = s[(int64_t)k * a.ijs];
+      }
+    }
+    __syncthreads();  // the tile is in LDS
+    const int R = (int)(code & 255);
+    code >>= 8;
+    with_radix<VAR, COMP>(R, [&](auto rc) {
+      constexpr int RR = decltype(rc)::value;
+      float2 v[(V + RR - 1) / RR][RR];
+      mixed_first_load<RR, V>(v, pen, 1, n, p, P);
+      __syncthreads();  // every input of the first stage is read
+      mixed_first_compute<RR, V>(v, a.conj_in, pen, n, p, P);
+    });
+    ns = R;
+  } else {
     // pencils past the end of a ragged last tile read the last pencil
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
@@ -307,7 +358,7 @@ fft_mixed_kernel(const float2* src, float2* dst, const float2* __restrict__ tw,
     });
     ns = R;
   }
-  mixed_rest<T, NMAX, TH, VAR>(code, ns, buf, pen, twv, dst, a, tile, n, sq, tid, p);
+  mixed_rest<T, NMAX, TH, VAR, SM>(code, ns, buf, pen, twv, dst, a, tile, n, sq, tid, p);
 }
 
 // Stages of a compile-time radix code (the first stage done, NS = its radix).
@@ -368,6 +419,9 @@ hipError_t launch_mixed_fixed(const PassArgs& a, const float2* src, float2* dst,
   return hipGetLastError();
 }
 
+// The compiled-length kernel reads pencils along their points and stores
+// across the pencils (the rotating pass); the registry also offers it for
+// the in-layout passes (the pass arguments carry the strides).
 template <int T, int NMAX, int TH, int N, uint64_t CODE>
 KernelInfo kernel_info_mixed_fixed() {
   constexpr int LDS = (T * NMAX + (2 * (T * NMAX + NMAX) * 8 <= 160 * 1024 ? NMAX : 0)) * 8;
@@ -380,7 +434,7 @@ KernelInfo kernel_info_mixed_fixed() {
   return k;
 }
 
-template <int T, int NMAX, int TH, int VAR>
+template <int T, int NMAX, int TH, int VAR, int LM = MODE_ROW, int SM = MODE_COL>
 hipError_t launch_mixed(const PassArgs& a, const float2* src, float2* dst, const float2* tw,
                         const float2* twp, hipStream_t stream) {
   const int64_t blocks = (a.B + T - 1) / T;
@@ -388,18 +442,17 @@ hipError_t launch_mixed(const PassArgs& a, const float2* src, float2* dst, const
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   if (a.res_mask < 2 || a.res_mask >= NMAX || !mixed_kernel_runs(VAR, NMAX, (uint64_t)a.twp_mask))
     return hipErrorInvalidValue;  // a stage radix this kernel does not run
-  hipLaunchKernelGGL((fft_mixed_kernel<T, NMAX, TH, VAR>), dim3((unsigned)blocks), dim3(TH), 0,
-                     stream, src, dst, tw, twp, a);
+  hipLaunchKernelGGL((fft_mixed_kernel<T, NMAX, TH, VAR, LM, SM>), dim3((unsigned)blocks),
+                     dim3(TH), 0, stream, src, dst, tw, twp, a);
   return hipGetLastError();
 }
 
-template <int T, int NMAX, int TH, int VAR>
+template <int T, int NMAX, int TH, int VAR, int LM = MODE_ROW, int SM = MODE_COL>
 KernelInfo kernel_info_mixed() {
   constexpr int LDS = (T * NMAX + (2 * (T * NMAX + NMAX) * 8 <= 160 * 1024 ? NMAX : 0)) * 8;
   static_assert(2 * LDS <= 160 * 1024, "two workgroups per CU");
   static_assert(TH % T == 0 && NMAX % (TH / T) == 0 && TH <= 1024, "tile shape");
-  KernelInfo k{NMAX, T, MODE_ROW, MODE_COL, 0, TH, LDS, &launch_mixed<T, NMAX, TH, VAR>, 0,
-               0};
+  KernelInfo k{NMAX, T, LM, SM, 0, TH, LDS, &launch_mixed<T, NMAX, TH, VAR, LM, SM>, 0, 0};
   k.mixed = VAR;
   return k;
 }

@@ -173,13 +173,13 @@ struct Builder {
         status = DFT3D_ERR_UNSUPPORTED_SCHEDULE;
         return;
       }
-      add_mixed(n, f, nf, ijs, oks, label + " mixed");
+      add_mixed(n, f, nf, ijs, oks, label + " mixed", lmode, smode);
       return;
     }
     if (opt.radices && radix_code_length(opt.radices) == n && !tw &&
         opt.precision == DFT3D_PREC_FP32 && !opt.move_only) {
       // a radix sequence asked for this length: the mixed-radix pass runs it
-      add_mixed(n, f, nf, ijs, oks, label + " radices");
+      add_mixed(n, f, nf, ijs, oks, label + " radices", lmode, smode);
       return;
     }
     const KernelInfo* k = nullptr;
@@ -266,10 +266,10 @@ struct Builder {
   // Mixed-radix pass of length n over the pencils of fields f
   // (mixed_kernel.h documents the argument fields).
   void add_mixed(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
-                 const std::string& label) {
+                 const std::string& label, int lmode = MODE_ROW, int smode = MODE_COL) {
     const uint64_t code =
         opt.radices && radix_code_length(opt.radices) == n ? opt.radices : mixed_radix_code(n);
-    const KernelInfo* k = find_mixed_kernel(n, code, opt.tile);
+    const KernelInfo* k = find_mixed_kernel(n, code, opt.tile, lmode, smode);
     if (!k || !code) {
       status = DFT3D_ERR_UNSUPPORTED_SIZE;
       return;
@@ -474,7 +474,7 @@ void axis_pass(Builder& b, int64_t n, int lmode, int smode, const Field* f, int 
     b.add((int)n, lmode, smode, 0, f, nf, ijs, oks, 0, 0, 0, label);
   } else if (mixed_radix_code(n)) {
     std::snprintf(lab, sizeof lab, "%s mixed", label);
-    b.add_mixed(n, f, nf, ijs, oks, lab);
+    b.add_mixed(n, f, nf, ijs, oks, lab, lmode, smode);
   } else {
     std::snprintf(lab, sizeof lab, "%s via %lld", label, (long long)bluestein_length(n));
     b.add_bluestein(n, f, nf, ijs, oks, lab);

@@ -84,15 +84,17 @@ bool mixed_kernel_runs(int variant, int nmax, uint64_t code) {
   return true;
 }
 
-const KernelInfo* find_mixed_kernel(int64_t n, uint64_t code, int tile) {
+const KernelInfo* find_mixed_kernel(int64_t n, uint64_t code, int tile, int lmode, int smode) {
   const int variant = mixed_variant(code);
   const KernelInfo* best = nullptr;
-  if (tile <= 0)  // a kernel compiled for this length and code, if any
+  if (tile <= 0)  // a kernel compiled for this length, code and modes, if any
     for (const KernelInfo& k : kernel_registry())
-      if (k.mixed && k.fixed_n == n && k.fixed_code == code) return &k;
+      if (k.mixed && k.fixed_n == n && k.fixed_code == code && k.lmode == lmode &&
+          k.smode == smode)
+        return &k;
   for (const KernelInfo& k : kernel_registry())
-    if (k.mixed == variant && k.fixed_n == 0 && k.n > n &&
-        mixed_kernel_runs(k.mixed, k.n, code)) {
+    if (k.mixed == variant && k.fixed_n == 0 && k.n > n && k.lmode == lmode &&
+        k.smode == smode && mixed_kernel_runs(k.mixed, k.n, code)) {
       if (tile > 0 && k.tile == tile) return &k;  // the asked-for tile, if any
       if (!best || k.n < best->n) best = &k;      // else the first, smallest
     }
