@@ -174,6 +174,17 @@ enum dft3d_option {
                                 pencils per workgroup times the kernel's
                                 threads per pencil.  Other values:
                                 INVALID_ARG */
+  DFT3D_OPT_RADER = 15,      /* prime lengths n whose n - 1 has no prime
+                                factor above 13: Rader's identity, the DFT
+                                as a cyclic convolution of length n - 1
+                                done with two mixed-radix FFTs of that
+                                length, instead of Bluestein (two FFTs of
+                                the power of two >= 2n - 1).  1 (default) =
+                                Rader for the primes a kernel is compiled
+                                for, 2 = for every such prime (a generic
+                                kernel for the others, measured slower than
+                                Bluestein), 0 = Bluestein.  Other values:
+                                INVALID_ARG */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 
@@ -192,10 +203,12 @@ const char* dft3d_status_string(int status);
  * the natural layout on every schedule (AUTO picks pencil), one pass per
  * such axis (rotate-on-write in the pencil schedule, in layout in the slab
  * and volumetric schedules): a mixed-radix pass (radices 2, 3, 4, 5, 7, 8,
- * 10, 11, 13, 16) when every prime factor of n_d is at most 13, else a
- * Bluestein pass (the DFT of length n as a circular convolution of length
- * m, the power of two >= 2n - 1, up to 8192, done with two power-of-two FFTs
- * in the same workgroup).  Split precisions, the shuffled layout and
+ * 10, 11, 13, 16) when every prime factor of n_d is at most 13, else for
+ * the primes n_d whose n_d - 1 has that property and that a Rader kernel is
+ * compiled for a Rader pass (a circular convolution of length n_d - 1 done
+ * with two mixed-radix FFTs, see DFT3D_OPT_RADER), else a Bluestein pass (the DFT of length n as a circular
+ * convolution of length m, the power of two >= 2n - 1, up to 8192, done
+ * with two power-of-two FFTs in the same workgroup).  Split precisions, the shuffled layout and
  * move-only plans with such lengths return UNSUPPORTED_SCHEDULE.  The
  * workspace is N * 8 bytes as for powers of two.  Validates the arguments
  * first

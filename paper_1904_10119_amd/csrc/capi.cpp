@@ -83,12 +83,26 @@ int rebuild(dft3d_plan_s* p) {
   std::map<std::pair<int, int64_t>, int64_t> bl_offsets;
   // mixed-radix stage twiddles per length n and radix code (value: offset)
   std::map<std::pair<int64_t, uint64_t>, int64_t> mx_offsets;
+  // Rader tables per prime length n (value: offset)
+  std::map<int64_t, int64_t> rd_offsets;
   int64_t total = 0;
   std::vector<const Pass*> all;
   for (const Pass& ps : passes) all.push_back(&ps);
   for (const Pass& ps : ipasses) all.push_back(&ps);
   for (const Pass* pp : all) {
     const Pass& ps = *pp;
+    if (ps.k->rader) {  // stage twiddles of n - 1, and the Rader tables of n
+      const std::pair<int64_t, uint64_t> key{ps.rader_n - 1, (uint64_t)ps.args.twp_mask};
+      if (!mx_offsets.count(key)) {
+        mx_offsets[key] = total;
+        total += key.first;
+      }
+      if (!rd_offsets.count(ps.rader_n)) {
+        rd_offsets[ps.rader_n] = total;
+        total += rader_table_size(ps.rader_n);
+      }
+      continue;
+    }
     if (ps.k->mixed) {
       const std::pair<int64_t, uint64_t> key{ps.args.res_mask, (uint64_t)ps.args.twp_mask};
       if (!mx_offsets.count(key)) {
@@ -123,6 +137,7 @@ int rebuild(dft3d_plan_s* p) {
   }
   for (auto& kv : mx_offsets)
     make_mixed_twiddles(kv.first.first, kv.first.second, host.data() + kv.second);
+  for (auto& kv : rd_offsets) make_rader_tables(kv.first, host.data() + kv.second);
   for (auto& kv : bl_offsets) {
     if (kv.first.first == 1)
       make_chirp(kv.first.second, host.data() + kv.second);
@@ -145,12 +160,17 @@ int rebuild(dft3d_plan_s* p) {
   p->tables = dev;
   p->passes.swap(passes);
   p->ipasses.swap(ipasses);
-  auto table_offsets = [&offsets, &bl_offsets, &mx_offsets](const std::vector<Pass>& list,
-                                                            std::vector<int64_t>& tw,
-                                                            std::vector<int64_t>& twp) {
+  auto table_offsets = [&offsets, &bl_offsets, &mx_offsets, &rd_offsets](
+                           const std::vector<Pass>& list, std::vector<int64_t>& tw,
+                           std::vector<int64_t>& twp) {
     tw.clear();
     twp.clear();
     for (const Pass& ps : list) {
+      if (ps.k->rader) {
+        tw.push_back(mx_offsets[{ps.rader_n - 1, (uint64_t)ps.args.twp_mask}]);
+        twp.push_back(rd_offsets[ps.rader_n]);
+        continue;
+      }
       if (ps.k->mixed) {  // the stage twiddles of the length
         tw.push_back(mx_offsets[{ps.args.res_mask, (uint64_t)ps.args.twp_mask}]);
         twp.push_back(0);
@@ -239,6 +259,10 @@ int apply_option(Options& o, int key, int64_t value) {
     case DFT3D_OPT_RADICES:
       if (!radix_code_valid((uint64_t)value)) return DFT3D_ERR_INVALID_ARG;
       o.radices = (uint64_t)value;
+      return DFT3D_OK;
+    case DFT3D_OPT_RADER:
+      if (value < 0 || value > 2) return DFT3D_ERR_INVALID_ARG;
+      o.rader = (int)value;
       return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
@@ -497,6 +521,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_MOVE_ONLY: *value = p->opt.move_only; break;
     case DFT3D_OPT_MFMA_LEAF: *value = p->opt.mfma_leaf; break;
     case DFT3D_OPT_RADICES: *value = (int64_t)p->opt.radices; break;
+    case DFT3D_OPT_RADER: *value = p->opt.rader; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }

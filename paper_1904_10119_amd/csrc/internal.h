@@ -63,6 +63,7 @@ struct KernelInfo {
                       // stages (butterflies and twiddles) removed; 2: a plain copy
   int r0 = 0, r1 = 0, r2 = 0;   // FP32 pass kernels: the radix of each stage (1: none)
   int mfma_leaf = 0;  // split-precision MFMA passes: the leaf length (16 or 32)
+  int rader = 0;      // > 0: Rader pass for prime lengths up to n - 1 (variant as mixed)
 };
 
 // All compiled pass kernels.
@@ -99,6 +100,18 @@ int64_t radix_code_length(uint64_t code);
 // mixed radix when the prime factors are at most 13, else Bluestein with a
 // convolution length up to 8192).
 bool length_supported(int64_t n);
+// Whether n is prime with n - 1 free of prime factors above 13 and a Rader
+// kernel runs it (the DFT of length n through two FFTs of length n - 1):
+// one compiled for n, or with any_kernel also the generic one.
+bool rader_length(int64_t n, bool any_kernel);
+// The Rader kernel for prime length n (the radix code of n - 1), with the
+// given tile if compiled, else the smallest tile length above n; null if none.
+const KernelInfo* find_rader_kernel(int64_t n, int tile);
+// Rader tables of prime length n: FFT_{n-1}(b) / (n - 1) with b[m] =
+// w_n^(g^-m), FP64-built (n - 1 entries), then the generator powers g^j mod
+// n (n - 1 32-bit integers, packed two per float2): rader_table_size slots.
+int64_t rader_table_size(int64_t n);
+void make_rader_tables(int64_t n, float2* out);
 // The one-pass Bluestein axis kernel of convolution length m with the given
 // tile, else the length's default tile; null if none is compiled.
 const KernelInfo* find_bluestein_kernel(int m, int tile);
@@ -145,6 +158,7 @@ struct Pass {
   int64_t twp_len = 0;  // post-twiddle table length, 0 if none
   int leaf = 0;         // precision of the MFMA leaf table the pass reads, 0: none
   int64_t bl_n = 0;     // Bluestein axis: the length n (tables: chirp, then filter)
+  int64_t rader_n = 0;  // Rader axis: the prime length n
   // Which ends of the pass follow the plan's buffer chain (IN -> OUT/WS
   // alternation); the others keep the buffers the planner set.
   bool chain_src = true, chain_dst = true;
@@ -167,6 +181,8 @@ struct Options {
   int mfma_leaf = 0;    // split-precision passes: leaf length 16 or 32, 0: default per length
   uint64_t radices = 0; // stage radices (8 bits each, first stage lowest) for the passes
                         // of their product's length, run by the mixed-radix kernel; 0: default
+  int rader = 1;        // prime lengths with smooth n - 1: 0 Bluestein, 1 Rader where a
+                        // kernel is compiled for n, 2 Rader also with the generic kernel
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

@@ -263,6 +263,29 @@ struct Builder {
     passes.push_back(p);
   }
 
+  // Rader pass of prime length n over the pencils of fields f (rader.h
+  // documents the argument fields).
+  void add_rader(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
+                 const std::string& label) {
+    const KernelInfo* k = find_rader_kernel(n, opt.tile);
+    const uint64_t code = mixed_radix_code(n - 1);
+    if (!k || !code) {
+      status = DFT3D_ERR_UNSUPPORTED_SIZE;
+      return;
+    }
+    Pass p;
+    p.k = k;
+    set_fields(p.args, f, nf);
+    p.args.ijs = ijs;
+    p.args.oks = oks;
+    p.args.res_mask = n;
+    p.args.twp_mask = (int64_t)code;
+    p.args.xcd_remap = opt.xcd_remap;
+    p.rader_n = n;
+    p.label = label;
+    passes.push_back(p);
+  }
+
   // Mixed-radix pass of length n over the pencils of fields f
   // (mixed_kernel.h documents the argument fields).
   void add_mixed(int64_t n, const Field* f, int nf, int64_t ijs, int64_t oks,
@@ -430,6 +453,14 @@ void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
     b.add_mixed(n, f, 1, 1, B, lab);
     return;
   }
+  if (!is_pow2(n) && b.opt.rader && rader_length(n, b.opt.rader == 2)) {
+    // prime, n - 1 with factors <= 13 (rader.h): one rotate-on-write pass
+    Field f[1] = {{B, n, 1}};
+    std::snprintf(lab, sizeof lab, "pencil%d DFT%lld rader x%lld rot", axis, (long long)n,
+                  (long long)B);
+    b.add_rader(n, f, 1, 1, B, lab);
+    return;
+  }
   if (!is_pow2(n)) {
     // Bluestein (bluestein.h): the whole axis in one rotate-on-write pass
     Field f[1] = {{B, n, 1}};
@@ -475,6 +506,9 @@ void axis_pass(Builder& b, int64_t n, int lmode, int smode, const Field* f, int 
   } else if (mixed_radix_code(n)) {
     std::snprintf(lab, sizeof lab, "%s mixed", label);
     b.add_mixed(n, f, nf, ijs, oks, lab, lmode, smode);
+  } else if (b.opt.rader && rader_length(n, b.opt.rader == 2)) {
+    std::snprintf(lab, sizeof lab, "%s rader", label);
+    b.add_rader(n, f, nf, ijs, oks, lab);
   } else {
     std::snprintf(lab, sizeof lab, "%s via %lld", label, (long long)bluestein_length(n));
     b.add_bluestein(n, f, nf, ijs, oks, lab);
@@ -817,8 +851,9 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << ",\"plane_rows\":" << p.k->plane_rows << ",\"fused_axes\":" << p.k->fused_axes
        << ",\"bluestein\":" << p.k->bluestein << ",\"bl_n\":" << p.bl_n
        << ",\"mixed\":" << p.k->mixed << ",\"fixed_n\":" << p.k->fixed_n
+       << ",\"rader\":" << p.k->rader << ",\"rader_n\":" << p.rader_n
        << ",\"move_only\":" << p.k->move_only << ",\"radices\":[";
-    if (p.k->mixed) {  // the stage radices, first stage first
+    if (p.k->mixed || p.k->rader) {  // the stage radices (of n - 1 for Rader), first first
       bool first = true;
       for (uint64_t c = (uint64_t)p.args.twp_mask; c; c >>= 8, first = false)
         os << (first ? "" : ",") << (c & 255);

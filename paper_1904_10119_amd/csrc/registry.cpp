@@ -20,6 +20,8 @@ void register_kernels_fused(std::vector<KernelInfo>& v);
 void register_kernels_bluestein(std::vector<KernelInfo>& v);
 void register_kernels_mixed(std::vector<KernelInfo>& v);
 void register_kernels_mixed_fixed(std::vector<KernelInfo>& v);
+void register_kernels_rader(std::vector<KernelInfo>& v);
+void register_kernels_rader_fixed(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -38,6 +40,8 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_bluestein(v);
     register_kernels_mixed(v);
     register_kernels_mixed_fixed(v);
+    register_kernels_rader(v);
+    register_kernels_rader_fixed(v);
     return v;
   }();
   return table;
@@ -169,6 +173,38 @@ bool radix_code_valid(uint64_t code) {
 }
 
 bool length_supported(int64_t n) { return n >= 1 && n <= 4096; }
+
+namespace {
+bool is_prime(int64_t n) {
+  if (n < 2) return false;
+  for (int64_t f = 2; f * f <= n; ++f)
+    if (n % f == 0) return false;
+  return true;
+}
+}  // namespace
+
+const KernelInfo* find_rader_kernel(int64_t n, int tile) {
+  const uint64_t code = mixed_radix_code(n - 1);
+  if (!code) return nullptr;
+  if (tile <= 0)  // a kernel compiled for this prime and code, if any
+    for (const KernelInfo& k : kernel_registry())
+      if (k.rader && k.fixed_n == n && k.fixed_code == code) return &k;
+  const int variant = mixed_variant(code);
+  const KernelInfo* best = nullptr;
+  for (const KernelInfo& k : kernel_registry())
+    if (k.rader == variant && k.fixed_n == 0 && k.n >= n + 1 &&
+        mixed_kernel_runs(variant, k.n, code)) {
+      if (tile > 0 && k.tile == tile) return &k;
+      if (!best || k.n < best->n) best = &k;
+    }
+  return best;
+}
+
+bool rader_length(int64_t n, bool any_kernel) {
+  if (n < 3 || !is_prime(n) || mixed_radix_code(n - 1) == 0) return false;
+  const KernelInfo* k = find_rader_kernel(n, 0);
+  return k && (any_kernel || k->fixed_n == n);
+}
 
 const KernelInfo* find_bluestein_kernel(int m, int tile) {
   const KernelInfo* first = nullptr;

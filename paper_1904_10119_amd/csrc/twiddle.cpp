@@ -124,6 +124,70 @@ void make_leaf_table(int precision, unsigned short* out) {
         }
 }
 
+namespace {
+int64_t mul_mod(int64_t a, int64_t b, int64_t n) { return (a * b) % n; }
+
+// The smallest generator of the multiplicative group mod the prime n.
+int64_t rader_generator(int64_t n) {
+  std::vector<int64_t> f;  // prime factors of n - 1
+  int64_t m = n - 1;
+  for (int64_t d = 2; d * d <= m; ++d)
+    if (m % d == 0) {
+      f.push_back(d);
+      while (m % d == 0) m /= d;
+    }
+  if (m > 1) f.push_back(m);
+  for (int64_t g = 2; g < n; ++g) {
+    bool gen = true;
+    for (int64_t p : f) {
+      int64_t e = (n - 1) / p, r = 1, base = g;
+      while (e) {  // g^((n - 1) / p) mod n
+        if (e & 1) r = mul_mod(r, base, n);
+        base = mul_mod(base, base, n);
+        e >>= 1;
+      }
+      if (r == 1) {
+        gen = false;
+        break;
+      }
+    }
+    if (gen) return g;
+  }
+  return 0;
+}
+}  // namespace
+
+int64_t rader_table_size(int64_t n) { return (n - 1) + (n - 1 + 1) / 2; }
+
+void make_rader_tables(int64_t n, float2* out) {
+  const int64_t L = n - 1, g = rader_generator(n);
+  std::vector<int64_t> pw(L);
+  pw[0] = 1;
+  for (int64_t j = 1; j < L; ++j) pw[j] = mul_mod(pw[j - 1], g, n);
+  // b[m] = w_n^(g^-m) = w_n^(g^((L - m) mod L)), B = DFT_L(b) in FP64
+  std::vector<double> br(L), bi(L), cr(L), ci(L);
+  for (int64_t m = 0; m < L; ++m) {
+    double c, s;
+    root_fp64(pw[(L - m) % L], n, c, s);
+    br[m] = c;
+    bi[m] = -s;
+  }
+  for (int64_t k = 0; k < L; ++k) root_fp64(k, L, cr[k], ci[k]);  // w_L^k = cr - i ci
+  for (int64_t k = 0; k < L; ++k) {
+    double sr = 0.0, si = 0.0;
+    for (int64_t m = 0; m < L; ++m) {
+      const int64_t e = (m * k) % L;
+      const double wr = cr[e], wi = -ci[e];
+      sr += br[m] * wr - bi[m] * wi;
+      si += br[m] * wi + bi[m] * wr;
+    }
+    out[k] = make_float2((float)(sr / (double)L), (float)(si / (double)L));
+  }
+  int32_t* perm = reinterpret_cast<int32_t*>(out + L);
+  for (int64_t j = 0; j < L; ++j) perm[j] = (int32_t)pw[j];
+  if (L % 2) perm[L] = 0;  // the last slot's second half
+}
+
 int64_t bluestein_length(int64_t n) {
   int64_t m = 1;
   while (m < 2 * n - 1) m <<= 1;

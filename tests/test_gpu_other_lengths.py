@@ -297,3 +297,43 @@ def test_autotune_other_lengths_radix_candidates(tmp_path, monkeypatch):
     x = inputs.uniform_c64(shape, 51)
     y = gpu_fftn(x, schedule="auto")
     assert oracle.rel_l2(y, direct_ref(x, -1)) <= tol_bl(shape) + 1e-6 / 18
+
+
+RADER_PRIMES = [17, 19, 23, 29, 31, 37, 41, 43, 53, 61, 73, 97, 101, 109, 151, 181, 211, 241,
+                271, 337, 401, 421, 449, 577, 601, 641, 673, 757, 769, 883, 1009, 1051, 1201,
+                1297, 1459, 1601, 2003, 2017, 2161, 2593, 3001, 3137, 4001]
+
+
+RADER_COMPILED = {197, 257, 281, 401, 577, 641, 769, 1009, 1201, 1601, 2017, 2593, 3001,
+                  4001}
+
+
+def run_plan(x, inverse, **kw):
+    xt = torch.from_numpy(x).cuda()
+    p = dft3d.Plan(x.shape, "pencil", **kw)
+    y = torch.empty_like(xt)
+    p.execute(xt, y, inverse=inverse)
+    torch.cuda.synchronize()
+    p.close()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", sorted(set(RADER_PRIMES) | RADER_COMPILED))
+def test_rader_lengths(n):
+    """Primes n with n - 1 free of prime factors above 13 through the Rader
+    pass (two mixed-radix FFTs of length n - 1 in LDS): the compiled-length
+    kernel (the default for its primes) and the generic one
+    (DFT3D_OPT_RADER = 2), forward and inverse against the oracle's direct
+    sums, along a contiguous and a strided axis, and the Bluestein pass
+    (DFT3D_OPT_RADER = 0) of the same plan."""
+    for shape in ((3, 2, n), (n, 2, 3)):
+        d = dft3d.describe(shape, "pencil")
+        assert any(p["rader"] and p["rader_n"] == n for p in d["passes"]) == (n in RADER_COMPILED)
+        say("case rader", shape)
+        x = inputs.uniform_c64(shape, 60)
+        for sign, inv in ((-1, False), (1, True)):
+            ref = direct_ref(x, sign)
+            for kw in ({}, {"rader": 2}, {"rader": 0}):
+                err = oracle.rel_l2(run_plan(x, inv, **kw), ref)
+                say("  sign", sign, kw, "rel_l2", err)
+                assert err <= tol_bl(shape), (shape, sign, kw, err)

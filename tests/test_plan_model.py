@@ -43,7 +43,7 @@ def pass_points(p):
     """Points one work item (pencil, or plane for fused plane passes) covers."""
     if p.get("bluestein"):
         return p["bl_n"]
-    if p.get("mixed"):
+    if p.get("mixed") or p.get("rader"):
         return p["args"]["res_mask"]
     return p["n"] * max(1, p.get("plane_rows", 0))
 
@@ -352,7 +352,7 @@ def test_bluestein_pass_lists(shape):
     the pass list computes the DFT, forward and inverse."""
     d = dft3d.describe(shape, "auto")
     assert d["schedule"] == "pencil"
-    assert any(p["bluestein"] or p["mixed"] for p in d["passes"])
+    assert any(p["bluestein"] or p["mixed"] or p["rader"] for p in d["passes"])
     g = np.random.default_rng(sum(shape))
     x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
     for sign in (-1, 1):
@@ -376,7 +376,9 @@ def test_bluestein_axis_passes(shape):
         n = pass_points(p)
         assert p["args"]["B"] * n == N
         if n & (n - 1):
-            assert bool(p["mixed"]) == is_smooth13(n) and bool(p["bluestein"]) != is_smooth13(n)
+            assert bool(p["mixed"]) == is_smooth13(n)
+            assert bool(p["rader"]) == is_rader(n)
+            assert bool(p["bluestein"]) == (not is_smooth13(n) and not is_rader(n))
         if p["mixed"]:
             assert int(np.prod(p["radices"])) == n and p["n"] >= n
             # composite radices only in the kernel without 11 and 13, below 2048
@@ -422,7 +424,7 @@ def test_other_lengths_on_slab_and_volumetric(shape, schedule):
     N = shape[0] * shape[1] * shape[2]
     for p in d["passes"]:
         if p["args"]["s0"] < 0:
-            assert p["mixed"] or p["bluestein"], p["label"]
+            assert p["mixed"] or p["bluestein"] or p["rader"], p["label"]
     if schedule == "volumetric":
         # axes that are powers of two with power-of-two axes after them are
         # still split four-step style
@@ -442,10 +444,46 @@ def test_other_lengths_on_slab_and_volumetric(shape, schedule):
             assert oracle.rel_l2(got, ref) < 1e-12, (shape, schedule, sign)
 
 
+def is_prime(n):
+    return n >= 2 and all(n % f for f in range(2, int(n ** 0.5) + 1))
+
+
+RADER_COMPILED = {197, 257, 281, 401, 577, 641, 769, 1009, 1201, 1601, 2017, 2593, 3001,
+                  4001}
+
+
+def is_rader(n, any_kernel=False):
+    """A prime above 13 (smaller ones run mixed radix) with n - 1 free of
+    prime factors above 13, within the Rader kernels' tile lengths (n + 1 <=
+    4096); by default only the primes a Rader kernel is compiled for."""
+    ok = is_prime(n) and n > 13 and is_smooth13(n - 1) and n + 1 <= 4096
+    return ok and (any_kernel or n in RADER_COMPILED)
+
+
+def test_rader_option_levels():
+    """DFT3D_OPT_RADER: 1 (default) Rader for the compiled primes only, 2 for
+    every eligible prime, 0 Bluestein; other values rejected."""
+    for n in range(14, 4097):
+        if not is_prime(n):
+            continue
+        p1 = dft3d.describe((1, 1, n), "pencil")["passes"][0]
+        p2 = dft3d.describe((1, 1, n), "pencil", rader=2)["passes"][0]
+        p0 = dft3d.describe((1, 1, n), "pencil", rader=0)["passes"][0]
+        assert bool(p1["rader"]) == is_rader(n), n
+        assert bool(p2["rader"]) == is_rader(n, True), n
+        assert not p0["rader"] and p0["bluestein"], n
+        if p1["rader"]:
+            assert p1["fixed_n"] == n and p1["radices"] == p2["radices"]
+    for bad in (-1, 3):
+        with pytest.raises(dft3d.Dft3dError):
+            dft3d.describe((1, 1, 17), "pencil", rader=bad)
+
+
 def test_every_length_up_to_4096():
     """Each length 1..4096 is planned as a power-of-two pass, a mixed-radix
-    pass (prime factors <= 13) or a Bluestein pass (other lengths, with a
-    convolution length up to 8192); 4097 is rejected."""
+    pass (prime factors <= 13), a Rader pass (primes with n - 1 of prime
+    factors <= 13) or a Bluestein pass (other lengths, with a convolution
+    length up to 8192); 4097 is rejected."""
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((4097, 1, 1), "pencil")
     for n in range(1, 4097):
@@ -456,7 +494,10 @@ def test_every_length_up_to_4096():
         if n == 1:
             continue
         assert bool(p["mixed"]) == (not pow2 and is_smooth13(n)), n
-        assert bool(p["bluestein"]) == (not pow2 and not is_smooth13(n)), n
+        assert bool(p["rader"]) == (not pow2 and is_rader(n)), n
+        assert bool(p["bluestein"]) == (not pow2 and not is_smooth13(n) and not is_rader(n)), n
+        if p["rader"]:
+            assert int(np.prod(p["radices"])) == n - 1 and p["n"] >= n + 1, n
         if p["mixed"]:
             assert int(np.prod(p["radices"])) == n and p["n"] >= n
             # composite radices only in the kernel without 11 and 13, below 2048
@@ -497,6 +538,46 @@ def test_mixed_stage_formulas(n):
     x = np.random.default_rng(n).standard_normal(n) + 1j * np.random.default_rng(n + 1).standard_normal(n)
     got = stockham_mixed(x, p["radices"])
     assert oracle.rel_l2(got, oracle.dft3d(x.reshape(n, 1, 1), -1, "direct").reshape(-1)) < 1e-12
+
+
+def rader_steps(x):
+    """Rader's identity written out step by step in numpy (the library's
+    tables are not used): generator g by trial, a[j] = x[g^j], b[m] =
+    w_n^(g^-m), cyclic convolution c = IFFT(FFT(a) FFT(b)), y[0] = sum x,
+    y[g^-p] = x[0] + c[p]."""
+    n = x.size
+    L = n - 1
+    g = next(c for c in range(2, n) if len({pow(c, j, n) for j in range(L)}) == L)
+    pw = [pow(g, j, n) for j in range(L)]
+    a = x[pw]
+    b = np.exp(-2j * np.pi * np.array([pw[(-m) % L] for m in range(L)]) / n)
+    c = np.fft.ifft(np.fft.fft(a) * np.fft.fft(b))
+    y = np.empty(n, complex)
+    y[0] = x.sum()
+    for p_ in range(L):
+        y[pw[(-p_) % L]] = x[0] + c[p_]
+    return y
+
+
+@pytest.mark.parametrize("n", [3, 5, 7, 17, 19, 23, 29, 31, 37, 41, 43, 53, 61, 97, 1009, 2003])
+def test_rader_identity(n):
+    """The steps of the Rader pass give the DFT (direct sums), and the
+    permutation of the output is that of the input (y[g^j] = x[0] +
+    FFT_L(FFT_L(a) B / L)[j], as the kernel stores it)."""
+    g_ = np.random.default_rng(n)
+    x = g_.standard_normal(n) + 1j * g_.standard_normal(n)
+    ref = oracle.dft3d(x.reshape(n, 1, 1), -1, "direct").reshape(-1)
+    assert oracle.rel_l2(rader_steps(x), ref) < 1e-12
+    L = n - 1
+    g = next(c for c in range(2, n) if len({pow(c, j, n) for j in range(L)}) == L)
+    pw = np.array([pow(g, j, n) for j in range(L)])
+    B = np.fft.fft(np.exp(-2j * np.pi * pw[(-np.arange(L)) % L] / n)) / L
+    A = np.fft.fft(x[pw])
+    D = np.fft.fft(A * B)
+    y = np.empty(n, complex)
+    y[pw] = x[0] + D
+    y[0] = x[0] + A[0]
+    assert oracle.rel_l2(y, ref) < 1e-12
 
 
 RADIX_CASES = [((4, 2, 1000), [10, 10, 10]), ((4, 2, 1000), [8, 5, 5, 5]),
