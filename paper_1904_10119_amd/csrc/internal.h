@@ -124,8 +124,10 @@ const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent, int 
 // with leaves of length leaf (16 or 32; 0: the default for the length).
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
                                    int persistent, int leaf);
-// The default MFMA leaf length of a pass length and split precision.
+// The default MFMA leaf length of a pass length and split precision, and
+// whether the persistent form is the default there.
 int default_mfma_leaf(int n, int precision);
+bool default_mfma_persistent(int n, int precision);
 
 // Roots w_n^m = exp(-2 pi i m / n), m < n, computed in FP64 with exact
 // octant reduction and rounded once to FP32 (eq. (4) entries).

@@ -587,9 +587,15 @@ __device__ __forceinline__ void mfma_finish(const float2* res, float2* dst, cons
   }
 }
 
+// Waves per SIMD the one-tile form asks the compiler for: four (at most
+// 128 VGPRs) where two workgroups fit in a CU's LDS, else two.
+template <int N> constexpr int mfma_one_tile_waves() {
+  return 2 * (mfma_buf_elems<N>() + N) * 8 <= 160 * 1024 ? 4 : 2;
+}
+
 // One tile per workgroup.
 template <int N, int LM, int SM, int PREC, int L>
-__global__ void __launch_bounds__(mfma_threads<N>())
+__global__ void __launch_bounds__(mfma_threads<N>(), mfma_one_tile_waves<N>())
 fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
               const unsigned short* __restrict__ leaf, const PassArgs a) {
   __shared__ float2 buf[mfma_buf_elems<N>()];

@@ -189,11 +189,15 @@ struct Builder {
                       nt_side);
     if (!k && opt.precision != DFT3D_PREC_FP32 && !tw) {
       // split-precision leaves on the matrix cores where a kernel exists;
-      // the persistent form under the same rule as the FP32 kernels (in
-      // automatic mode only for arrays that stream through HBM: measured at
-      // 256^3 bf16x6, 0.165 ms one tile per workgroup vs 0.185 persistent)
-      const bool pers = opt.persistent &&
-                        (opt.nontemporal != 2 || total_points * 8 >= kStreamBytes);
+      // the one-tile form (two workgroups per CU, four waves per SIMD)
+      // unless the persistent form measured faster for this length and
+      // precision on arrays that stream through HBM (registry.cpp); with
+      // streaming forced on (nontemporal = 1) the persistent form wherever
+      // the persistent option is on
+      const bool pers =
+          opt.persistent &&
+          (opt.nontemporal == 1 || (opt.nontemporal == 2 && total_points * 8 >= kStreamBytes &&
+                                    default_mfma_persistent(n, opt.precision)));
       k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, opt.mfma_leaf);
       // a length without leaves of the asked length keeps its default leaves
       if (!k && opt.mfma_leaf) k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, 0);
