@@ -89,6 +89,12 @@ int rebuild(dft3d_plan_s* p) {
   std::vector<const Pass*> all;
   for (const Pass& ps : passes) all.push_back(&ps);
   for (const Pass& ps : ipasses) all.push_back(&ps);
+  // every table-carrying pass has its length (a kernel picked for the wrong
+  // kind of pass would size its tables from zero)
+  for (const Pass* pp : all)
+    if ((pp->k->rader && pp->rader_n < 3) || (pp->k->mixed && pp->args.res_mask < 2) ||
+        (pp->k->bluestein && pp->bl_n < 1))
+      return DFT3D_ERR_UNSUPPORTED_SIZE;
   for (const Pass* pp : all) {
     const Pass& ps = *pp;
     if (ps.k->rader) {  // stage twiddles of n - 1, and the Rader tables of n

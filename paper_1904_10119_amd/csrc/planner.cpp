@@ -97,7 +97,8 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
   for (const KernelInfo& k : kernel_registry())
     if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw &&
         k.persistent == 0 && k.nontemporal == nt && k.precision == 0 && k.plane_rows == 0 &&
-        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.move_only == 0)
+        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.rader == 0 &&
+        k.move_only == 0)
       return &k;
   return nullptr;
 }

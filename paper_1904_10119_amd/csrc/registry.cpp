@@ -53,14 +53,15 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
     if (k.n == n && k.tile == tile && k.lmode == lmode && k.smode == smode &&
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
         k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0 &&
-        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.move_only == 0)
+        k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.rader == 0 &&
+        k.move_only == 0)
       return &k;
   return nullptr;
 }
 
 const KernelInfo* find_move_only_kernel(const KernelInfo* k, int mode) {
   if (!k || k->precision || k->plane_rows || k->fused_axes || k->bluestein || k->mixed ||
-      k->move_only)
+      k->rader || k->move_only)
     return nullptr;
   for (const KernelInfo& c : kernel_registry()) {
     if (c.move_only != mode) continue;

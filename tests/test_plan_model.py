@@ -460,6 +460,27 @@ def is_rader(n, any_kernel=False):
     return ok and (any_kernel or n in RADER_COMPILED)
 
 
+@pytest.mark.parametrize("tile", [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
+def test_tile_option_keeps_pass_kinds(tile):
+    """A tile option only picks among kernels of the pass's own kind: on
+    power-of-two shapes no pass becomes a mixed-radix, Rader or Bluestein
+    pass (a Rader kernel of 256 pencils of up to 32 points once matched a
+    length-32 power-of-two pass by its tile alone), and on other shapes
+    those passes carry their lengths."""
+    for shape in [(64, 128, 32), (32, 32, 32), (4096, 2, 2), (2, 1024, 8), (16, 256, 512)]:
+        for sched in ("pencil", "slab", "volumetric"):
+            for p in dft3d.describe(shape, sched, tile=tile)["passes"]:
+                assert not (p["mixed"] or p["rader"] or p["bluestein"]), (shape, sched, tile, p["label"])
+    for shape in [(1009, 2, 3), (17, 19, 23), (1000, 4, 8)]:
+        for p in dft3d.describe(shape, "pencil", tile=tile)["passes"]:
+            if p["rader"]:
+                assert p["rader_n"] >= 3
+            if p["mixed"]:
+                assert p["args"]["res_mask"] >= 2
+            if p["bluestein"]:
+                assert p["bl_n"] >= 1
+
+
 def test_rader_option_levels():
     """DFT3D_OPT_RADER: 1 (default) Rader for the compiled primes only, 2 for
     every eligible prime, 0 Bluestein; other values rejected."""
