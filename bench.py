@@ -385,11 +385,13 @@ def extras(x1024_host, refs):
     prec = {}
     for pr, lf in (("fp32", 0), ("bf16x6", 16), ("bf16x9", 16), ("fp16x3", 16),
                    ("bf16x6", 32), ("bf16x9", 32), ("fp16x3", 32)):
-        key = pr if lf in (0, 16) else f"{pr} leaf32"
+        key = pr if lf == 0 else f"{pr} leaf{lf}"
         p = dft3d.Plan((1024,) * 3, "pencil", precision=pr, mfma_leaf=lf)
         f = timed(lambda: p.execute(x, y), 3)
         prec[key] = {"fwd_ms": round(f, 3), "fwd_gflops": round(fl / (f * 1e-3) / 1e9, 1)}
         if pr != "fp32":
+            prec[key]["default_leaf"] = lf == dft3d.describe(
+                (1024,) * 3, "pencil", precision=pr)["passes"][0]["mfma_leaf"]
             prec[key].update(check_1024(p, key, roundtrip=False))
         else:
             prec[key].update({k: v for k, v in sched["pencil"].items()
@@ -431,9 +433,10 @@ def extras(x1024_host, refs):
     x = torch.from_numpy(xh).cuda()
     y = torch.empty_like(x)
     prec = {}
-    for pr, lf in (("fp32", 0), ("bf16x1", 16), ("fp16x1", 16), ("bf16x6", 16),
-                   ("bf16x9", 16), ("fp16x3", 16), ("bf16x6", 32), ("fp16x3", 32)):
-        key = pr if lf in (0, 16) else f"{pr} leaf32"
+    for pr, lf in (("fp32", 0), ("bf16x1", 0), ("fp16x1", 0), ("bf16x6", 16),
+                   ("bf16x9", 16), ("fp16x3", 16), ("bf16x6", 32), ("bf16x9", 32),
+                   ("fp16x3", 32)):
+        key = pr if lf == 0 else f"{pr} leaf{lf}"
         p = dft3d.Plan(shape, "pencil", precision=pr, mfma_leaf=lf)
         f = timed(lambda: p.execute(x, y), 20)
         prec[key] = {"fwd_ms": round(f, 4),
@@ -508,7 +511,8 @@ def extras(x1024_host, refs):
     r = {}
     runs = [("auto untuned", dict(schedule="auto")), ("pencil", dict(schedule="pencil")),
             ("auto bf16x6", dict(schedule="auto", precision="bf16x6")),
-            ("auto bf16x6 leaf32", dict(schedule="auto", precision="bf16x6", mfma_leaf=32))]
+            ("auto bf16x6 leaf16", dict(schedule="auto", precision="bf16x6", mfma_leaf=16)),
+            ("auto fp16x3", dict(schedule="auto", precision="fp16x3"))]
     for name, kw in runs:
         p = dft3d.Plan(shape, **kw)
         f = timed(lambda: p.execute(x, y), 3)
