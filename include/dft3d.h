@@ -185,6 +185,15 @@ enum dft3d_option {
                                 kernel for the others, measured slower than
                                 Bluestein), 0 = Bluestein.  Other values:
                                 INVALID_ARG */
+  DFT3D_OPT_HALVES = 16,     /* FP32 rotate-on-write passes of length 2048
+                                (the pencil schedule's): 1 (default) = as
+                                two half-length transforms after a radix-2
+                                split (the four-step factorisation of eq. (3)
+                                with radix 2 first), 16 pencils per
+                                workgroup, so every stored row segment is
+                                128 bytes; 0 = the whole length in 8-pencil
+                                tiles.  Taken when DFT3D_OPT_TILE is 0 or 16.
+                                Other values: INVALID_ARG */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

@@ -60,7 +60,8 @@ struct Level {
 // plan by plan).
 bool batchable(const std::vector<Pass>& passes, bool persistent) {
   for (const Pass& ps : passes) {
-    if (ps.k->bluestein || ps.k->mixed || ps.k->rader || ps.k->precision) return false;
+    if (ps.k->bluestein || ps.k->mixed || ps.k->rader || ps.k->halves || ps.k->precision)
+      return false;
     if (ps.k->plane_rows) {
       if (!batch_runs_plane(ps.k->plane_rows, ps.k->n, persistent)) return false;
       continue;

@@ -64,6 +64,8 @@ struct KernelInfo {
   int r0 = 0, r1 = 0, r2 = 0;   // FP32 pass kernels: the radix of each stage (1: none)
   int mfma_leaf = 0;  // split-precision MFMA passes: the leaf length (16 or 32)
   int rader = 0;      // > 0: Rader pass for prime lengths up to n - 1 (variant as mixed)
+  int halves = 0;     // 1: rotate-on-write pass of length n as two half-length
+                      // transforms after a radix-2 split (halves_kernel.h)
 };
 
 // All compiled pass kernels.
@@ -73,6 +75,9 @@ const std::vector<KernelInfo>& kernel_registry();
 const KernelInfo* find_move_only_kernel(const KernelInfo* k, int mode);
 const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_twiddle,
                               int persistent, int nontemporal);
+// The two-halves rotate-on-write pass of length n (halves_kernel.h) with the
+// given form, or null if none is compiled.
+const KernelInfo* find_halves_kernel(int n, int persistent, int nontemporal, int move_only);
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
 // Whether a mixed-radix kernel (variant 1: no 11 or 13 stages, composites
@@ -185,6 +190,8 @@ struct Options {
                         // of their product's length, run by the mixed-radix kernel; 0: default
   int rader = 1;        // prime lengths with smooth n - 1: 0 Bluestein, 1 Rader where a
                         // kernel is compiled for n, 2 Rader also with the generic kernel
+  int halves = 1;       // rotate-on-write passes of length 2048 as two halves in
+                        // 16-pencil tiles (1) or whole in 8-pencil tiles (0)
 };
 
 // Builds the pass list of a schedule.  Returns a dft3d status; on success

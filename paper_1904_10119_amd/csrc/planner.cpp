@@ -84,6 +84,13 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
     if (opt.persistent) order[nchoice++] = {1, opt.nontemporal};
     order[nchoice++] = {0, opt.nontemporal};
   }
+  // length 2048 rotated on write: the two-halves kernel (16-pencil tiles,
+  // one tile per workgroup; ordinary accesses unless streaming is forced,
+  // measured faster at 2048 x 1024 x 512)
+  if (opt.halves && lmode == MODE_ROW && smode == MODE_COL && tw == 0 &&
+      (opt.tile <= 0 || opt.tile == 16))
+    if (const KernelInfo* k = find_halves_kernel(n, 0, opt.nontemporal == 1 ? 1 : 0, 0))
+      return k;
   for (int c = 0; c < nchoice; ++c) {
     const int pers = order[c].pers, nt = order[c].nt;
     if (opt.tile > 0) {
@@ -98,7 +105,7 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
     if (k.n == n && k.lmode == lmode && k.smode == smode && k.post_twiddle == tw &&
         k.persistent == 0 && k.nontemporal == nt && k.precision == 0 && k.plane_rows == 0 &&
         k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.rader == 0 &&
-        k.move_only == 0)
+        k.halves == 0 && k.move_only == 0)
       return &k;
   return nullptr;
 }
@@ -857,6 +864,7 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << ",\"bluestein\":" << p.k->bluestein << ",\"bl_n\":" << p.bl_n
        << ",\"mixed\":" << p.k->mixed << ",\"fixed_n\":" << p.k->fixed_n
        << ",\"rader\":" << p.k->rader << ",\"rader_n\":" << p.rader_n
+       << ",\"halves\":" << p.k->halves
        << ",\"move_only\":" << p.k->move_only << ",\"radices\":[";
     if (p.k->mixed || p.k->rader) {  // the stage radices (of n - 1 for Rader), first first
       bool first = true;

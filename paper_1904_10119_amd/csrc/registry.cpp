@@ -22,6 +22,7 @@ void register_kernels_mixed(std::vector<KernelInfo>& v);
 void register_kernels_mixed_fixed(std::vector<KernelInfo>& v);
 void register_kernels_rader(std::vector<KernelInfo>& v);
 void register_kernels_rader_fixed(std::vector<KernelInfo>& v);
+void register_kernels_halves(std::vector<KernelInfo>& v);
 
 const std::vector<KernelInfo>& kernel_registry() {
   static const std::vector<KernelInfo> table = [] {
@@ -42,6 +43,7 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_mixed_fixed(v);
     register_kernels_rader(v);
     register_kernels_rader_fixed(v);
+    register_kernels_halves(v);
     return v;
   }();
   return table;
@@ -54,7 +56,15 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
         k.post_twiddle == post_twiddle && k.persistent == persistent &&
         k.nontemporal == nontemporal && k.precision == 0 && k.plane_rows == 0 &&
         k.fused_axes == 0 && k.bluestein == 0 && k.mixed == 0 && k.rader == 0 &&
-        k.move_only == 0)
+        k.halves == 0 && k.move_only == 0)
+      return &k;
+  return nullptr;
+}
+
+const KernelInfo* find_halves_kernel(int n, int persistent, int nontemporal, int move_only) {
+  for (const KernelInfo& k : kernel_registry())
+    if (k.halves && k.n == n && k.persistent == persistent && k.nontemporal == nontemporal &&
+        k.move_only == move_only)
       return &k;
   return nullptr;
 }
@@ -63,8 +73,9 @@ const KernelInfo* find_move_only_kernel(const KernelInfo* k, int mode) {
   if (!k || k->precision || k->plane_rows || k->fused_axes || k->bluestein || k->mixed ||
       k->rader || k->move_only)
     return nullptr;
+  if (k->halves && mode == 1) return find_halves_kernel(k->n, 0, k->nontemporal, 1);
   for (const KernelInfo& c : kernel_registry()) {
-    if (c.move_only != mode) continue;
+    if (c.move_only != mode || c.halves) continue;
     if (mode == 2 && c.n == k->n) return &c;
     if (mode == 1 && c.n == k->n && c.tile == k->tile && c.lmode == k->lmode &&
         c.smode == k->smode && c.post_twiddle == k->post_twiddle &&

@@ -500,6 +500,34 @@ def test_rader_option_levels():
             dft3d.describe((1, 1, 17), "pencil", rader=bad)
 
 
+def test_halves_option():
+    """DFT3D_OPT_HALVES: the pencil schedule's rotate-on-write passes of
+    length 2048 run as two halves in 16-pencil tiles by default (whatever
+    the persistent option, as there is one form), as the whole length in
+    8-pencil tiles with 0 or with tile 8; other lengths, load and store
+    orders, split precision and other values are untouched or rejected."""
+    for shape in ((2048, 1024, 512), (2048, 3, 5), (4, 2048, 2), (2, 2, 2048)):
+        for kw in ({}, {"persistent": 0}, {"nontemporal": 1}, {"tile": 16}):
+            d = dft3d.describe(shape, "pencil", **kw)
+            for p in d["passes"]:
+                assert p["halves"] == (p["n"] == 2048), (shape, kw, p)
+                if p["halves"]:
+                    assert (p["tile"], p["threads"], p["persistent"]) == (16, 512, 0)
+                    assert p["load"] == "row" and p["store"] == "col" and not p["post_twiddle"]
+                    assert p["nontemporal"] == kw.get("nontemporal", 0)
+        for kw in ({"halves": 0}, {"tile": 8}, {"precision": "bf16x6"}):
+            if "precision" in kw and 3 in shape:
+                continue  # split precision is for powers of two
+            d = dft3d.describe(shape, "pencil", **kw)
+            assert not any(p["halves"] for p in d["passes"]), (shape, kw)
+    # slab and volumetric keep their in-layout passes
+    for sch in ("slab", "volumetric"):
+        assert not any(p["halves"] for p in dft3d.describe((2048, 4, 4), sch)["passes"])
+    for bad in (-1, 2):
+        with pytest.raises(dft3d.Dft3dError):
+            dft3d.describe((2048, 2, 2), "pencil", halves=bad)
+
+
 def test_every_length_up_to_4096():
     """Each length 1..4096 is planned as a power-of-two pass, a mixed-radix
     pass (prime factors <= 13), a Rader pass (primes with n - 1 of prime
@@ -763,6 +791,32 @@ def stockham_identity_perm(n, radices):
     return src
 
 
+def halves_identity_perm(n, radices):
+    """The two-halves pass of length n (radix 2, then the Stockham stages of
+    radices[1:] on each half) with every butterfly and twiddle removed: half
+    h of the input goes through the half-length maps to the outputs 2k + h."""
+    assert radices[0] == 2
+    half = stockham_identity_perm(n // 2, radices[1:])
+    perm = np.empty(n, dtype=np.int64)
+    for h in range(2):
+        perm[h::2] = h * (n // 2) + half
+    return perm
+
+
+def halves_dft(x, radices):
+    """The two-halves pass of length n with its arithmetic: the radix-2 split
+    a = x[:n/2] + x[n/2:], b = (x[:n/2] - x[n/2:]) w_n^j, then the Stockham
+    stages of radices[1:] on a (the even outputs) and on b (the odd ones)."""
+    n = x.size
+    assert radices[0] == 2
+    lo, hi = x[:n // 2], x[n // 2:]
+    w = np.exp(-2j * np.pi * np.arange(n // 2) / n)
+    y = np.empty(n, dtype=complex)
+    y[0::2] = stockham_mixed(lo + hi, radices[1:])
+    y[1::2] = stockham_mixed((lo - hi) * w, radices[1:])
+    return y
+
+
 def run_move_model(x, d, sign=-1):
     """Run a move-only (1) or copy (2) pass list on x, as the kernels move
     data: per pencil the identity-butterfly permutation, or a flat copy."""
@@ -785,7 +839,10 @@ def run_move_model(x, d, sign=-1):
         v = bufs[p["src"]][ia + p["in_off"]]
         if sign == 1 and p["src"] == "in":
             v = np.conj(v)
-        y = v[:, stockham_identity_perm(p["n"], p["radices"])]
+        if p["halves"]:
+            y = v[:, halves_identity_perm(p["n"], p["radices"])]
+        else:
+            y = v[:, stockham_identity_perm(p["n"], p["radices"])]
         if sign == 1 and i == len(passes) - 1:
             y = np.conj(y)
         bufs[p["dst"]][oa + p["out_off"]] = y
@@ -802,13 +859,16 @@ def test_power_of_two_stage_radices_compute_the_dft():
         for shape in ((1, 1, n), (1, n, 2), (n, 2, 2)):
             for sch in ("pencil", "slab"):
                 for p in dft3d.describe(shape, sch, fused_plane=0)["passes"]:
-                    key = (p["n"], tuple(p["radices"]))
+                    key = (p["n"], tuple(p["radices"]), p["halves"])
                     if p["n"] < 2 or key in seen:
                         continue
                     seen.add(key)
                     assert int(np.prod(p["radices"])) == p["n"], p
                     x = np.random.default_rng(p["n"]).standard_normal(p["n"]) * (1 + 1j)
-                    got = stockham_mixed(x, p["radices"])
+                    if p["halves"]:
+                        got = halves_dft(x, p["radices"])
+                    else:
+                        got = stockham_mixed(x, p["radices"])
                     assert oracle.rel_l2(got, np.fft.fft(x)) < 1e-12, key
     assert len(seen) >= 12
 
