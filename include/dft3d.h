@@ -185,15 +185,19 @@ enum dft3d_option {
                                 kernel for the others, measured slower than
                                 Bluestein), 0 = Bluestein.  Other values:
                                 INVALID_ARG */
-  DFT3D_OPT_HALVES = 16,     /* FP32 rotate-on-write passes of length 2048
-                                (the pencil schedule's): 1 (default) = as
-                                two half-length transforms after a radix-2
-                                split (the four-step factorisation of eq. (3)
-                                with radix 2 first), 16 pencils per
-                                workgroup, so every stored row segment is
-                                128 bytes; 0 = the whole length in 8-pencil
-                                tiles.  Taken when DFT3D_OPT_TILE is 0 or 16.
-                                Other values: INVALID_ARG */
+  DFT3D_OPT_HALVES = 16,     /* FP32 passes as two half-length transforms
+                                after a radix-2 split (the four-step
+                                factorisation of eq. (3) with radix 2
+                                first), in tiles of twice the pencils, so
+                                that the strided row segments are longer:
+                                the pencil schedule's rotate-on-write passes
+                                of length 2048 (16 pencils, 128-byte
+                                segments) and the slab schedule's strided
+                                passes of lengths 1024 (32 pencils, 256
+                                bytes) and 2048 (16).  1 (default) = on,
+                                0 = the whole-length kernels.  Taken when
+                                DFT3D_OPT_TILE is 0 or the halves kernel's
+                                tile.  Other values: INVALID_ARG */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

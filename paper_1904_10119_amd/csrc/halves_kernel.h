@@ -1,30 +1,32 @@
-// The rotate-on-write pass of length 2048 as two half-length transforms, so
-// that a tile of 16 pencils fits in LDS.
+// A pass of length N as two half-length transforms, so that a tile of twice
+// as many pencils fits in LDS: the rotate-on-write pass of length 2048 in
+// 16-pencil tiles and the strided (column) pass of length 1024 in 32-pencil
+// tiles.
 //
 // Splitting the index in halves (decimation in frequency, the four-step
-// factorisation of eq. (3) with the radix 2 taken first):
-//   a[n] = x[n] + x[n + 1024],   b[n] = (x[n] - x[n + 1024]) w_2048^n,
-//   y[2k] = DFT_1024(a)[k],      y[2k + 1] = DFT_1024(b)[k].
-// Each thread loads the points n and n + 1024 of its pencil, so the radix-2
+// factorisation of eq. (3) with the radix 2 taken first), with M = N / 2:
+//   a[n] = x[n] + x[n + M],   b[n] = (x[n] - x[n + M]) w_N^n,
+//   y[2k] = DFT_M(a)[k],      y[2k + 1] = DFT_M(b)[k].
+// Each thread loads the points n and n + M of its pencil, so the radix-2
 // step runs in registers; the two halves then go one after the other
-// through the 1024-point stages of the pass kernel (radix 32, LDS exchange,
-// radix 32) in the same 16-pencil LDS tile, and each half stores its output
-// rows (the even ones, then the odd ones).  A 16-pencil tile of the whole
-// length would need 256 KB of LDS, and with 8 pencils the rotated store
-// writes 64-byte row segments; this way every row segment is 16 pencils,
-// 128 bytes.
+// through the two M-point stages of the pass kernel (radix R0, LDS
+// exchange, radix R1) in the same LDS tile, and each half stores its output
+// rows (the even ones, then the odd ones).  A tile of the whole length
+// would need twice the LDS: with the split, the stored (and, for strided
+// loads, the loaded) row segments are T pencils long, 128 bytes at
+// N = 2048 and 256 bytes at N = 1024, where the whole-length kernels take
+// 8 and 16 pencils.
 //
-// The 1024-point stage twiddles are the 2048-point roots at even indices:
-// the table in LDS holds w_2048^m (m < 2048) and the radix stages are
-// instantiated for length 2048, which doubles their root stride.
+// The M-point stage twiddles are the N-point roots at even indices: the
+// table in LDS holds w_N^m (m < N).
 #pragma once
 
 #include "pass_kernel.h"
 
 namespace dft3d {
 
-// Radix-2 step of the split: lo[e] = x[n] + x[n + 1024] and
-// hi[e] = x[n] - x[n + 1024] for n = p + P e; the twiddle w^n of the
+// Radix-2 step of the split: lo[e] = x[n] + x[n + M] and
+// hi[e] = x[n] - x[n + M] for n = p + P e; the twiddle w^n of the
 // differences is applied when their half starts (halves_half), so that its
 // table entries are not held in registers during the first half.
 template <int E, bool MV>
@@ -38,52 +40,66 @@ __device__ __forceinline__ void halves_split(float2 (&lo)[E], float2 (&hi)[E]) {
   }
 }
 
-// The second radix-32 stage of a half (after 32, thread p owns butterfly
-// t = p), its twiddles w_1024^{p r} = w_2048^{2 p r} formed as the products
-// w_2048^{16 p k} w_2048^{2 p j} (r = 8 k + j) of ten table entries: the 31
-// entries the stage would otherwise read stay out of the registers, which
-// the other half's 32 points share with it.
-template <int P, bool MV>
-__device__ __forceinline__ void halves_stage2(float2 (&v)[32], int p, const float2* roots) {
+// The second stage of a half (radix R after NS = M / R; thread p runs the
+// butterflies t = p + P u), its twiddles w_M^{t r} = w_N^{2 t r} formed as
+// the products w_N^{16 t k} w_N^{2 t j} (r = 8 k + j) of a few table
+// entries: the R - 1 entries a butterfly would otherwise read stay out of
+// the registers, which the other half's points share with it.
+template <int N, int E, int P, int NS, int R, bool MV>
+__device__ __forceinline__ void halves_stage2(float2 (&v)[E], int p, const float2* roots) {
   if constexpr (MV) return;
-  float2 lo[8], hi[4];
+  static_assert(R % 8 == 0 && NS * R == N / 2, "second stage of a half");
+  constexpr int U = E / R;
 #pragma unroll
-  for (int j = 1; j < 8; ++j) lo[j] = roots[2 * p * j];
+  for (int u = 0; u < U; ++u) {
+    const int t = (p + P * u) & (NS - 1);
+    float2 lo[8], hi[R / 8];
 #pragma unroll
-  for (int k = 1; k < 4; ++k) hi[k] = roots[16 * p * k];
+    for (int j = 1; j < 8; ++j) lo[j] = roots[2 * t * j];
 #pragma unroll
-  for (int r = 1; r < 32; ++r) {
-    const int j = r & 7, k = r >> 3;
-    const float2 w = k == 0 ? lo[j] : (j == 0 ? hi[k] : cmul(hi[k], lo[j]));
-    v[r] = cmul(v[r], w);
+    for (int k = 1; k < R / 8; ++k) hi[k] = roots[16 * t * k];
+    float2 a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[u + r * U];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const int j = r & 7, k = r >> 3;
+      const float2 w = k == 0 ? lo[j] : (j == 0 ? hi[k] : cmul(hi[k], lo[j]));
+      a[r] = cmul(a[r], w);
+    }
+    dft<R>(a);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[u + r * U] = a[r];
   }
-  dft<32>(v);
 }
 
 // One half (H = 0: the sums a, H = 1: the twiddled differences b) of a
-// tile through the 1024-point stages, stored at the output rows 2k + H.
+// tile through the M-point stages, stored at the output rows 2k + H.
 // SYNC: wait before the exchange writes LDS (a previous exchange's reads).
-template <int T, int NT, int SQ, int H, bool SYNC>
+template <int N, int T, int LM, int SM, int NT, int SQ, int H, bool SYNC>
 __device__ __forceinline__ void halves_half(float2 (&v)[32], float2* dst, const float2* roots,
                                             float2* lds, const PassArgs& a, int64_t tile,
                                             int tid) {
-  constexpr int E = 32, P = 32;
+  using BL = Blocking<N / 2>;
+  constexpr int E = 32, P = N / 2 / E;
+  static_assert(BL::E == E && num_stages<BL>() == 2, "two-stage halves of 32 per thread");
   constexpr bool MV = move_only(NT);
   int q, p;
-  thread_map<MODE_ROW, T, P>(tid, q, p);
+  thread_map<LM, T, P>(tid, q, p);
   if constexpr (H == 1 && !MV) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cmul(v[e], roots[p + P * e]);
   }
-  radix_stage<2048, E, P, 1, 32, MV>(v, p, roots);
+  radix_stage<N, E, P, 1, BL::R0, MV>(v, p, roots);
   if constexpr (SYNC) __syncthreads();
-  lds_exchange<1024, E, P, T, SQ, 1, 32, MODE_COL>(v, lds, tid, q, p);
-  halves_stage2<P, MV>(v, p, roots);
+  lds_exchange<N / 2, E, P, T, SQ, 1, BL::R0, SM>(v, lds, tid, q, p);
+  halves_stage2<N, E, P, BL::R0, BL::R1, MV>(v, p, roots);
   const int64_t b = tile * T + q;
   if (b < a.B) {
     float2* d = dst + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.os0, a.os1, a.os2);
-    d += (int64_t)(2 * p + H) * a.oks;              // output row 2 (p + P e) + H
-    const int64_t step = (int64_t)(2 * P) * a.oks;
+    const int64_t os = SM == MODE_ROW ? 1 : a.oks;
+    d += (int64_t)(2 * p + H) * os;                 // output row 2 (p + P e) + H
+    const int64_t step = (int64_t)(2 * P) * os;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       float2 w = v[e];
@@ -93,11 +109,43 @@ __device__ __forceinline__ void halves_half(float2 (&v)[32], float2* dst, const 
   }
 }
 
-// Conjugation of an inverse transform's input and the radix-2 split.
-template <int NT>
-__device__ __forceinline__ void halves_begin(float2 (&lo)[32], float2 (&hi)[32],
-                                             const PassArgs& a) {
-  if (a.conj_in) {
+// Loads of one tile: thread (q, p) of the load mapping gets the points
+// p + P e (lo) and M + p + P e (hi) of pencil q; pencils past the end of a
+// ragged last tile read the last pencil (in bounds, never stored).
+template <int N, int T, int LM, int NT>
+__device__ __forceinline__ void halves_load(float2 (&lo)[32], float2 (&hi)[32], const float2* src,
+                                            const PassArgs& a, int64_t tile, int tid) {
+  constexpr int P = N / 2 / 32;
+  int q, p;
+  thread_map<LM, T, P>(tid, q, p);
+  int64_t b = tile * T + q;
+  b = b < a.B ? b : a.B - 1;
+  const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2);
+  const int64_t is = LM == MODE_ROW ? 1 : a.ijs;
+  s += (int64_t)p * is;
+#pragma unroll
+  for (int e = 0; e < 32; ++e) lo[e] = load_c64(s + (int64_t)(P * e) * is, nt_loads(NT));
+#pragma unroll
+  for (int e = 0; e < 32; ++e) hi[e] = load_c64(s + (int64_t)(N / 2 + P * e) * is, nt_loads(NT));
+}
+
+// One workgroup per tile.  In place (src == dst, COL to COL) is allowed:
+// the whole tile is in registers before its first store, and tiles are
+// disjoint.
+template <int N, int T, int LM, int SM, int NT>
+__global__ void __launch_bounds__(T * (N / 64))
+fft_pass_halves(const float2* src, float2* dst, const float2* __restrict__ tw,
+                const float2* __restrict__ twp, const PassArgs a) {
+  constexpr int SQ = lds_pencil_stride<N / 2, T>();
+  __shared__ float2 lds[T * SQ];
+  __shared__ float2 roots[N];
+  const int tid = threadIdx.x;
+  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
+  float2 lo[32], hi[32];
+  halves_load<N, T, LM, NT>(lo, hi, src, a, tile, tid);
+  for (int i = tid; i < N; i += T * (N / 64)) roots[i] = tw[i];
+  __syncthreads();
+  if (a.conj_in) {  // inverse as conj(DFT(conj(x)))
 #pragma unroll
     for (int e = 0; e < 32; ++e) {
       lo[e].y = -lo[e].y;
@@ -105,58 +153,18 @@ __device__ __forceinline__ void halves_begin(float2 (&lo)[32], float2 (&hi)[32],
     }
   }
   halves_split<32, move_only(NT)>(lo, hi);
+  halves_half<N, T, LM, SM, NT, SQ, 0, false>(lo, dst, roots, lds, a, tile, tid);
+  halves_half<N, T, LM, SM, NT, SQ, 1, true>(hi, dst, roots, lds, a, tile, tid);
 }
 
-// Loads of one tile: thread (q, p) of the load mapping gets the points
-// p + P e (lo) and 1024 + p + P e (hi) of pencil q; pencils past the end of
-// a ragged last tile read the last pencil (in bounds, never stored).
-template <int T, int NT>
-__device__ __forceinline__ void halves_load(float2 (&lo)[32], float2 (&hi)[32], const float2* src,
-                                            const PassArgs& a, int64_t tile, int tid,
-                                            bool low, bool high) {
-  constexpr int P = 32;
-  int q, p;
-  thread_map<MODE_ROW, T, P>(tid, q, p);
-  int64_t b = tile * T + q;
-  b = b < a.B ? b : a.B - 1;
-  const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2) + p;
-  if (low) {
-#pragma unroll
-    for (int e = 0; e < 32; ++e) lo[e] = load_c64(s + P * e, nt_loads(NT));
-  }
-  if (high) {
-#pragma unroll
-    for (int e = 0; e < 32; ++e) hi[e] = load_c64(s + 1024 + P * e, nt_loads(NT));
-  }
-}
-
-// One workgroup per tile.
-template <int T, int NT>
-__global__ void __launch_bounds__(T * 32)
-fft_pass_halves(const float2* src, float2* dst, const float2* __restrict__ tw,
-                const float2* __restrict__ twp, const PassArgs a) {
-  constexpr int SQ = lds_pencil_stride<1024, T>();
-  __shared__ float2 lds[T * SQ];
-  __shared__ float2 roots[2048];
-  const int tid = threadIdx.x;
-  const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
-  float2 lo[32], hi[32];
-  halves_load<T, NT>(lo, hi, src, a, tile, tid, true, true);
-  for (int i = tid; i < 2048; i += T * 32) roots[i] = tw[i];
-  __syncthreads();
-  halves_begin<NT>(lo, hi, a);
-  halves_half<T, NT, SQ, 0, false>(lo, dst, roots, lds, a, tile, tid);
-  halves_half<T, NT, SQ, 1, true>(hi, dst, roots, lds, a, tile, tid);
-}
-
-template <int T, int NT>
+template <int N, int T, int LM, int SM, int NT>
 hipError_t launch_halves(const PassArgs& a, const float2* src, float2* dst, const float2* tw,
                          const float2* twp, hipStream_t stream) {
   const int64_t tiles = (a.B + T - 1) / T;
   if (tiles <= 0) return hipSuccess;
   if (tiles > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((fft_pass_halves<T, NT>), dim3((unsigned)tiles), dim3(T * 32), 0, stream,
-                     src, dst, tw, twp, a);
+  hipLaunchKernelGGL((fft_pass_halves<N, T, LM, SM, NT>), dim3((unsigned)tiles),
+                     dim3(T * (N / 64)), 0, stream, src, dst, tw, twp, a);
   return hipGetLastError();
 }
 
@@ -164,18 +172,27 @@ hipError_t launch_halves(const PassArgs& a, const float2* src, float2* dst, cons
 // per CU, and a persistent form that loads the next tile's lower halves
 // during the upper halves' stages needs more registers than its two waves
 // per SIMD have (it spilled and measured slower).
-template <int T, int NT>
+template <int N, int T, int LM, int SM, int NT>
 KernelInfo kernel_info_halves() {
-  constexpr int LDS = (T * lds_pencil_stride<1024, T>() + 2048) * 8;
+  constexpr int LDS = (T * lds_pencil_stride<N / 2, T>() + N) * 8;
   static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
-  static_assert(T * 32 <= 1024, "workgroup too large");
-  KernelInfo k{2048, T, MODE_ROW, MODE_COL, 0, T * 32, LDS, &launch_halves<T, NT>, 0, NT & 3};
+  static_assert(T * (N / 64) <= 1024, "workgroup too large");
+  KernelInfo k{N, T, LM, SM, 0, T * (N / 64), LDS, &launch_halves<N, T, LM, SM, NT>, 0, NT & 3};
   k.move_only = move_only(NT) ? 1 : 0;
   k.r0 = 2;
-  k.r1 = 32;
-  k.r2 = 32;
+  k.r1 = Blocking<N / 2>::R0;
+  k.r2 = Blocking<N / 2>::R1;
   k.halves = 1;
   return k;
+}
+
+// Ordinary and streaming accesses, and their move-only twins.
+template <int N, int T, int LM, int SM>
+void add_halves_kernels(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info_halves<N, T, LM, SM, 0>());
+  v.push_back(kernel_info_halves<N, T, LM, SM, 1>());
+  v.push_back(kernel_info_halves<N, T, LM, SM, 4>());
+  v.push_back(kernel_info_halves<N, T, LM, SM, 5>());
 }
 
 }  // namespace dft3d

@@ -84,13 +84,16 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
     if (opt.persistent) order[nchoice++] = {1, opt.nontemporal};
     order[nchoice++] = {0, opt.nontemporal};
   }
-  // length 2048 rotated on write: the two-halves kernel (16-pencil tiles,
-  // one tile per workgroup; ordinary accesses unless streaming is forced,
-  // measured faster at 2048 x 1024 x 512)
-  if (opt.halves && lmode == MODE_ROW && smode == MODE_COL && tw == 0 &&
-      (opt.tile <= 0 || opt.tile == 16))
-    if (const KernelInfo* k = find_halves_kernel(n, 0, opt.nontemporal == 1 ? 1 : 0, 0))
-      return k;
+  // a two-halves kernel where one is compiled for the length and orders
+  // (one tile per workgroup).  Automatic streaming: only for the strided
+  // 2048 pass of arrays that stream anyway (measured 5.6 against 6.0 ms at
+  // 2048 x 1024 x 512; the others were faster with ordinary accesses)
+  if (opt.halves && tw == 0) {
+    int nt = opt.nontemporal;
+    if (nt == 2) nt = (total_points * 8 >= kStreamBytes && n == 2048 && lmode == MODE_COL);
+    if (const KernelInfo* k = find_halves_kernel(n, lmode, smode, nt, 0))
+      if (opt.tile <= 0 || opt.tile == k->tile) return k;
+  }
   for (int c = 0; c < nchoice; ++c) {
     const int pers = order[c].pers, nt = order[c].nt;
     if (opt.tile > 0) {

@@ -1,10 +1,12 @@
-"""GPU parity of the two-halves rotate-on-write pass of length 2048
-(DFT3D_OPT_HALVES): the radix-2 split x[n] +- x[n + 1024], the difference
-twiddled by w_2048^n, and each half through the 1024-point stages in one
-16-pencil LDS tile, the even outputs first.  Ordinary and streaming
-accesses, forward and inverse, element by element against the FP64 oracle,
-with ragged last tiles and grids of more tiles than resident workgroups; the
-pass is the same whatever the persistent option says (it has one form)."""
+"""GPU parity of the two-halves passes (DFT3D_OPT_HALVES): the radix-2
+split x[n] +- x[n + N/2], the difference twiddled by w_N^n, and each half
+through the N/2-point stages in one LDS tile of twice the pencils, the even
+outputs first -- the rotate-on-write pass of length 2048 (16 pencils) and
+the strided in-place passes of the slab schedule (2048: 16 pencils, 1024:
+32).  Ordinary and streaming accesses, forward and
+inverse, element by element against the FP64 oracle, with ragged last tiles
+and grids of more tiles than resident workgroups; the pass is the same
+whatever the persistent option says (it has one form)."""
 import numpy as np
 import pytest
 
@@ -27,10 +29,10 @@ def say(*a):
     print(*a, flush=True)
 
 
-def execute(x, inverse=False, **kw):
+def execute(x, schedule="pencil", inverse=False, **kw):
     xt = torch.from_numpy(x).cuda()
     y = torch.empty_like(xt)
-    p = dft3d.Plan(x.shape, "pencil", **kw)
+    p = dft3d.Plan(x.shape, schedule, **kw)
     p.execute(xt, y, inverse=inverse)
     torch.cuda.synchronize()
     p.close()
@@ -43,28 +45,41 @@ def reference(x, sign):
     return oracle.dft3d(x.astype(np.complex128), sign, "fft" if pow2 else "direct")
 
 
-def halves_passes(shape, **kw):
-    d = dft3d.describe(shape, "pencil", **kw)
+# (schedule, shape, fused_plane option, the halves passes (n, load, store)):
+# fewer pencils than one tile, a ragged last tile, every axis position
+CASES = [
+    ("pencil", (2048, 3, 5), 1, [(2048, "row", "col")]),
+    ("pencil", (2048, 17, 2), 1, [(2048, "row", "col")]),
+    ("pencil", (2, 2048, 40), 1, [(2048, "row", "col")]),
+    ("pencil", (33, 2, 2048), 1, [(2048, "row", "col")]),
+    ("slab", (1024, 1024, 2), 0, [(1024, "col", "col")] * 2),
+    ("slab", (1024, 4, 2), 0, [(1024, "col", "col")]),
+    ("slab", (1024, 2, 64), 0, [(1024, "col", "col")]),
+    ("slab", (8, 1024, 16), 0, [(1024, "col", "col")]),
+    ("slab", (2048, 4, 8), 0, [(2048, "col", "col")]),
+    ("slab", (2048, 32, 2), 0, [(2048, "col", "col")]),
+]
+
+
+def halves_passes(shape, schedule="pencil", **kw):
+    d = dft3d.describe(shape, schedule, **kw)
     return [p for p in d["passes"] if p["halves"]]
 
 
-# (shape, pencils of the 2048 pass): fewer than one tile, a ragged second
-# tile, 2048 as the middle and the first axis
-SHAPES = [(2048, 3, 5), (2048, 17, 2), (2, 2048, 40), (33, 2, 2048)]
-
-
-@pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("persistent", [0, 1])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[1]}")
 @pytest.mark.parametrize("nontemporal", [0, 1])
-def test_halves_element_by_element(shape, persistent, nontemporal):
-    say("case halves", shape, "persistent", persistent, "nontemporal", nontemporal)
-    kw = dict(persistent=persistent, nontemporal=nontemporal)
-    hp = halves_passes(shape, **kw)
-    assert len(hp) == 1 and hp[0]["tile"] == 16 and hp[0]["persistent"] == 0
-    assert hp[0]["nontemporal"] == nontemporal and hp[0]["radices"] == [2, 32, 32]
+def test_halves_element_by_element(case, nontemporal):
+    schedule, shape, fused_plane, want = case
+    say("case halves", schedule, shape, "nontemporal", nontemporal)
+    kw = dict(nontemporal=nontemporal, fused_plane=fused_plane)
+    hp = halves_passes(shape, schedule, **kw)
+    assert [(p["n"], p["load"], p["store"]) for p in hp] == want, hp
+    for p in hp:
+        assert p["tile"] == 32768 // p["n"] and p["persistent"] == 0
+        assert p["nontemporal"] == nontemporal and p["radices"][0] == 2
     x = inputs.uniform_c64(shape, 71)
     for sign, inv in ((-1, False), (1, True)):
-        y = execute(x, inverse=inv, **kw)
+        y = execute(x, schedule, inverse=inv, **kw)
         ref = reference(x, sign)
         rel, worst = oracle.compare(y, ref)
         say("  ", sign, rel, worst)
@@ -79,7 +94,7 @@ def test_halves_off_keeps_the_whole_length_kernel():
     x = inputs.uniform_c64(shape, 72)
     ref = reference(x, -1)
     for kw in ({"halves": 0}, {"halves": 1}):
-        rel, worst = oracle.compare(execute(x, **kw), ref)
+        rel, worst = oracle.compare(execute(x, "pencil", **kw), ref)
         say("case halves option", kw, rel, worst)
         assert rel <= oracle.tol(x.size) and worst <= 10 * oracle.tol(x.size), kw
 
@@ -94,7 +109,7 @@ def test_halves_many_tiles_per_workgroup(shape, persistent):
     assert halves_passes(shape, **kw)[0]["pencils"] == shape[1] * shape[2]
     x = inputs.uniform_c64(shape, 73)
     for sign, inv in ((-1, False), (1, True)):
-        y = execute(x, inverse=inv, **kw)
+        y = execute(x, "pencil", inverse=inv, **kw)
         rel, worst = oracle.compare(y, reference(x, sign))
         say("  ", sign, rel, worst)
         assert rel <= oracle.tol(x.size), (sign, rel)

@@ -48,16 +48,20 @@ def test_move_only_output_is_the_modelled_permutation(shape, schedule, mode):
 def test_move_only_streaming_persistent_kernels():
     """Shapes of 512 MiB and more run the persistent streaming kernels (the
     forms the 1024^3 breakdown times): (1024, 1024, 64) on the pencil and
-    slab schedules, every element against the model."""
+    slab schedules with the whole-length kernels, and the slab's strided
+    passes as two halves, every element against the model."""
     shape = (1024, 1024, 64)
     x = inputs.uniform_c64(shape, 62)
     xt = torch.from_numpy(x).cuda()
-    for schedule in ("pencil", "slab"):
-        print("case move-only streaming", shape, schedule, flush=True)
-        d = dft3d.describe(shape, schedule, move_only=1)
-        assert any(p["persistent"] and p["nontemporal"] == 1 for p in d["passes"])
+    for schedule, halves in (("pencil", 0), ("slab", 0), ("slab", 1)):
+        print("case move-only streaming", shape, schedule, "halves", halves, flush=True)
+        d = dft3d.describe(shape, schedule, move_only=1, halves=halves)
+        if halves:
+            assert sum(p["halves"] for p in d["passes"]) == 2
+        else:
+            assert any(p["persistent"] and p["nontemporal"] == 1 for p in d["passes"])
         y = torch.empty_like(xt)
-        p = dft3d.Plan(shape, schedule, move_only=1)
+        p = dft3d.Plan(shape, schedule, move_only=1, halves=halves)
         p.execute(xt, y)
         torch.cuda.synchronize()
         assert np.array_equal(bits(y.cpu().numpy()), bits(run_move_model(x, d)))

@@ -500,29 +500,43 @@ def test_rader_option_levels():
             dft3d.describe((1, 1, 17), "pencil", rader=bad)
 
 
+HALVES = {(2048, "row", "col"): 16, (2048, "col", "col"): 16, (1024, "col", "col"): 32}
+
+
 def test_halves_option():
     """DFT3D_OPT_HALVES: the pencil schedule's rotate-on-write passes of
-    length 2048 run as two halves in 16-pencil tiles by default (whatever
-    the persistent option, as there is one form), as the whole length in
-    8-pencil tiles with 0 or with tile 8; other lengths, load and store
-    orders, split precision and other values are untouched or rejected."""
-    for shape in ((2048, 1024, 512), (2048, 3, 5), (4, 2048, 2), (2, 2, 2048)):
-        for kw in ({}, {"persistent": 0}, {"nontemporal": 1}, {"tile": 16}):
-            d = dft3d.describe(shape, "pencil", **kw)
-            for p in d["passes"]:
-                assert p["halves"] == (p["n"] == 2048), (shape, kw, p)
-                if p["halves"]:
-                    assert (p["tile"], p["threads"], p["persistent"]) == (16, 512, 0)
-                    assert p["load"] == "row" and p["store"] == "col" and not p["post_twiddle"]
-                    assert p["nontemporal"] == kw.get("nontemporal", 0)
-        for kw in ({"halves": 0}, {"tile": 8}, {"precision": "bf16x6"}):
-            if "precision" in kw and 3 in shape:
-                continue  # split precision is for powers of two
-            d = dft3d.describe(shape, "pencil", **kw)
-            assert not any(p["halves"] for p in d["passes"]), (shape, kw)
-    # slab and volumetric keep their in-layout passes
-    for sch in ("slab", "volumetric"):
-        assert not any(p["halves"] for p in dft3d.describe((2048, 4, 4), sch)["passes"])
+    length 2048 and the slab schedule's strided passes of lengths 1024 and
+    2048 run as two halves in tiles of twice the pencils (whatever the
+    persistent option, as there is one form); with 0, or a tile option the
+    halves kernel does not have, the whole-length kernels run.  Other
+    lengths, orders, split precision and other values are untouched or
+    rejected."""
+    for shape in ((2048, 1024, 512), (1024, 1024, 1024), (2048, 3, 5), (4, 2048, 2),
+                  (2, 2, 2048), (1024, 4, 2)):
+        for sch in ("pencil", "slab", "volumetric"):
+            for kw in ({}, {"persistent": 0}, {"nontemporal": 1}, {"nontemporal": 0},
+                       {"fused_plane": 0}):
+                d = dft3d.describe(shape, sch, **kw)
+                for p in d["passes"]:
+                    key = (p["n"], p["load"], p["store"])
+                    want = key in HALVES and not p["post_twiddle"] and not p["mixed"] and \
+                        not p["plane_rows"] and not p["fused_axes"]
+                    assert p["halves"] == want, (shape, sch, kw, p)
+                    if p["halves"]:
+                        assert p["tile"] == HALVES[key] and p["persistent"] == 0
+                        assert p["threads"] == p["tile"] * p["n"] // 64
+                        assert p["radices"][0] == 2 and int(np.prod(p["radices"])) == p["n"]
+                        if "nontemporal" in kw:
+                            assert p["nontemporal"] == kw["nontemporal"]
+            for kw in ({"halves": 0}, {"tile": 8}, {"precision": "bf16x6"}):
+                if "precision" in kw and 3 in shape:
+                    continue  # split precision is for powers of two
+                d = dft3d.describe(shape, sch, **kw)
+                assert not any(p["halves"] for p in d["passes"]), (shape, sch, kw)
+    # automatic streaming: only the strided 2048 pass of a streamed array
+    d = dft3d.describe((2048, 1024, 512), "slab")
+    assert [(p["n"], p["nontemporal"]) for p in d["passes"] if p["halves"]] == \
+        [(1024, 0), (2048, 1)]
     for bad in (-1, 2):
         with pytest.raises(dft3d.Dft3dError):
             dft3d.describe((2048, 2, 2), "pencil", halves=bad)
