@@ -77,8 +77,8 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
                               int persistent, int nontemporal);
 // The two-halves pass of length n (halves_kernel.h) with the given load and
 // store orders and form, or null if none is compiled.
-const KernelInfo* find_halves_kernel(int n, int lmode, int smode, int nontemporal,
-                                     int move_only);
+const KernelInfo* find_halves_kernel(int n, int lmode, int smode, int persistent,
+                                     int nontemporal, int move_only);
 // The fused plane kernel for (n1, n2) planes, if compiled.
 const KernelInfo* find_plane_kernel(int n1, int n2);
 // Whether a mixed-radix kernel (variant 1: no 11 or 13 stages, composites

@@ -84,14 +84,17 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
     if (opt.persistent) order[nchoice++] = {1, opt.nontemporal};
     order[nchoice++] = {0, opt.nontemporal};
   }
-  // a two-halves kernel where one is compiled for the length and orders
-  // (one tile per workgroup).  Automatic streaming: only for the strided
-  // 2048 pass of arrays that stream anyway (measured 5.6 against 6.0 ms at
-  // 2048 x 1024 x 512; the others were faster with ordinary accesses)
+  // a two-halves kernel where one is compiled for the length and orders,
+  // streaming and persistent under the same rule as the other passes,
+  // except that the strided 2048 pass has one tile per workgroup only (its
+  // persistent form measured slower: 5.42 against 5.29 ms per launch at
+  // 2048 x 1024 x 512)
   if (opt.halves && tw == 0) {
-    int nt = opt.nontemporal;
-    if (nt == 2) nt = (total_points * 8 >= kStreamBytes && n == 2048 && lmode == MODE_COL);
-    if (const KernelInfo* k = find_halves_kernel(n, lmode, smode, nt, 0))
+    const bool big = total_points * 8 >= kStreamBytes;
+    const int nt = opt.nontemporal == 2 ? (big ? 1 : 0) : opt.nontemporal;
+    const int pers = opt.persistent && (opt.nontemporal != 2 || big) &&
+                     !(n == 2048 && lmode == MODE_COL);
+    if (const KernelInfo* k = find_halves_kernel(n, lmode, smode, pers, nt, 0))
       if (opt.tile <= 0 || opt.tile == k->tile) return k;
   }
   for (int c = 0; c < nchoice; ++c) {

@@ -61,11 +61,12 @@ const KernelInfo* find_kernel(int n, int tile, int lmode, int smode, int post_tw
   return nullptr;
 }
 
-const KernelInfo* find_halves_kernel(int n, int lmode, int smode, int nontemporal,
-                                     int move_only) {
+const KernelInfo* find_halves_kernel(int n, int lmode, int smode, int persistent,
+                                     int nontemporal, int move_only) {
   for (const KernelInfo& k : kernel_registry())
     if (k.halves && k.n == n && k.lmode == lmode && k.smode == smode &&
-        k.nontemporal == nontemporal && k.move_only == move_only)
+        k.persistent == persistent && k.nontemporal == nontemporal &&
+        k.move_only == move_only)
       return &k;
   return nullptr;
 }
@@ -75,7 +76,7 @@ const KernelInfo* find_move_only_kernel(const KernelInfo* k, int mode) {
       k->rader || k->move_only)
     return nullptr;
   if (k->halves && mode == 1)
-    return find_halves_kernel(k->n, k->lmode, k->smode, k->nontemporal, 1);
+    return find_halves_kernel(k->n, k->lmode, k->smode, k->persistent, k->nontemporal, 1);
   for (const KernelInfo& c : kernel_registry()) {
     if (c.move_only != mode || c.halves) continue;
     if (mode == 2 && c.n == k->n) return &c;

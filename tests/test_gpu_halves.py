@@ -4,9 +4,10 @@ through the N/2-point stages in one LDS tile of twice the pencils, the even
 outputs first -- the rotate-on-write pass of length 2048 (16 pencils) and
 the strided in-place passes of the slab schedule (2048: 16 pencils, 1024:
 32).  Ordinary and streaming accesses, forward and
-inverse, element by element against the FP64 oracle, with ragged last tiles
-and grids of more tiles than resident workgroups; the pass is the same
-whatever the persistent option says (it has one form)."""
+inverse, one tile per workgroup and persistent (the next tile's lower
+halves loaded during the current tile's second half), element by element
+against the FP64 oracle, with ragged last tiles and grids of more tiles than
+resident workgroups."""
 import numpy as np
 import pytest
 
@@ -68,14 +69,17 @@ def halves_passes(shape, schedule="pencil", **kw):
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[1]}")
 @pytest.mark.parametrize("nontemporal", [0, 1])
-def test_halves_element_by_element(case, nontemporal):
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_halves_element_by_element(case, nontemporal, persistent):
     schedule, shape, fused_plane, want = case
-    say("case halves", schedule, shape, "nontemporal", nontemporal)
-    kw = dict(nontemporal=nontemporal, fused_plane=fused_plane)
+    say("case halves", schedule, shape, "nontemporal", nontemporal, "persistent", persistent)
+    kw = dict(nontemporal=nontemporal, fused_plane=fused_plane, persistent=persistent)
     hp = halves_passes(shape, schedule, **kw)
     assert [(p["n"], p["load"], p["store"]) for p in hp] == want, hp
     for p in hp:
-        assert p["tile"] == 32768 // p["n"] and p["persistent"] == 0
+        # the strided 2048 pass has one tile per workgroup only
+        pers = persistent and not (p["n"] == 2048 and p["load"] == "col")
+        assert p["tile"] == 32768 // p["n"] and p["persistent"] == pers
         assert p["nontemporal"] == nontemporal and p["radices"][0] == 2
     x = inputs.uniform_c64(shape, 71)
     for sign, inv in ((-1, False), (1, True)):
@@ -103,10 +107,11 @@ def test_halves_off_keeps_the_whole_length_kernel():
 @pytest.mark.parametrize("persistent", [0, 1])
 def test_halves_many_tiles_per_workgroup(shape, persistent):
     """More tiles than resident workgroups (512 tiles; 273 with a last tile
-    of 3 pencils), with the other passes in both forms."""
+    of 3 pencils): the persistent form walks several tiles per workgroup."""
     say("case halves many tiles", shape, "persistent", persistent)
     kw = dict(persistent=persistent, nontemporal=1)
-    assert halves_passes(shape, **kw)[0]["pencils"] == shape[1] * shape[2]
+    hp = halves_passes(shape, **kw)
+    assert hp[0]["pencils"] == shape[1] * shape[2] and hp[0]["persistent"] == persistent
     x = inputs.uniform_c64(shape, 73)
     for sign, inv in ((-1, False), (1, True)):
         y = execute(x, "pencil", inverse=inv, **kw)

@@ -506,8 +506,9 @@ HALVES = {(2048, "row", "col"): 16, (2048, "col", "col"): 16, (1024, "col", "col
 def test_halves_option():
     """DFT3D_OPT_HALVES: the pencil schedule's rotate-on-write passes of
     length 2048 and the slab schedule's strided passes of lengths 1024 and
-    2048 run as two halves in tiles of twice the pencils (whatever the
-    persistent option, as there is one form); with 0, or a tile option the
+    2048 run as two halves in tiles of twice the pencils, persistent under
+    the rule of the other passes except the strided 2048 pass (one form);
+    with 0, or a tile option the
     halves kernel does not have, the whole-length kernels run.  Other
     lengths, orders, split precision and other values are untouched or
     rejected."""
@@ -523,7 +524,10 @@ def test_halves_option():
                         not p["plane_rows"] and not p["fused_axes"]
                     assert p["halves"] == want, (shape, sch, kw, p)
                     if p["halves"]:
-                        assert p["tile"] == HALVES[key] and p["persistent"] == 0
+                        big = shape[0] * shape[1] * shape[2] * 8 >= 256 << 20
+                        pers = kw.get("persistent", 1) and ("nontemporal" in kw or big) and \
+                            key != (2048, "col", "col")
+                        assert p["tile"] == HALVES[key] and p["persistent"] == pers
                         assert p["threads"] == p["tile"] * p["n"] // 64
                         assert p["radices"][0] == 2 and int(np.prod(p["radices"])) == p["n"]
                         if "nontemporal" in kw:
@@ -533,10 +537,16 @@ def test_halves_option():
                     continue  # split precision is for powers of two
                 d = dft3d.describe(shape, sch, **kw)
                 assert not any(p["halves"] for p in d["passes"]), (shape, sch, kw)
-    # automatic streaming: only the strided 2048 pass of a streamed array
+    # automatic streaming and persistence on a streamed array
     d = dft3d.describe((2048, 1024, 512), "slab")
-    assert [(p["n"], p["nontemporal"]) for p in d["passes"] if p["halves"]] == \
-        [(1024, 0), (2048, 1)]
+    assert [(p["n"], p["nontemporal"], p["persistent"]) for p in d["passes"] if p["halves"]] \
+        == [(1024, 1, 1), (2048, 1, 0)]
+    d = dft3d.describe((2048, 1024, 512), "pencil")
+    assert [(p["n"], p["nontemporal"], p["persistent"]) for p in d["passes"] if p["halves"]] \
+        == [(2048, 1, 1)]
+    d = dft3d.describe((2048, 4, 8), "pencil")
+    assert [(p["n"], p["nontemporal"], p["persistent"]) for p in d["passes"] if p["halves"]] \
+        == [(2048, 0, 0)]
     for bad in (-1, 2):
         with pytest.raises(dft3d.Dft3dError):
             dft3d.describe((2048, 2, 2), "pencil", halves=bad)
