@@ -99,6 +99,11 @@ const KernelInfo* pick_kernel(int n, int lmode, int smode, int tw, const Options
   }
   for (int c = 0; c < nchoice; ++c) {
     const int pers = order[c].pers, nt = order[c].nt;
+    // the persistent rotate-on-write pass of length 512 in 32-pencil tiles
+    // (256-byte row segments at one workgroup per CU: 3.50 against 3.68 ms
+    // per launch at 2048 x 1024 x 512)
+    if (opt.tile <= 0 && pers && n == 512 && lmode == MODE_ROW && smode == MODE_COL && !tw)
+      if (const KernelInfo* k = find_kernel(n, 32, lmode, smode, tw, pers, nt)) return k;
     if (opt.tile > 0) {
       if (const KernelInfo* k = find_kernel(n, opt.tile, lmode, smode, tw, pers, nt)) return k;
     }
