@@ -64,6 +64,7 @@ struct KernelInfo {
   int r0 = 0, r1 = 0, r2 = 0;   // FP32 pass kernels: the radix of each stage (1: none)
   int mfma_leaf = 0;  // split-precision MFMA passes: the leaf length (16 or 32)
   int rader = 0;      // > 0: Rader pass for prime lengths up to n - 1 (variant as mixed)
+  int mfma_wide = 0;  // 1: MFMA one-tile pass with twice the default tile
   int halves = 0;     // 1: rotate-on-write pass of length n as two half-length
                       // transforms after a radix-2 split (halves_kernel.h)
 };
@@ -126,10 +127,12 @@ const KernelInfo* find_bluestein_kernel(int m, int tile);
 // shuffled: the finished axis left in the shuffled order).
 const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent, int shuffled);
 // The split-precision MFMA pass kernel for a length and layout, if any
-// (the persistent form when asked for and compiled, else the other form),
-// with leaves of length leaf (16 or 32; 0: the default for the length).
+// (the persistent form when asked for and compiled, else the other form;
+// the wide one-tile form where one is compiled, when the one-tile form or
+// its tile is asked for), with leaves of length leaf (16 or 32; 0: the
+// default for the length).
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
-                                   int persistent, int leaf);
+                                   int persistent, int leaf, int tile = 0);
 // The default MFMA leaf length of a pass length and split precision, and
 // whether the persistent form is the default there.
 int default_mfma_leaf(int n, int precision);

@@ -297,12 +297,12 @@ template <int N> constexpr int mfma_row() { return N + N / 32 + 1; }
 template <int N> __device__ __forceinline__ int mfma_lds(int q, int x) {
   return q * mfma_row<N>() + x + (x >> 5);
 }
-template <int N> constexpr int mfma_buf_elems() {
-  return (mfma_tile_elems<N>() / N) * mfma_row<N>();
+template <int N, int TE = mfma_tile_elems<N>()> constexpr int mfma_buf_elems() {
+  return (TE / N) * mfma_row<N>();
 }
 // Workgroup size: 1024 tile elements per wave, 16 per lane (two waves per
 // SIMD for 8192 points).
-template <int N> constexpr int mfma_threads() { return mfma_tile_elems<N>() / 16; }
+template <int N, int TE = mfma_tile_elems<N>()> constexpr int mfma_threads() { return TE / 16; }
 // Tile elements each lane holds for a stage: 64 / R groups of 16 vectors,
 // R / 4 rows of one vector per group.
 constexpr int kMfmaRegs = 16;
@@ -311,10 +311,10 @@ constexpr int kMfmaRegs = 16;
 // first stage the load mode's contiguous index runs fastest across lanes
 // (ROW: t, COL: q), so the operands come straight from global memory in
 // 128-byte runs; later stages use the ROW order.
-template <int N, int R, int MODE>
+template <int N, int R, int MODE, int TE = mfma_tile_elems<N>()>
 __device__ __forceinline__ void mfma_vec(int g, int& q, int& t) {
   constexpr int stride = N / R;
-  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int T = TE / N;
   if constexpr (MODE == MODE_ROW) { q = g / stride; t = g % stride; }
   else { q = g % T; t = g / T; }
 }
@@ -337,10 +337,10 @@ __device__ __forceinline__ int mfma_first_row(int lane) {
 // n, h) of group gi gets rows rb .. rb + R / 4 - 1 (rb = mfma_first_row)
 // of its vector in v[gi * R / 4 ..].  Pencils past the end of a ragged last
 // tile re-read the last pencil (in bounds, never stored).
-template <int N, int R, int LM>
+template <int N, int R, int LM, int TE = mfma_tile_elems<N>()>
 __device__ __forceinline__ void mfma_load(float2 (&v)[kMfmaRegs], const float2* src,
                                           const PassArgs& a, int64_t tile, int tid) {
-  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int T = TE / N;
   constexpr int stride = N / R;
   const int lane = tid & 63, wave = tid >> 6;
   const int rb = mfma_first_row<R>(lane);
@@ -349,7 +349,7 @@ __device__ __forceinline__ void mfma_load(float2 (&v)[kMfmaRegs], const float2* 
 #pragma unroll
   for (int gi = 0; gi < 64 / R; ++gi) {
     int q, t;
-    mfma_vec<N, R, LM>(mfma_group_vec<R>(wave, gi, lane), q, t);
+    mfma_vec<N, R, LM, TE>(mfma_group_vec<R>(wave, gi, lane), q, t);
     int64_t b = tile * T + q;
     b = b < a.B ? b : a.B - 1;
     const float2* s = src + pencil_offset(b, a.m0, a.m1, a.s0, a.s1, a.is0, a.is1, a.is2) +
@@ -428,7 +428,7 @@ __device__ __forceinline__ void mfma_leaf_store(const float2 (&x)[R / 4],
 
 // First stage from the registers mfma_load filled (conjugated for the
 // inverse), output to LDS buffer out.
-template <int N, int R, int LM, int PREC>
+template <int N, int R, int LM, int PREC, int TE = mfma_tile_elems<N>()>
 __device__ __forceinline__ void mfma_first_stage(const float2 (&v)[kMfmaRegs], float2* out,
                                                  const LeafA<PREC, R>& A, int conj,
                                                  int64_t pbase, int tid) {
@@ -436,7 +436,7 @@ __device__ __forceinline__ void mfma_first_stage(const float2 (&v)[kMfmaRegs], f
 #pragma unroll
   for (int gi = 0; gi < 64 / R; ++gi) {
     int q, t;
-    mfma_vec<N, R, LM>(mfma_group_vec<R>(wave, gi, lane), q, t);
+    mfma_vec<N, R, LM, TE>(mfma_group_vec<R>(wave, gi, lane), q, t);
     float2 x[R / 4];
 #pragma unroll
     for (int k = 0; k < R / 4; ++k) {
@@ -467,7 +467,7 @@ __device__ __forceinline__ void mfma_stage_inputs(float2 (&x)[R / 4], const floa
 // reads the inputs of its groups (twiddled) into registers, the workgroup
 // waits, and the leaves write their outputs back to their Stockham places.
 // One buffer (not two) leaves room for two workgroups per CU.
-template <int N, int R, int PREC>
+template <int N, int R, int PREC, int TE = mfma_tile_elems<N>()>
 __device__ __forceinline__ void mfma_later_stages(float2* io, const float2* ltw,
                                                   const LeafA<PREC, R>& A, int64_t pbase,
                                                   int tid) {
@@ -481,14 +481,14 @@ __device__ __forceinline__ void mfma_later_stages(float2* io, const float2* ltw,
 #pragma unroll
     for (int gi = 0; gi < 64 / R; ++gi) {
       int q, t;
-      mfma_vec<N, R, MODE_ROW>(mfma_group_vec<R>(wave, gi, lane), q, t);
+      mfma_vec<N, R, MODE_ROW, TE>(mfma_group_vec<R>(wave, gi, lane), q, t);
       mfma_stage_inputs<N, R>(x[gi], io, ltw, q, t, NS, rb);
     }
     __syncthreads();  // every input of the stage is read
 #pragma unroll
     for (int gi = 0; gi < 64 / R; ++gi) {
       int q, t;
-      mfma_vec<N, R, MODE_ROW>(mfma_group_vec<R>(wave, gi, lane), q, t);
+      mfma_vec<N, R, MODE_ROW, TE>(mfma_group_vec<R>(wave, gi, lane), q, t);
       mfma_leaf_store<N, R, PREC>(x[gi], A, io, pbase, q, t, NS, lane);
     }
     __syncthreads();  // every output of the stage is written
@@ -532,11 +532,11 @@ __device__ __forceinline__ int mfma_later_stages_pingpong(float2 (*buf)[mfma_buf
 // Last step: with a leftover radix, its butterflies read LDS and write
 // straight to global memory (lanes ordered by the store mode's contiguous
 // index); otherwise the result is copied out in the store mode's order.
-template <int N, int SM, int L>
+template <int N, int SM, int L, int TE = mfma_tile_elems<N>()>
 __device__ __forceinline__ void mfma_finish(const float2* res, float2* dst, const float2* ltw,
                                             const PassArgs& a, int64_t tile, int tid) {
-  constexpr int T = mfma_tile_elems<N>() / N;
-  constexpr int NTHR = mfma_threads<N>();
+  constexpr int T = TE / N;
+  constexpr int NTHR = mfma_threads<N, TE>();
   constexpr int REST = mfma_rest<N, L>();
   if constexpr (REST > 1) {
     constexpr int BF = N / REST;  // butterflies per pencil == stride of the outputs
@@ -570,7 +570,7 @@ __device__ __forceinline__ void mfma_finish(const float2* res, float2* dst, cons
       }
     }
   } else {
-    constexpr int EPT = mfma_tile_elems<N>() / NTHR;
+    constexpr int EPT = TE / NTHR;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int idx = tid + NTHR * e;
@@ -589,29 +589,31 @@ __device__ __forceinline__ void mfma_finish(const float2* res, float2* dst, cons
 
 // Waves per SIMD the one-tile form asks the compiler for: four (at most
 // 128 VGPRs) where two workgroups fit in a CU's LDS, else two.
-template <int N> constexpr int mfma_one_tile_waves() {
-  return 2 * (mfma_buf_elems<N>() + N) * 8 <= 160 * 1024 ? 4 : 2;
+template <int N, int TE = mfma_tile_elems<N>()> constexpr int mfma_one_tile_waves() {
+  return (2 * (mfma_buf_elems<N, TE>() + N) * 8 <= 160 * 1024 || mfma_threads<N, TE>() >= 1024)
+             ? 4 : 2;
 }
 
-// One tile per workgroup.
-template <int N, int LM, int SM, int PREC, int L>
-__global__ void __launch_bounds__(mfma_threads<N>(), mfma_one_tile_waves<N>())
+// One tile per workgroup (TE tile elements: the default, or twice that in
+// the wide form, whose rotated store writes rows of twice the pencils).
+template <int N, int LM, int SM, int PREC, int L, int TE = mfma_tile_elems<N>()>
+__global__ void __launch_bounds__((mfma_threads<N, TE>()), (mfma_one_tile_waves<N, TE>()))
 fft_pass_mfma(const float2* src, float2* dst, const float2* __restrict__ tw,
               const unsigned short* __restrict__ leaf, const PassArgs a) {
-  __shared__ float2 buf[mfma_buf_elems<N>()];
+  __shared__ float2 buf[mfma_buf_elems<N, TE>()];
   __shared__ float2 ltw[N];
   const int tid = threadIdx.x;
   const int64_t tile = tile_index(blockIdx.x, gridDim.x, a.xcd_remap);
   float2 v[kMfmaRegs];
-  mfma_load<N, L, LM>(v, src, a, tile, tid);
-  for (int i = tid; i < N; i += mfma_threads<N>()) ltw[i] = tw[i];
+  mfma_load<N, L, LM, TE>(v, src, a, tile, tid);
+  for (int i = tid; i < N; i += mfma_threads<N, TE>()) ltw[i] = tw[i];
   LeafA<PREC, L> A;
   A.load(leaf, tid & 63);
-  constexpr int T = mfma_tile_elems<N>() / N;
-  mfma_first_stage<N, L, LM, PREC>(v, buf, A, a.conj_in, tile * T, tid);
+  constexpr int T = TE / N;
+  mfma_first_stage<N, L, LM, PREC, TE>(v, buf, A, a.conj_in, tile * T, tid);
   __syncthreads();
-  mfma_later_stages<N, L, PREC>(buf, ltw, A, tile * T, tid);
-  mfma_finish<N, SM, L>(buf, dst, ltw, a, tile, tid);
+  mfma_later_stages<N, L, PREC, TE>(buf, ltw, A, tile * T, tid);
+  mfma_finish<N, SM, L, TE>(buf, dst, ltw, a, tile, tid);
 }
 
 // Persistent form: about one resident workgroup per CU walks the tiles
@@ -652,15 +654,15 @@ fft_pass_mfma_persistent(const float2* src, float2* dst, const float2* __restric
   }
 }
 
-template <int N, int LM, int SM, int PREC, int L>
+template <int N, int LM, int SM, int PREC, int L, int TE = mfma_tile_elems<N>()>
 hipError_t launch_mfma(const PassArgs& a, const float2* src, float2* dst, const float2* tw,
                        const float2* leaf, hipStream_t stream) {
-  constexpr int T = mfma_tile_elems<N>() / N;
+  constexpr int T = TE / N;
   const int64_t blocks = (a.B + T - 1) / T;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((fft_pass_mfma<N, LM, SM, PREC, L>), dim3((unsigned)blocks),
-                     dim3(mfma_threads<N>()), 0, stream, src, dst, tw,
+  hipLaunchKernelGGL((fft_pass_mfma<N, LM, SM, PREC, L, TE>), dim3((unsigned)blocks),
+                     dim3(mfma_threads<N, TE>()), 0, stream, src, dst, tw,
                      reinterpret_cast<const unsigned short*>(leaf), a);
   return hipGetLastError();
 }
@@ -703,6 +705,21 @@ KernelInfo kernel_info_mfma() {
   return k;
 }
 
+// The wide one-tile form (twice the tile elements, one workgroup per CU
+// with 1024 threads, four waves per SIMD).
+template <int N, int LM, int SM, int PREC, int L>
+KernelInfo kernel_info_mfma_wide() {
+  constexpr int TE = 2 * mfma_tile_elems<N>();
+  constexpr int LDS = (mfma_buf_elems<N, TE>() + N) * 8;
+  static_assert(LDS <= 160 * 1024, "tile exceeds LDS");
+  static_assert(mfma_threads<N, TE>() <= 1024, "workgroup too large");
+  KernelInfo k{N, TE / N, LM, SM, 0, mfma_threads<N, TE>(), LDS,
+               &launch_mfma<N, LM, SM, PREC, L, TE>, 0, 0, PREC};
+  k.mfma_leaf = L;
+  k.mfma_wide = 1;
+  return k;
+}
+
 template <int N, int PREC, int L>
 void add_mfma_kernels_prec(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_COL, PREC, 0, L>());
@@ -711,6 +728,17 @@ void add_mfma_kernels_prec(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_COL, PREC, 1, L>());
   v.push_back(kernel_info_mfma<N, MODE_ROW, MODE_ROW, PREC, 1, L>());
   v.push_back(kernel_info_mfma<N, MODE_COL, MODE_COL, PREC, 1, L>());
+}
+
+// The wide rotate-on-write form of every precision of one length and leaf
+// length.
+template <int N, int L>
+void add_mfma_wide_kernels(std::vector<KernelInfo>& v) {
+  v.push_back(kernel_info_mfma_wide<N, MODE_ROW, MODE_COL, DFT3D_PREC_BF16X1, L>());
+  v.push_back(kernel_info_mfma_wide<N, MODE_ROW, MODE_COL, DFT3D_PREC_FP16X1, L>());
+  v.push_back(kernel_info_mfma_wide<N, MODE_ROW, MODE_COL, DFT3D_PREC_BF16X6, L>());
+  v.push_back(kernel_info_mfma_wide<N, MODE_ROW, MODE_COL, DFT3D_PREC_BF16X9, L>());
+  v.push_back(kernel_info_mfma_wide<N, MODE_ROW, MODE_COL, DFT3D_PREC_FP16X3, L>());
 }
 
 // Every precision of one length and leaf length.

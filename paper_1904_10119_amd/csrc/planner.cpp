@@ -217,9 +217,10 @@ struct Builder {
           opt.persistent &&
           (opt.nontemporal == 1 || (opt.nontemporal == 2 && total_points * 8 >= kStreamBytes &&
                                     default_mfma_persistent(n, opt.precision)));
-      k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, opt.mfma_leaf);
+      k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, opt.mfma_leaf, opt.tile);
       // a length without leaves of the asked length keeps its default leaves
-      if (!k && opt.mfma_leaf) k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, 0);
+      if (!k && opt.mfma_leaf)
+        k = find_mfma_kernel(n, lmode, smode, opt.precision, pers, 0, opt.tile);
       if (k) leaf = opt.precision;
     }
     if (!k) k = pick_kernel(n, lmode, smode, tw, opt, total_points);

@@ -15,6 +15,7 @@ void register_kernels_mfma_b(std::vector<KernelInfo>& v);
 void register_kernels_mfma_c(std::vector<KernelInfo>& v);
 void register_kernels_mfma_d(std::vector<KernelInfo>& v);
 void register_kernels_mfma_e(std::vector<KernelInfo>& v);
+void register_kernels_mfma_f(std::vector<KernelInfo>& v);
 void register_kernels_plane(std::vector<KernelInfo>& v);
 void register_kernels_fused(std::vector<KernelInfo>& v);
 void register_kernels_bluestein(std::vector<KernelInfo>& v);
@@ -36,6 +37,7 @@ const std::vector<KernelInfo>& kernel_registry() {
     register_kernels_mfma_c(v);
     register_kernels_mfma_d(v);
     register_kernels_mfma_e(v);
+    register_kernels_mfma_f(v);
     register_kernels_plane(v);
     register_kernels_fused(v);
     register_kernels_bluestein(v);
@@ -273,12 +275,19 @@ bool default_mfma_persistent(int n, int precision) {
 }
 
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
-                                   int persistent, int leaf) {
+                                   int persistent, int leaf, int tile) {
   if (leaf == 0) leaf = default_mfma_leaf(n, precision);
+  // the wide one-tile form where compiled (length 2048 rotated on write),
+  // unless the persistent form or another tile is asked for
+  if (tile > 0 || !persistent)
+    for (const KernelInfo& k : kernel_registry())
+      if (k.mfma_wide && k.n == n && k.lmode == lmode && k.smode == smode &&
+          k.precision == precision && k.mfma_leaf == leaf && (tile <= 0 || k.tile == tile))
+        return &k;
   const KernelInfo* other = nullptr;
   for (const KernelInfo& k : kernel_registry())
-    if (k.n == n && k.lmode == lmode && k.smode == smode && k.precision == precision &&
-        k.mfma_leaf == leaf) {
+    if (!k.mfma_wide && k.n == n && k.lmode == lmode && k.smode == smode &&
+        k.precision == precision && k.mfma_leaf == leaf) {
       if (k.persistent == persistent) return &k;
       other = &k;
     }
