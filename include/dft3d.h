@@ -198,6 +198,20 @@ enum dft3d_option {
                                 0 = the whole-length kernels.  Taken when
                                 DFT3D_OPT_TILE is 0 or the halves kernel's
                                 tile.  Other values: INVALID_ARG */
+  DFT3D_OPT_PENCIL_ORDER = 17, /* pencil schedule, every axis a power of two
+                                and unsplit: the intermediate orders, all
+                                ending in the natural order.  0 = each pass
+                                writes its axis slowest (the rotation
+                                xyz -> yzx of eq. (8)); 1 = the first pass
+                                swaps the two fastest axes and the second
+                                writes (C, B, A); 2 = (A, B, C) ->
+                                (B, C, A) -> (C, A, B) -> (A, B, C), every
+                                pass loading pencils one plane apart and
+                                storing rows one row length apart; -1
+                                (default) = 2 for split precision and for
+                                arrays with an axis of 2048, else 0 (the
+                                faster order measured for each).  Other
+                                values: INVALID_ARG */
   DFT3D_OPT_NUM_PASSES = 100 /* read-only: number of kernel launches */
 };
 

@@ -274,6 +274,10 @@ int apply_option(Options& o, int key, int64_t value) {
       if (value < 0 || value > 1) return DFT3D_ERR_INVALID_ARG;
       o.halves = (int)value;
       return DFT3D_OK;
+    case DFT3D_OPT_PENCIL_ORDER:
+      if (value < -1 || value > 2) return DFT3D_ERR_INVALID_ARG;
+      o.pencil_order = (int)value;
+      return DFT3D_OK;
     default:
       return DFT3D_ERR_INVALID_ARG;
   }
@@ -533,6 +537,7 @@ int dft3d_plan_get_option(dft3d_plan_t p, int key, int64_t* value) {
     case DFT3D_OPT_RADICES: *value = (int64_t)p->opt.radices; break;
     case DFT3D_OPT_RADER: *value = p->opt.rader; break;
     case DFT3D_OPT_HALVES: *value = p->opt.halves; break;
+    case DFT3D_OPT_PENCIL_ORDER: *value = p->opt.pencil_order; break;
     case DFT3D_OPT_NUM_PASSES: *value = (int64_t)p->passes.size(); break;
     default: return DFT3D_ERR_INVALID_ARG;
   }

@@ -194,6 +194,10 @@ struct Options {
                         // of their product's length, run by the mixed-radix kernel; 0: default
   int rader = 1;        // prime lengths with smooth n - 1: 0 Bluestein, 1 Rader where a
                         // kernel is compiled for n, 2 Rader also with the generic kernel
+  int pencil_order = -1; // pencil schedule intermediates (powers of two, unsplit):
+                         // 0 rotate (c2, c0, c1) each pass; 1 swap the two fastest
+                         // axes on the first two passes; 2 cycle (A, B, C) ->
+                         // (B, C, A) -> (C, A, B) -> (A, B, C); -1 automatic
   int halves = 1;       // rotate-on-write passes of length 2048 as two halves in
                         // 16-pencil tiles (1) or whole in 8-pencil tiles (0)
 };

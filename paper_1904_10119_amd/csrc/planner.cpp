@@ -517,6 +517,73 @@ void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
   }
 }
 
+// The pencil order a plan runs: the option, or automatically the cycle
+// for split precision (1024^3 bf16x6 14.3 -> 12.2 ms, bf16x9 14.9 -> 11.4,
+// 2048 x 1024 x 512 bf16x6 15.5 -> 13.1: the matrix-core passes' 64-byte
+// row segments cost far less one row apart than one plane apart) and for
+// FP32 arrays with an axis of 2048 (2048 x 1024 x 512: 11.1 -> 10.6 ms),
+// else the rotation (1024^3: 10.5 ms against 10.75 cycled; its pass keeps
+// whole-pencil loads).
+int pencil_order(const int64_t n[3], const Options& opt) {
+  if (opt.pencil_order >= 0) return opt.pencil_order;
+  if (opt.precision != DFT3D_PREC_FP32) return 2;
+  return (n[0] == 2048 || n[1] == 2048 || n[2] == 2048) ? 2 : 0;
+}
+
+// The pencil schedule in the other intermediate orders, on an (A, B, C)
+// array of powers of two.  Order 1: the C pass writes (A, C, B) (output
+// rows B apart instead of A B), the B pass reads pencils (a fastest, c) of
+// that and writes (C, B, A) (rows A apart), and the A pass reads pencils
+// (c fastest, b) and writes the natural (A, B, C).  Order 2: the cycle
+// below.  Every pass loads whole pencils and stores rows of consecutive
+// pencils, as the rotation does; only the intermediate orders differ.
+void pencil_swapped(Builder& b, const int64_t n[3]) {
+  const int64_t A = n[0], B = n[1], C = n[2];
+  char lab[64];
+  if (pencil_order(n, b.opt) == 2) {
+    // every pass: tiles of pencils one plane apart, rows one row length
+    // apart: (A, B, C) -> (B, C, A) -> (C, A, B) -> (A, B, C)
+    {
+      Field f[2] = {{A, B * C, 1}, {B, C, C * A}};
+      std::snprintf(lab, sizeof lab, "pencil2 DFT%lld x%lld cyc", (long long)C,
+                    (long long)(A * B));
+      b.add((int)C, MODE_ROW, MODE_COL, 0, f, 2, 1, A, 0, 0, 0, lab);
+    }
+    if (b.status != DFT3D_OK) return;
+    {
+      Field f[2] = {{B, C * A, 1}, {C, A, A * B}};
+      std::snprintf(lab, sizeof lab, "pencil0 DFT%lld x%lld cyc", (long long)A,
+                    (long long)(B * C));
+      b.add((int)A, MODE_ROW, MODE_COL, 0, f, 2, 1, B, 0, 0, 0, lab);
+    }
+    if (b.status != DFT3D_OK) return;
+    {
+      Field f[2] = {{C, A * B, 1}, {A, B, B * C}};
+      std::snprintf(lab, sizeof lab, "pencil1 DFT%lld x%lld cyc", (long long)B,
+                    (long long)(A * C));
+      b.add((int)B, MODE_ROW, MODE_COL, 0, f, 2, 1, C, 0, 0, 0, lab);
+    }
+    return;
+  }
+  {
+    Field f[2] = {{B, C, 1}, {A, B * C, C * B}};
+    std::snprintf(lab, sizeof lab, "pencil2 DFT%lld x%lld swap", (long long)C, (long long)(A * B));
+    b.add((int)C, MODE_ROW, MODE_COL, 0, f, 2, 1, B, 0, 0, 0, lab);
+  }
+  if (b.status != DFT3D_OK) return;
+  {
+    Field f[2] = {{A, C * B, 1}, {C, B, B * A}};
+    std::snprintf(lab, sizeof lab, "pencil1 DFT%lld x%lld swap", (long long)B, (long long)(A * C));
+    b.add((int)B, MODE_ROW, MODE_COL, 0, f, 2, 1, A, 0, 0, 0, lab);
+  }
+  if (b.status != DFT3D_OK) return;
+  {
+    Field f[2] = {{C, B * A, 1}, {B, A, C}};
+    std::snprintf(lab, sizeof lab, "pencil0 DFT%lld x%lld rot", (long long)A, (long long)(B * C));
+    b.add((int)A, MODE_ROW, MODE_COL, 0, f, 2, 1, B * C, 0, 0, 0, lab);
+  }
+}
+
 // One pass of length n along an axis, in layout (element strides ijs, oks)
 // over the pencils of fields f: the power-of-two pass kernels, else the
 // mixed-radix pass (prime factors at most 13), else the one-pass Bluestein
@@ -704,6 +771,11 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
   if (group > 0) {
     pencil_grouped(b, n, group);
     need_ws = 1;
+  } else if (resolved == DFT3D_SCHED_PENCIL && pencil_order(n, opt) > 0 && is_pow2(n[0]) &&
+             is_pow2(n[1]) && is_pow2(n[2]) && n[0] <= split_max && n[1] <= split_max &&
+             n[2] <= split_max) {
+    pencil_swapped(b, n);
+    assign_chain(passes, 0, need_ws);
   } else if (resolved == DFT3D_SCHED_PENCIL) {
     int64_t cur[3] = {n[0], n[1], n[2]};
     for (int step = 0; step < 3; ++step) {

@@ -22,7 +22,7 @@ PRECISIONS = {"fp32": 0, "bf16x1": 1, "fp16x1": 2, "bf16x6": 3, "bf16x9": 4,
 OPT_PRECISION, OPT_TILE, OPT_XCD_REMAP, OPT_SPLIT_MAX, OPT_NONTEMPORAL = 1, 2, 3, 4, 5
 OPT_PERSISTENT, OPT_SLAB_GROUP, OPT_FUSED_PLANE, OPT_FUSED_AXES = 6, 7, 8, 9
 OPT_PENCIL_GROUP, OPT_BATCH_LAUNCH, OPT_MOVE_ONLY, OPT_MFMA_LEAF = 10, 11, 12, 13
-OPT_RADICES, OPT_RADER, OPT_HALVES = 14, 15, 16
+OPT_RADICES, OPT_RADER, OPT_HALVES, OPT_PENCIL_ORDER = 14, 15, 16, 17
 OPT_NUM_PASSES = 100
 
 OK = 0
@@ -102,7 +102,7 @@ OPTION_KEYS = {"precision": OPT_PRECISION, "tile": OPT_TILE,
                "fused_axes": OPT_FUSED_AXES, "pencil_group": OPT_PENCIL_GROUP,
                "batch_launch": OPT_BATCH_LAUNCH, "move_only": OPT_MOVE_ONLY,
                "mfma_leaf": OPT_MFMA_LEAF, "radices": OPT_RADICES, "rader": OPT_RADER,
-               "halves": OPT_HALVES}
+               "halves": OPT_HALVES, "pencil_order": OPT_PENCIL_ORDER}
 
 
 def radix_code(radices) -> int:
@@ -169,7 +169,8 @@ class Plan:
                  nontemporal: int = -1, persistent: int = -1,
                  slab_group: int = -2, fused_plane: int = -1, fused_axes: int = -1,
                  pencil_group: int = -2, batch_launch: int = -1, move_only: int = 0,
-                 mfma_leaf: int = 0, radices=0, rader: int = -1, halves: int = -1):
+                 mfma_leaf: int = 0, radices=0, rader: int = -1, halves: int = -1,
+                 pencil_order: int = -1):
         self.shape = tuple(int(s) for s in shape)
         self.schedule = schedule
         h = ctypes.c_void_p()
@@ -211,6 +212,8 @@ class Plan:
                 self.set_option(OPT_RADER, rader)
             if halves >= 0:
                 self.set_option(OPT_HALVES, halves)
+            if pencil_order >= 0:
+                self.set_option(OPT_PENCIL_ORDER, pencil_order)
         except Exception:
             self.close()
             raise

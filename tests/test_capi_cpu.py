@@ -145,7 +145,10 @@ def test_volumetric_splits_every_axis():
 
 def test_auto_splits_long_axes():
     # untuned auto splits only 4096-long axes; split_max lowers the bar
+    # (unsplit, the 2048 array takes the cycled pencil order: axes 2, 0, 1)
     d = dft3d.describe((2048, 1024, 512), "auto")
+    assert [p["n"] for p in d["passes"]] == [512, 2048, 1024]
+    d = dft3d.describe((2048, 1024, 512), "auto", pencil_order=0)
     assert [p["n"] for p in d["passes"]] == [512, 1024, 2048]
     d = dft3d.describe((4096, 128, 64), "auto")
     assert [p["n"] for p in d["passes"]] == [64, 128, 64, 64]
@@ -169,8 +172,9 @@ def test_auto_uses_slab_below_the_cache_size():
 def test_split_precision_uses_mfma_leaves_where_available():
     d = dft3d.describe((256, 256, 256), "pencil", precision="bf16x6")
     assert all(p["precision"] == dft3d.PRECISIONS["bf16x6"] for p in d["passes"])
-    # lengths below 16 have no MFMA leaf and stay on FP32 butterflies
-    d = dft3d.describe((8, 256, 4), "pencil", precision="bf16x9")
+    # lengths below 16 have no MFMA leaf and stay on FP32 butterflies (in
+    # the rotation's pass order: axes 2, 1, 0)
+    d = dft3d.describe((8, 256, 4), "pencil", precision="bf16x9", pencil_order=0)
     assert [p["precision"] for p in d["passes"]] == [0, dft3d.PRECISIONS["bf16x9"], 0]
     # four-step first halves (post twiddle) stay FP32
     d = dft3d.describe((2048, 1024, 512), "auto", precision="fp16x3", split_max=1024)

@@ -932,3 +932,47 @@ def test_move_only_limits():
         dft3d.describe((100, 64, 64), "pencil", move_only=1)
     with pytest.raises(dft3d.Dft3dError):
         dft3d.describe((64, 64, 64), "volumetric", "shuffled", move_only=1)
+
+
+# ---------------------------------------------------------------------------
+# Pencil orders (DFT3D_OPT_PENCIL_ORDER): the intermediate layouts of the
+# pencil schedule.
+
+ORDER_SHAPES = [(8, 16, 32), (32, 4, 8), (2, 64, 4), (16, 16, 16), (1, 8, 4), (4, 1, 2),
+                (2048, 2, 4), (4, 1024, 2)]
+
+
+@pytest.mark.parametrize("shape", ORDER_SHAPES)
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_pencil_orders_compute_the_dft(shape, order):
+    """Every order's pass list (fields, strides, buffers) computes the 3D
+    DFT when each pass is run as the kernels address memory, forward and
+    inverse, and its last pass writes the natural order."""
+    d = dft3d.describe(shape, "pencil", pencil_order=order)
+    assert len(d["passes"]) == 3
+    tag = {0: "rot", 1: "swap", 2: "cyc"}[order]
+    assert all(p["label"].split()[-1] in (tag, "rot") for p in d["passes"])
+    check_pass_maps(d, int(np.prod(shape)))
+    g = np.random.default_rng(int(np.prod(shape)) + order)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    for sign in (-1, 1):
+        assert oracle.rel_l2(run_model(x, d, sign), oracle.dft3d(x, sign, "fft")) < 1e-12
+
+
+def test_pencil_order_default_and_values():
+    """Automatic order: the cycle for split precision and for arrays with an
+    axis of 2048, else the rotation; lengths that are not powers of two and
+    split axes keep the rotation; values outside -1..2 are rejected."""
+    def tags(shape, **kw):
+        return [p["label"].split()[-1] for p in dft3d.describe(shape, "pencil", **kw)["passes"]]
+    assert tags((1024, 1024, 1024)) == ["rot"] * 3
+    assert tags((1024, 1024, 1024), precision="bf16x6") == ["cyc"] * 3
+    assert tags((2048, 1024, 512)) == ["cyc"] * 3
+    assert tags((2048, 1024, 512), pencil_order=0) == ["rot"] * 3
+    assert tags((1024, 1024, 1024), pencil_order=2) == ["cyc"] * 3
+    assert tags((1024, 1024, 1024), pencil_order=1) == ["swap", "swap", "rot"]
+    assert all(t in ("rot",) for t in tags((1000, 1000, 1000), pencil_order=2))
+    assert tags((8, 8, 4096), pencil_order=2, split_max=2048)[-1] == "rot"
+    for bad in (-2, 3):
+        with pytest.raises(dft3d.Dft3dError):
+            dft3d.describe((8, 8, 8), "pencil", pencil_order=bad)
