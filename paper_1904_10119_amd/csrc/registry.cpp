@@ -253,25 +253,29 @@ const KernelInfo* find_plane_kernel(int n1, int n2) {
 
 // Measured on MI355X (pencil plans, same box): leaf 32 / leaf 16 time at
 // 128^3, 256^3 and 4096 x 256 x 256 0.87 .. 0.97 in every split form, 64^3
-// 1.10 .. 1.13 (64 = 32 * 2 against 16 * 4).  With the one-tile kernel at
-// four waves per SIMD: 1024^3 bf16x6 14.33 ms (32) / 14.85 (16), fp16x3
-// 14.78 / 15.17 (persistent 14.18 / 14.46), bf16x9 15.30 / 14.99;
-// 2048 x 1024 x 512 bf16x6 16.71 / 17.23, fp16x3 15.81 / 16.31, bf16x9
-// 17.75 / 18.19.
+// 1.10 .. 1.13 (64 = 32 * 2 against 16 * 4).  At lengths 1024 and 2048,
+// with the cycled intermediate orders that split-precision pencil plans
+// run, leaves of 16 are faster in every split form: 1024^3 bf16x6 10.57 ms
+// (16) against 11.76 (32), bf16x9 11.43 / 12.83, fp16x3 12.19 / 12.46;
+// 2048 x 1024 x 512 bf16x6 12.50 / 13.06, bf16x9 13.32 / 13.86, fp16x3
+// 12.15 / 12.31.
 int default_mfma_leaf(int n, int precision) {
-  if (n == 1024 && precision == DFT3D_PREC_BF16X9) return 16;
-  if (n == 128 || n == 256 || n == 1024 || n == 2048 || n == 4096) return 32;
+  (void)precision;
+  if (n == 128 || n == 256 || n == 4096) return 32;
   return 16;
 }
 
 // The persistent MFMA form (one workgroup per CU, next tile prefetched)
-// measured faster than the one-tile form (two workgroups per CU, four
-// waves per SIMD) only for the fp16 forms at length 1024 (1024^3 fp16x3
-// 14.18 against 14.78 ms); elsewhere the one-tile form (1024^3 bf16x6 14.33
-// against 15.31, 2048 x 1024 x 512 bf16x6 16.71 against 19.33, 512^3
-// 1.31 against 1.39).
+// against the one-tile form (two workgroups per CU, four waves per SIMD),
+// cycled pencil orders: slower in every form measured (1024^3 fp16x3
+// 14.46 against 12.19 ms, bf16x6 equal within 0.5 %; 2048 x 1024 x 512
+// fp16x3 12.89 against 12.15), so the one-tile form is the default
+// wherever both exist; the persistent form stays an option (nontemporal = 1
+// with persistent on).
 bool default_mfma_persistent(int n, int precision) {
-  return n == 1024 && (precision == DFT3D_PREC_FP16X3 || precision == DFT3D_PREC_FP16X1);
+  (void)n;
+  (void)precision;
+  return false;
 }
 
 const KernelInfo* find_mfma_kernel(int n, int lmode, int smode, int precision,
