@@ -54,7 +54,8 @@ struct KernelInfo {
   int precision = 0; // DFT3D_PREC_*: FP32 butterflies or split MFMA leaves
   int plane_rows = 0; // > 0: fused 2D DFT of (plane_rows, n) planes, one per workgroup
   int fused_axes = 0; // 1: volumetric V2 of one axis fused with V1 of the next (n = a);
-                      // 2: the same with the finished axis left in the shuffled order
+                      // 2: the same with the finished axis left in the shuffled order;
+                      // 3: inverse from the shuffled order (the transposed pass)
   int bluestein = 0;  // 1: one-pass Bluestein axis (length not a power of two, n = m)
   int mixed = 0;      // > 0: mixed-radix pass in LDS for lengths up to n (the variant)
   int fixed_n = 0;              // mixed-radix pass compiled for this one length, 0: any
@@ -125,7 +126,8 @@ const KernelInfo* find_bluestein_kernel(int m, int tile);
 // The fused volumetric two-axis kernel for split factor a, if compiled
 // (contig: V2 runs contiguous in memory; the persistent form if asked for;
 // shuffled: the finished axis left in the shuffled order).
-const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent, int shuffled);
+// kind: 1 natural, 2 shuffled forward, 3 inverse from the shuffled order
+const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent, int kind);
 // The split-precision MFMA pass kernel for a length and layout, if any
 // (the persistent form when asked for and compiled, else the other form;
 // the wide one-tile form where one is compiled, when the one-tile form or

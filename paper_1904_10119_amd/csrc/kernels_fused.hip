@@ -1,5 +1,5 @@
 // Fused volumetric two-axis kernels for split factors 16 and 32, natural and
-// shuffled layouts.
+// shuffled layouts, and the inverse from the shuffled layout.
 #include "fused_axes_kernel.h"
 
 namespace dft3d {
@@ -21,5 +21,14 @@ void register_kernels_fused(std::vector<KernelInfo>& v) {
   v.push_back(kernel_info_fused_axes<32, 16, 0, 1, 1>());
   v.push_back(kernel_info_fused_axes<16, 16, 1, 1, 1>());
   v.push_back(kernel_info_fused_axes<16, 32, 0, 1, 1>());
+  // inverse from the shuffled layout: the transposed pass, in place
+  v.push_back(kernel_info_fused_axes<32, 16, 1, 0, 3>());
+  v.push_back(kernel_info_fused_axes<32, 16, 0, 0, 3>());
+  v.push_back(kernel_info_fused_axes<16, 16, 1, 0, 3>());
+  v.push_back(kernel_info_fused_axes<16, 32, 0, 0, 3>());
+  v.push_back(kernel_info_fused_axes<32, 16, 1, 1, 3>());
+  v.push_back(kernel_info_fused_axes<32, 16, 0, 1, 3>());
+  v.push_back(kernel_info_fused_axes<16, 16, 1, 1, 3>());
+  v.push_back(kernel_info_fused_axes<16, 32, 0, 1, 3>());
 }
 }  // namespace dft3d

@@ -400,36 +400,63 @@ void volumetric_v2(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis
   }
 }
 
-// V2 of axis d and V1 of axis d - 1 in one pass, when a = A_d equals
-// B_{d-1} and a kernel for it exists; returns false otherwise.  The array
-// is [outer][n_prev][n][inner] with outer == 1 unless the V2 runs are
-// contiguous (inner == 1).
-bool volumetric_fused(Builder& b, int64_t outer, int64_t n_prev, int64_t n, int64_t inner,
-                      int axis, int persistent, bool shuffled) {
+// The kernel for V2 of axis d and V1 of axis d - 1 in one pass, when
+// a = A_d equals B_{d-1} and the tile fits the array; null otherwise.
+const KernelInfo* fused_kernel_for(int64_t outer, int64_t n_prev, int64_t n, int64_t inner,
+                                   int persistent, int kind) {
   int64_t A, Bf, Ap, Bp;
   split_axis(n, A, Bf);
   split_axis(n_prev, Ap, Bp);
-  if (A != Bp) return false;
+  if (A != Bp) return nullptr;
   const int contig = inner == 1;
-  const KernelInfo* k = find_fused_axes_kernel((int)A, contig, persistent, shuffled ? 1 : 0);
+  const KernelInfo* k = find_fused_axes_kernel((int)A, contig, persistent, kind);
+  if (!k) return nullptr;
+  if (contig ? Bf % k->tile != 0 : (outer != 1 || inner % k->tile != 0)) return nullptr;
+  return k;
+}
+
+// V2 of axis d and V1 of axis d - 1 in one pass where fused_kernel_for
+// finds a kernel; returns false otherwise.  The array is
+// [outer][n_prev][n][inner] with outer == 1 unless the V2 runs are
+// contiguous (inner == 1).  kind 1: natural layout, 2: shuffled forward,
+// 3: the inverse from the shuffled order (W2 of axis d - 1, then W1 of
+// axis d, on the same tiles in place; twiddles of axis d, and with
+// pre_twiddle those W1 of axis d - 1 left out).
+bool volumetric_fused(Builder& b, int64_t outer, int64_t n_prev, int64_t n, int64_t inner,
+                      int axis, int persistent, int kind, bool pre_twiddle = false) {
+  int64_t A, Bf, Ap, Bp;
+  split_axis(n, A, Bf);
+  split_axis(n_prev, Ap, Bp);
+  const int contig = inner == 1;
+  const KernelInfo* k = fused_kernel_for(outer, n_prev, n, inner, persistent, kind);
   if (!k) return false;
+  const bool shuffled = kind != 1;
   const int64_t KC = k->tile;
   const int64_t sd = inner, sprev = n * inner, so = n_prev * sprev;
+  const int64_t twp_len = kind == 3 ? n : n_prev;
   char lab[64];
-  std::snprintf(lab, sizeof lab, "vol%d.V2+vol%d.V1 DFT%lldx%lld%s", axis, axis - 1,
-                (long long)A, (long long)Bp, shuffled ? " shuffled" : "");
+  if (kind == 3)
+    std::snprintf(lab, sizeof lab, "vol%d.W2+vol%d.W1 DFT%lldx%lld", axis - 1, axis,
+                  (long long)Bp, (long long)A);
+  else
+    std::snprintf(lab, sizeof lab, "vol%d.V2+vol%d.V1 DFT%lldx%lld%s", axis, axis - 1,
+                  (long long)A, (long long)Bp, shuffled ? " shuffled" : "");
   // the run field: natural output k + b l' (runs KC apart at stride 1),
   // shuffled output a k' + l' where the run was read (same stride as in)
   if (contig) {
-    if (Bf % KC) return false;
     Field f[3] = {{Bf / KC, KC * A * sd, shuffled ? KC * A * sd : KC * sd},
                   {Ap, sprev, sprev}, {outer, so, so}};
-    b.add_fused(k, f, Ap * sprev, sd, Bf, n_prev, (int)A, lab);
+    b.add_fused(k, f, Ap * sprev, sd, Bf, twp_len, (int)A, lab);
   } else {
-    if (outer != 1 || inner % KC) return false;
     Field f[3] = {{inner / KC, KC, KC}, {Ap, sprev, sprev},
                   {Bf, A * sd, shuffled ? A * sd : sd}};
-    b.add_fused(k, f, Ap * sprev, sd, Bf, n_prev, (int)A, lab);
+    b.add_fused(k, f, Ap * sprev, sd, Bf, twp_len, (int)A, lab);
+  }
+  if (kind == 3 && pre_twiddle) {  // axis d - 1's first-half twiddle, from tw
+    Pass& p = b.passes.back();
+    p.args.res_shift = 1;
+    p.args.res_mask = n_prev - 1;
+    p.tw_len = n_prev;
   }
   return true;
 }
@@ -437,24 +464,36 @@ bool volumetric_fused(Builder& b, int64_t outer, int64_t n_prev, int64_t n, int6
 // One axis of the inverse of a shuffled plan: input entry y[k' + Bf l'] at
 // position l' + A k', natural output x[a + A b] at position a + A b:
 //   x[a + A b] = sum_k' w_Bf^{k' b} w_n^{k' a} sum_l' w_A^{l' a} y[k' + Bf l']
-// (forward roots; the inverse conjugates around the whole list).
-void volumetric_axis_from_shuffled(Builder& b, int64_t outer, int64_t n, int64_t inner,
-                                   int axis) {
+// (forward roots; the inverse conjugates around the whole list).  W1 is the
+// inner sum times the twiddle, W2 the outer sum.
+// twiddle = false: the twiddle is left to the pass that runs W2 of the axis.
+void volumetric_w1(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis,
+                   bool twiddle) {
   int64_t A, Bf;
   split_axis(n, A, Bf);
   const int64_t slab = n * inner;
   char lab[64];
   {  // W1: pencils (o, k', c), elements l' at A k' + l', outputs a there too
-    std::snprintf(lab, sizeof lab, "vol%d.W1 DFT%lld x%lld", axis, (long long)A,
-                  (long long)(outer * Bf * inner));
+    std::snprintf(lab, sizeof lab, "vol%d.W1 DFT%lld x%lld%s", axis, (long long)A,
+                  (long long)(outer * Bf * inner), twiddle ? "" : " untwiddled");
+    const int tw = twiddle ? 1 : 0;
+    const int64_t twl = twiddle ? n : 0;
     if (inner == 1) {
       Field f[2] = {{Bf, A, A}, {outer, slab, slab}};
-      b.add((int)A, MODE_ROW, MODE_ROW, 1, f, 2, 1, 1, n, 0, Bf - 1, lab);
+      b.add((int)A, MODE_ROW, MODE_ROW, tw, f, 2, 1, 1, twl, 0, twiddle ? Bf - 1 : 0, lab);
     } else {
       Field f[3] = {{inner, 1, 1}, {Bf, A * inner, A * inner}, {outer, slab, slab}};
-      b.add((int)A, MODE_COL, MODE_COL, 1, f, 3, inner, inner, n, ilog2(inner), Bf - 1, lab);
+      b.add((int)A, MODE_COL, MODE_COL, tw, f, 3, inner, inner, twl,
+            twiddle ? ilog2(inner) : 0, twiddle ? Bf - 1 : 0, lab);
     }
   }
+}
+
+void volumetric_w2(Builder& b, int64_t outer, int64_t n, int64_t inner, int axis) {
+  int64_t A, Bf;
+  split_axis(n, A, Bf);
+  const int64_t slab = n * inner;
+  char lab[64];
   {  // W2: pencils (o, a, c), elements k' at a + A k', outputs b at a + A b
     Field f[2] = {{A * inner, 1, 1}, {outer, slab, slab}};
     std::snprintf(lab, sizeof lab, "vol%d.W2 DFT%lld x%lld", axis, (long long)Bf,
@@ -845,15 +884,32 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
     // FP32 plans fuse V2 of an axis with V1 of the next where the split
     // factors match (four passes instead of six for 256^3, 1024^3)
     // (the shuffled forward list too: its fused passes leave the finished
-    // axis in digit order; the inverse from the shuffled order is unfused)
-    const bool fuse =
-        opt.fused_axes && !from_layout && opt.precision == DFT3D_PREC_FP32 && !any_other;
-    int pending = -1;  // axis whose V2 is still to come
+    // axis in digit order; the inverse from the shuffled order runs the
+    // transposed passes in reverse order, W1 of axis 0 first)
+    const bool fuse = opt.fused_axes && opt.precision == DFT3D_PREC_FP32 && !any_other;
+    // the persistent fused form only when streaming is forced on: at 1024^3
+    // it measured no faster (15.0 vs 14.7 ms for the schedule), the one-tile
+    // form's workgroup turnover already overlaps the phases
+    const int fpers = opt.persistent && opt.nontemporal == 1;
+    int pending = -1;  // axis whose V2 (W2 from the shuffled order) is still to come
     auto dims = [&n](int axis, int64_t& outer, int64_t& inner) {
       outer = 1;
       inner = 1;
       for (int d = 0; d < axis; ++d) outer *= n[d];
       for (int d = axis + 1; d < 3; ++d) inner *= n[d];
+    };
+    auto in_layout = [&](int axis, int64_t outer, int64_t inner) {
+      // too short to split (its shuffled order is natural), or not a power
+      // of two: one pass in layout
+      char lab[64];
+      std::snprintf(lab, sizeof lab, "vol%d DFT%lld", axis, (long long)n[axis]);
+      if (inner == 1) {
+        Field f[1] = {{outer, n[axis], n[axis]}};
+        axis_pass(b, n[axis], MODE_ROW, MODE_ROW, f, 1, 1, 1, lab);
+      } else {
+        Field f[2] = {{inner, 1, 1}, {outer, n[axis] * inner, n[axis] * inner}};
+        axis_pass(b, n[axis], MODE_COL, MODE_COL, f, 2, inner, inner, lab);
+      }
     };
     auto flush = [&]() {
       if (pending < 0) return;
@@ -862,51 +918,88 @@ int build_passes(const int64_t n[3], int schedule, int layout, const Options& gi
       volumetric_v2(b, o, n[pending], in, pending, shuffled);
       pending = -1;
     };
-    for (int axis = 2; axis >= 0; --axis) {
-      int64_t outer = 1, inner = 1;
-      dims(axis, outer, inner);
-      // a four-step split needs power-of-two bit fields: the axis and the
-      // axes after it (the residue of the twiddle stage is a bit field of
-      // the pencil index); other axes run as one pass in layout
-      const bool split = n[axis] >= 4 && is_pow2(n[axis]) && is_pow2(inner);
-      if (split && shuffled && from_layout) {
-        volumetric_axis_from_shuffled(b, outer, n[axis], inner, axis);
-        continue;
-      }
-      if (split) {
-        if (pending == axis + 1 && fuse && n[pending] >= 4) {
+    if (shuffled && from_layout) {
+      // inverse from the shuffled order: per split axis W1 then W2; W2 of
+      // an axis and W1 of the next inner one share a pass where the split
+      // factors match
+      auto flush_w2 = [&]() {
+        if (pending < 0) return;
+        int64_t o, in;
+        dims(pending, o, in);
+        volumetric_w2(b, o, n[pending], in, pending);
+        pending = -1;
+      };
+      auto split_at = [&](int axis) {
+        int64_t o, in;
+        dims(axis, o, in);
+        return n[axis] >= 4 && is_pow2(n[axis]) && is_pow2(in);
+      };
+      // W2 of axis e (split) and W1 of axis e + 1 share a pass
+      auto fuses = [&](int e) {
+        if (!fuse || e + 1 > 2 || !split_at(e) || !split_at(e + 1)) return false;
+        int64_t po, pin, o, in;
+        dims(e, po, pin);
+        dims(e + 1, o, in);
+        return fused_kernel_for(po, n[e], n[e + 1], in, fpers, 3) != nullptr;
+      };
+      bool owed = false;  // the pending axis's W1 twiddle is still to apply
+      for (int axis = 0; axis < 3; ++axis) {
+        int64_t outer = 1, inner = 1;
+        dims(axis, outer, inner);
+        if (!split_at(axis)) {
+          flush_w2();
+          in_layout(axis, outer, inner);
+          continue;
+        }
+        if (pending >= 0 && pending == axis - 1 && fuses(pending)) {
           int64_t po, pin;
           dims(pending, po, pin);
-          // the pending axis's outer dimensions are [outer][n[axis]]
-          // the persistent form only when streaming is forced on: at 1024^3
-          // it measured no faster (15.0 vs 14.7 ms for the schedule), the
-          // one-tile form's workgroup turnover already overlaps the phases
-          const int pers = opt.persistent && opt.nontemporal == 1;
-          if (volumetric_fused(b, outer, n[axis], n[pending], pin, pending, pers, shuffled)) {
-            pending = axis;
-            continue;
+          // the array as [po][n[pending]][n[axis]][inner]
+          if (!volumetric_fused(b, po, n[pending], n[axis], inner, axis, fpers, 3, owed)) {
+            b.status = DFT3D_ERR_UNSUPPORTED_SCHEDULE;  // fuses() said it would
+            break;
           }
+          pending = axis;
+          owed = false;
+          continue;
+        }
+        flush_w2();
+        // a W1 whose W2 will share a pass with the next axis leaves its
+        // twiddle to that pass (a row twiddle uniform over the workgroup)
+        owed = fuses(axis);
+        volumetric_w1(b, outer, n[axis], inner, axis, !owed);
+        pending = axis;
+      }
+      flush_w2();
+    } else {
+      for (int axis = 2; axis >= 0; --axis) {
+        int64_t outer = 1, inner = 1;
+        dims(axis, outer, inner);
+        // a four-step split needs power-of-two bit fields: the axis and the
+        // axes after it (the residue of the twiddle stage is a bit field of
+        // the pencil index); other axes run as one pass in layout
+        const bool split = n[axis] >= 4 && is_pow2(n[axis]) && is_pow2(inner);
+        if (split) {
+          if (pending == axis + 1 && fuse && n[pending] >= 4) {
+            int64_t po, pin;
+            dims(pending, po, pin);
+            // the pending axis's outer dimensions are [outer][n[axis]]
+            if (volumetric_fused(b, outer, n[axis], n[pending], pin, pending, fpers,
+                                 shuffled ? 2 : 1)) {
+              pending = axis;
+              continue;
+            }
+          }
+          flush();
+          volumetric_v1(b, outer, n[axis], inner, axis);
+          pending = axis;
+          continue;
         }
         flush();
-        volumetric_v1(b, outer, n[axis], inner, axis);
-        pending = axis;
-        continue;
+        in_layout(axis, outer, inner);
       }
       flush();
-      {  // too short to split (its shuffled order is natural), or not a
-         // power of two: one pass in layout
-        char lab[64];
-        std::snprintf(lab, sizeof lab, "vol%d DFT%lld", axis, (long long)n[axis]);
-        if (inner == 1) {
-          Field f[1] = {{outer, n[axis], n[axis]}};
-          axis_pass(b, n[axis], MODE_ROW, MODE_ROW, f, 1, 1, 1, lab);
-        } else {
-          Field f[2] = {{inner, 1, 1}, {outer, n[axis] * inner, n[axis] * inner}};
-          axis_pass(b, n[axis], MODE_COL, MODE_COL, f, 2, inner, inner, lab);
-        }
-      }
     }
-    flush();
     assign_chain(passes, 0, need_ws);
   }
   if (b.status != DFT3D_OK) {
@@ -976,7 +1069,7 @@ void describe_list(std::ostringstream& os, const std::vector<Pass>& passes) {
        << ",\"os\":[" << p.args.os0 << "," << p.args.os1 << "," << p.args.os2 << "]"
        << ",\"ijs\":" << p.args.ijs << ",\"oks\":" << p.args.oks
        << ",\"res_shift\":" << p.args.res_shift << ",\"res_mask\":" << p.args.res_mask
-       << ",\"twp_len\":" << p.twp_len << "}}";
+       << ",\"twp_len\":" << p.twp_len << ",\"tw_len\":" << p.tw_len << "}}";
   }
   os << "]";
 }

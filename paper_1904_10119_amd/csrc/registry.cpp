@@ -233,9 +233,8 @@ const KernelInfo* find_bluestein_kernel(int m, int tile) {
   return first;
 }
 
-const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent, int shuffled) {
+const KernelInfo* find_fused_axes_kernel(int a, int contig, int persistent, int kind) {
   const int mode = contig ? MODE_ROW : MODE_COL;
-  const int kind = shuffled ? 2 : 1;
   const KernelInfo* other = nullptr;
   for (const KernelInfo& k : kernel_registry())
     if (k.fused_axes == kind && k.n == a && k.lmode == mode) {

@@ -133,6 +133,29 @@ def test_1024_cubed_shuffled_every_element():
     assert rel <= oracle.tol(n) and worst <= 10 * oracle.tol(n)
 
 
+def test_1024_cubed_shuffled_inverse_every_element():
+    """The inverse from the shuffled order (four passes, two of them the
+    fused transposed passes): the input permuted into the shuffled order
+    must come back as the natural inverse DFT of the input, every element."""
+    shape = (1024, 1024, 1024)
+    say("case fullsize shuffled inverse", shape)
+    x, _, inv = refs(shape)
+    d = dft3d.describe(shape, "volumetric", "shuffled")
+    assert [p["fused_axes"] for p in d["inverse_passes"]] == [0, 3, 3, 0]
+    xs = np.ascontiguousarray(oracle.to_shuffled(x, dft3d.shuffle_factors(shape)))
+    xt = torch.from_numpy(xs).cuda()
+    del xs
+    y = torch.empty_like(xt)
+    p = dft3d.Plan(shape, "volumetric", layout="shuffled")
+    p.execute(xt, y, inverse=True)
+    torch.cuda.synchronize()
+    p.close()
+    got = y.cpu().numpy()
+    del xt, y
+    torch.cuda.empty_cache()
+    check(shape, got, inv, "volumetric shuffled inverse")
+
+
 CASES_2048 = [("auto", {}, False), ("auto", {}, True), ("pencil", {}, False),
               ("auto", {"precision": "bf16x6"}, False),
               ("auto", {"precision": "bf16x6", "mfma_leaf": 32}, False)]

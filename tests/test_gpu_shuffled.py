@@ -67,6 +67,37 @@ def test_shuffled_forward_inverse_roundtrip(shape, schedule):
     assert oracle.rel_l2(back, x) <= 2 * oracle.tol(N)
 
 
+FUSED_SHAPES = [(2, 256, 256), (256, 256, 32), (2, 1024, 512), (1024, 512, 16),
+                (256, 256, 256), (64, 256, 256)]
+
+
+@pytest.mark.parametrize("form", ["one-tile", "persistent"])
+@pytest.mark.parametrize("shape", FUSED_SHAPES)
+def test_shuffled_inverse_fused_passes(shape, form):
+    """Shapes whose split factors (16 or 32) let the inverse from the
+    shuffled order fuse W2 of an axis with W1 of the next (runs contiguous
+    and strided), in the one-tile and the persistent kernel forms: every
+    element of the natural inverse DFT of arbitrary shuffled-order input,
+    and the round trip through the fused forward."""
+    opts = {"persistent": 1, "nontemporal": 1} if form == "persistent" else {}
+    say("case shuffled inverse fused", shape, form)
+    d = dft3d.describe(shape, "volumetric", "shuffled", **opts)
+    assert any(p["fused_axes"] == 3 for p in d["inverse_passes"])
+    assert all(p["persistent"] == (form == "persistent")
+               for p in d["inverse_passes"] if p["fused_axes"] == 3)
+    f = dft3d.shuffle_factors(shape)
+    z = inputs.uniform_c64(shape, 37)
+    N = z.size
+    yi = run(oracle.to_shuffled(z, f).astype(np.complex64), inverse=True, **opts)
+    want = ref(z, +1)
+    rel, worst = oracle.compare(yi, want)
+    say(f"  inverse rel_l2 {rel:.3e} max element {worst:.3e} x rms")
+    assert rel <= oracle.tol(N) and worst <= 10 * oracle.tol(N)
+    x = inputs.uniform_c64(shape, 38)
+    back = run(run(x, **opts), inverse=True, **opts) / N
+    assert oracle.rel_l2(back, x) <= 2 * oracle.tol(N)
+
+
 def test_shuffled_is_the_natural_result_permuted():
     shape = (64, 32, 128)
     f = dft3d.shuffle_factors(shape)

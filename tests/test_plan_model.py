@@ -66,10 +66,14 @@ def fused_tiles(p):
     c = np.arange(C)[None, None, None, :, None]
     l = np.arange(A)[None, None, None, None, :]
     ia = ib[:, None, None, None, None] + m * RM + (kk * A + l) * SD + c
-    if p["fused_axes"] == 2:   # shuffled: output l' of run k' where the run was read
+    if p["fused_axes"] in (2, 3):   # shuffled order: in place
         oa = ob[:, None, None, None, None] + m * RM + (kk * A + l) * SD + c
     else:
         oa = ob[:, None, None, None, None] + m * RM + (kk + b * l) * SD + c
+    if p["fused_axes"] == 3:        # the run index k' of the tile's runs kk
+        run = (f0[:, None] * KC + np.arange(K)[None, :]) if contig else \
+            np.broadcast_to(f2[:, None], (f2.size, K))
+        return ia, oa, run
     return ia, oa, f1
 
 
@@ -78,6 +82,28 @@ def fused_model(bufs, p, sign, last):
     v = bufs[p["src"]][ia]
     if sign == 1 and p["src"] == "in":
         v = np.conj(v)
+    if p["fused_axes"] == 3:
+        # inverse from the shuffled order: W2 of axis d-1 (DFT over the rows
+        # m; with res_shift = 1 first the twiddle w^{r' m} of axis d-1's W1,
+        # table length tw_len), then W1 of axis d (DFT over l' of run k',
+        # times w_L^{k' a'})
+        a = p["args"]
+        if a["res_shift"]:
+            Lr = a["tw_len"]
+            m = np.arange(p["n"])
+            r1 = fused_tiles(dict(p, fused_axes=2))[2]       # the residue r'
+            pre = np.exp(-2j * np.pi * ((r1[:, None] * m[None, :]) % Lr) / Lr)
+            v = v * pre[:, :, None, None, None]
+        v = np.fft.fft(v, axis=1)
+        v = np.fft.fft(v, axis=4)
+        L = p["args"]["twp_len"]
+        ap = np.arange(p["n"])
+        tw = np.exp(-2j * np.pi * ((r[:, :, None] * ap[None, None, :]) % L) / L)
+        v = v * tw[:, None, :, None, :]
+        if sign == 1 and last:
+            v = np.conj(v)
+        bufs[p["dst"]][oa] = v
+        return
     v = np.fft.fft(v, axis=4)            # V2 of axis d: DFT_a over l
     v = np.fft.fft(v, axis=1)            # V1 of axis d-1: DFT over the rows m
     L = p["args"]["twp_len"]
@@ -277,6 +303,33 @@ def test_shuffled_pass_maps_in_bounds(shape):
                 addr = addresses(a, p["n"], inp).reshape(-1)
                 assert addr.min() >= 0 and addr.max() < N, (key, p["label"], inp)
                 assert np.unique(addr).size == addr.size, (key, p["label"], inp)
+
+
+@pytest.mark.parametrize("shape,nfused", [
+    ((2, 256, 256), 1), ((256, 256, 32), 1), ((2, 1024, 512), 1), ((1024, 512, 16), 1),
+    ((64, 256, 256), 1), ((16, 256, 16), 0), ((4, 1024, 1024), 1),
+    ((256, 256, 256), 2), ((1024, 1024, 1024), 2)])
+def test_shuffled_inverse_fused(shape, nfused):
+    """The inverse from the shuffled order fuses W2 of an axis with W1 of the
+    next inner axis wherever the forward fuses the pair: as many passes as
+    the forward, each fused pair one pass in place (the forward's transposed
+    tiles); the list still maps shuffled input to the natural inverse DFT."""
+    d = dft3d.describe(shape, "volumetric", "shuffled")
+    fwd = [p["fused_axes"] for p in d["passes"]]
+    inv = [p["fused_axes"] for p in d["inverse_passes"]]
+    assert fwd.count(2) == nfused and inv.count(3) == nfused, (fwd, inv)
+    assert len(d["inverse_passes"]) == len(d["passes"])
+    for p in d["inverse_passes"]:
+        if p["fused_axes"]:
+            assert p["args"]["is"] == p["args"]["os"], p["label"]
+    off = dft3d.describe(shape, "volumetric", "shuffled", fused_axes=0)
+    assert not any(p["fused_axes"] for p in off["inverse_passes"])
+    assert len(off["inverse_passes"]) == len(d["inverse_passes"]) + nfused
+    if shape[0] * shape[1] * shape[2] <= (1 << 22):
+        g = np.random.default_rng(sum(shape) + 7)
+        x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+        s = oracle.to_shuffled(x, dft3d.shuffle_factors(shape))
+        assert oracle.rel_l2(run_model(s, d, +1), oracle.dft3d(x, +1, "fft")) < 1e-13
 
 
 @pytest.mark.parametrize("schedule", ["pencil", "slab"])
