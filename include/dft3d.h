@@ -111,11 +111,15 @@ enum dft3d_option {
                                 plane in one pass when n1, n2 are in
                                 [16, 128] (the plane stays in LDS between
                                 rows and columns); default 1 */
-  DFT3D_OPT_FUSED_AXES = 9,  /* volumetric, FP32, natural layout: 1 = the
-                                second half of one axis and the first half
-                                of the next in one pass where the split
-                                factors match (a_d = b_{d-1} = 16 or 32:
-                                256^3, 1024^3); default 1 */
+  DFT3D_OPT_FUSED_AXES = 9,  /* volumetric, FP32: 1 = the second half of
+                                one axis and the first half of the next in
+                                one pass where the split factors match
+                                (a_d = b_{d-1} = 16 or 32: 256^3, 1024^3),
+                                in the natural layout and in the shuffled
+                                one, whose inverse runs the forward's
+                                passes transposed (second half of an axis
+                                with the first half of the next inner
+                                axis, Section 2.4); default 1 */
   DFT3D_OPT_PENCIL_GROUP = 10, /* pencil, FP32, powers of two: planes of
                                 axis 0 per group of the first two passes
                                 (rounded down to a power of two), so a
