@@ -560,13 +560,35 @@ void pencil_axis(Builder& b, const int64_t cur[3], bool split, int axis) {
 // for split precision (1024^3 bf16x6 14.3 -> 12.2 ms, bf16x9 14.9 -> 11.4,
 // 2048 x 1024 x 512 bf16x6 15.5 -> 13.1: the matrix-core passes' 64-byte
 // row segments cost far less one row apart than one plane apart) and for
-// FP32 arrays with an axis of 2048 (2048 x 1024 x 512: 11.1 -> 10.6 ms),
-// else the rotation (1024^3: 10.5 ms against 10.75 cycled; its pass keeps
-// whole-pencil loads).
+// FP32 arrays that stream through HBM (256 MiB and more) or have an axis of
+// 2048 or more (2048 x 1024 x 512: 11.1 -> 10.6 ms; 4096 x 512 x 256:
+// 7.17 -> 5.52; 1024^3: 10.62 -> 10.44 and 512^3 1.28 -> 1.26 with the
+// one-tile kernels of add_cycled), else the rotation (256^3: 0.142 against
+// 0.145 ms cycled).
 int pencil_order(const int64_t n[3], const Options& opt) {
   if (opt.pencil_order >= 0) return opt.pencil_order;
   if (opt.precision != DFT3D_PREC_FP32) return 2;
-  return (n[0] == 2048 || n[1] == 2048 || n[2] == 2048) ? 2 : 0;
+  const bool long_axis = n[0] >= 2048 || n[1] >= 2048 || n[2] >= 2048;
+  return long_axis || n[0] * n[1] * n[2] * 8 >= kStreamBytes ? 2 : 0;
+}
+
+// One rotate-on-write pass of the cycled order.  FP32 passes of length up
+// to 1024 take the one-tile kernel (two workgroups' tiles in flight per CU
+// instead of one persistent workgroup prefetching): measured in this order
+// 1024^3 10.75 -> 10.44 ms, 512^3 1.29 -> 1.26 ms; the persistent form
+// stays where streaming is forced on (nontemporal = 1) and for longer
+// lengths (the 2048 pass as persistent halves).
+void add_cycled(Builder& b, int len, const Field* f, int64_t oks, const char* lab) {
+  if (b.opt.precision == DFT3D_PREC_FP32 && b.opt.nontemporal == 2 && b.nt_side == 0 &&
+      len <= 1024) {
+    Options one = b.opt;
+    one.persistent = 0;
+    Builder o{one, b.passes, b.total_points};
+    o.add(len, MODE_ROW, MODE_COL, 0, f, 2, 1, oks, 0, 0, 0, lab);
+    b.status = o.status;
+    return;
+  }
+  b.add(len, MODE_ROW, MODE_COL, 0, f, 2, 1, oks, 0, 0, 0, lab);
 }
 
 // The pencil schedule in the other intermediate orders, on an (A, B, C)
@@ -586,21 +608,21 @@ void pencil_swapped(Builder& b, const int64_t n[3]) {
       Field f[2] = {{A, B * C, 1}, {B, C, C * A}};
       std::snprintf(lab, sizeof lab, "pencil2 DFT%lld x%lld cyc", (long long)C,
                     (long long)(A * B));
-      b.add((int)C, MODE_ROW, MODE_COL, 0, f, 2, 1, A, 0, 0, 0, lab);
+      add_cycled(b, (int)C, f, A, lab);
     }
     if (b.status != DFT3D_OK) return;
     {
       Field f[2] = {{B, C * A, 1}, {C, A, A * B}};
       std::snprintf(lab, sizeof lab, "pencil0 DFT%lld x%lld cyc", (long long)A,
                     (long long)(B * C));
-      b.add((int)A, MODE_ROW, MODE_COL, 0, f, 2, 1, B, 0, 0, 0, lab);
+      add_cycled(b, (int)A, f, B, lab);
     }
     if (b.status != DFT3D_OK) return;
     {
       Field f[2] = {{C, A * B, 1}, {A, B, B * C}};
       std::snprintf(lab, sizeof lab, "pencil1 DFT%lld x%lld cyc", (long long)B,
                     (long long)(A * C));
-      b.add((int)B, MODE_ROW, MODE_COL, 0, f, 2, 1, C, 0, 0, 0, lab);
+      add_cycled(b, (int)B, f, C, lab);
     }
     return;
   }

@@ -46,22 +46,29 @@ def test_move_only_output_is_the_modelled_permutation(shape, schedule, mode):
 
 
 def test_move_only_streaming_persistent_kernels():
-    """Shapes of 512 MiB and more run the persistent streaming kernels (the
-    forms the 1024^3 breakdown times): (1024, 1024, 64) on the pencil and
-    slab schedules with the whole-length kernels, and the slab's strided
-    passes as two halves, every element against the model."""
+    """Shapes of 512 MiB and more: (1024, 1024, 64) on the pencil schedule
+    in its default form (the cycled order's one-tile kernels, which the
+    1024^3 breakdown times) and with streaming forced (the persistent
+    streaming kernels), on the slab schedule with the whole-length kernels
+    (persistent, streaming) and with the strided passes as two halves, every
+    element against the model."""
     shape = (1024, 1024, 64)
     x = inputs.uniform_c64(shape, 62)
     xt = torch.from_numpy(x).cuda()
-    for schedule, halves in (("pencil", 0), ("slab", 0), ("slab", 1)):
-        print("case move-only streaming", shape, schedule, "halves", halves, flush=True)
-        d = dft3d.describe(shape, schedule, move_only=1, halves=halves)
+    for schedule, halves, nt in (("pencil", 0, -1), ("pencil", 0, 1), ("slab", 0, -1),
+                                 ("slab", 1, -1)):
+        print("case move-only streaming", shape, schedule, "halves", halves, "nt", nt,
+              flush=True)
+        opts = {"nontemporal": nt} if nt >= 0 else {}
+        d = dft3d.describe(shape, schedule, move_only=1, halves=halves, **opts)
         if halves:
             assert sum(p["halves"] for p in d["passes"]) == 2
+        elif schedule == "pencil" and nt < 0:
+            assert all("cyc" in p["label"].split() and not p["persistent"] for p in d["passes"])
         else:
             assert any(p["persistent"] and p["nontemporal"] == 1 for p in d["passes"])
         y = torch.empty_like(xt)
-        p = dft3d.Plan(shape, schedule, move_only=1, halves=halves)
+        p = dft3d.Plan(shape, schedule, move_only=1, halves=halves, **opts)
         p.execute(xt, y)
         torch.cuda.synchronize()
         assert np.array_equal(bits(y.cpu().numpy()), bits(run_move_model(x, d)))

@@ -1013,13 +1013,28 @@ def test_pencil_orders_compute_the_dft(shape, order):
 
 
 def test_pencil_order_default_and_values():
-    """Automatic order: the cycle for split precision and for arrays with an
-    axis of 2048, else the rotation; lengths that are not powers of two and
-    split axes keep the rotation; values outside -1..2 are rejected."""
+    """Automatic order: the cycle for split precision, for FP32 arrays of
+    256 MiB and more and for arrays with an axis of 2048 or more, else the
+    rotation; lengths that are not powers of two and split axes keep the
+    rotation; values outside -1..2 are rejected.  In the cycle, FP32 passes
+    of length up to 1024 take the one-tile kernels unless streaming is
+    forced on."""
     def tags(shape, **kw):
         return [p["label"].split()[-1] for p in dft3d.describe(shape, "pencil", **kw)["passes"]]
-    assert tags((1024, 1024, 1024)) == ["rot"] * 3
+    assert tags((1024, 1024, 1024)) == ["cyc"] * 3
+    assert tags((256, 256, 256)) == ["rot"] * 3
+    assert tags((512, 512, 256)) == ["cyc"] * 3           # 512 MiB
+    assert tags((256, 256, 512)) == ["cyc"] * 3           # exactly 256 MiB
+    assert tags((256, 128, 512)) == ["rot"] * 3           # 128 MiB
+    assert tags((4096, 8, 8)) == ["cyc"] * 3
     assert tags((1024, 1024, 1024), precision="bf16x6") == ["cyc"] * 3
+    d = dft3d.describe((1024, 1024, 1024), "pencil")
+    assert [p["persistent"] for p in d["passes"]] == [0, 0, 0]
+    d = dft3d.describe((1024, 1024, 1024), "pencil", nontemporal=1)
+    assert [p["persistent"] for p in d["passes"]] == [1, 1, 1]
+    d = dft3d.describe((2048, 1024, 512), "pencil")
+    assert [(p["n"], p["persistent"]) for p in d["passes"]] == [(512, 0), (2048, 1), (1024, 0)]
+    assert tags((1024, 1024, 1024), pencil_order=0) == ["rot"] * 3
     assert tags((2048, 1024, 512)) == ["cyc"] * 3
     assert tags((2048, 1024, 512), pencil_order=0) == ["rot"] * 3
     assert tags((1024, 1024, 1024), pencil_order=2) == ["cyc"] * 3
