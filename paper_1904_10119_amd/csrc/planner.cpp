@@ -15,8 +15,9 @@
 //     y[k' + Bf l'].
 //   AUTO: below 256 MiB (arrays the Infinity Cache can hold between
 //     passes) SLAB, whose planes of up to 128 x 128 points take one fused
-//     pass; above it the pencil rotation, with axes longer than a threshold
-//     split into V1 + V2 as in the volumetric schedule.
+//     pass; above it the pencil schedule (the cycled intermediate orders
+//     where every axis is a power of two and unsplit), with axes longer than
+//     a threshold split into V1 + V2 as in the volumetric schedule.
 //   SHUFFLED layout (volumetric only; Section 2.4, Section 3.2): the forward
 //     transform leaves out the final digit exchange of every split axis, so
 //     natural entry y[k' + Bf l'] stays at position l' + A k' (V2 writes in
